@@ -1,0 +1,22 @@
+"""Plain FP64 CPU reference for the replica-tensor-train Monte Carlo path.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product package may import, call,
+link or execute anything here; only the tests, the smoke check and the CPU
+baseline leg of the benchmark do.  The code is deliberately slow and literal:
+amplitudes are direct matrix products, flip ratios recompute whole amplitudes,
+and the Metropolis chain follows the textbook rule.  It shares no code with
+the HIP kernels; the only common module is the seeded input generator
+(``paper_2604_22718_amd.workloads``), which holds no method arithmetic.
+
+Modules
+  rtt     amplitudes, flip ratios, local energies, linear combinations
+  tfim    transverse-field Ising lattice, bonds, sparse H, exact diagonalisation
+  philox  Philox4x64-10 counter-based generator (Salmon et al., SC'11)
+  mcmc    single-spin-flip Metropolis on |psi|^2
+  stats   exactly rounded means, integrated autocorrelation time, V-score
+  tt      TT-SVD, direct-sum trains, MPS transfer-matrix expectation values
+  quant   BF16 / FP8-e4m3 core quantisation via torch CPU casts
+
+Every function states the passage of the paper it follows.  None is
+"parity unpinned": each is pinned by tests under ``tests/test_oracle_*.py``.
+"""

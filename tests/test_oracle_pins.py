@@ -1,0 +1,367 @@
+"""Pins of the FP64 CPU oracle against facts that do not come from the oracle:
+the paper's worked examples, brute-force constructions, closed forms,
+invariances, library routines and exact diagonalisation."""
+import itertools
+import math
+
+import numpy as np
+import pytest
+
+from conftest import read_golden
+from oracle import rtt, tfim, tt, mcmc, stats, philox, quant
+from paper_2604_22718_amd import workloads as wl
+
+
+def rand_cores(bond, seed, std=None):
+    return wl.gaussian_cores(bond, seed, std)
+
+
+# ---------------------------------------------------------------- worked example
+def test_worked_path_replica_sets():
+    g = read_golden("path_hv_2x3.txt")
+    pi = np.array(g["path_hv"]) - 1
+    R = rtt.replica_sets(pi, 6)
+    # X3 -> X3 X8 ; X1 X2 -> X1 X2 X9 X12 (Sec. 2.2.3)
+    assert [p + 1 for p in R[2]] == g["x_positions_spin3"]
+    assert sorted(p + 1 for p in R[0] + R[1]) == g["x_positions_spin1_spin2"]
+    assert [p + 1 for p in R[0]] == g["z_choices_spin1"]
+    assert [p + 1 for p in R[5]] == g["z_choices_spin6"]
+    assert np.array_equal(wl.path_hv_2x3(), pi)
+
+
+def test_flip_of_spin3_switches_positions_3_and_8():
+    """The oracle's flip ratio for spin 3 equals the product in which exactly
+    the tensors listed by the paper's X3 -> X3 X8 mapping switch slice."""
+    g = read_golden("path_hv_2x3.txt")
+    pi = np.array(g["path_hv"]) - 1
+    cores = rand_cores(wl.open_bonds(12, 3), 11)
+    S = rtt.all_configs(6)
+    flips = set(p - 1 for p in g["x_positions_spin3"])
+    for s in S[::5]:
+        idx = [int(s[pi[k]]) ^ (1 if k in flips else 0) for k in range(12)]
+        M = np.ones((1, 1))
+        for k in range(12):
+            M = M @ cores[k][idx[k]]
+        direct = M[0, 0] / rtt.amplitude(cores, pi, s)
+        r = rtt.flip_ratios(cores, pi, s[None])[0, 2]
+        assert r == pytest.approx(direct, rel=1e-12, abs=0)
+
+
+def test_vertical_ordering_product():
+    g = read_golden("path_hv_2x3.txt")
+    pv = np.array(g["path_v"]) - 1
+    cores = rand_cores(wl.open_bonds(6, 2), 12)
+    s = np.array([1, 0, 1, 1, 0, 0])
+    # psi^V = Tr A1^{s4} A2^{s3} A3^{s2} A4^{s5} A5^{s6} A6^{s1}
+    explicit = (cores[0][s[3]] @ cores[1][s[2]] @ cores[2][s[1]] @ cores[3][s[4]]
+                @ cores[4][s[5]] @ cores[5][s[0]])[0, 0]
+    assert rtt.amplitude(cores, pv, s) == pytest.approx(explicit, rel=1e-14)
+
+
+def test_psi_equals_constraint_times_tt():
+    """psi = C phi (Sec. 2.2.3): phi over the 2^12 replica space from the TT,
+    C the 0/1 copy-tensor constraint, compared for all 2^6 configurations."""
+    pi = wl.path_hv_2x3()
+    Om, N = 12, 6
+    cores = rand_cores(wl.open_bonds(Om, 3), 13)
+    # phi_i for all i in {0,1}^12 by contracting the train on the full index set
+    phi = np.ones((1, 1))                      # (configs so far, bond)
+    for k in range(Om):
+        nxt = np.einsum("ca,iab->cib", phi, cores[k])   # append index i_k
+        phi = nxt.reshape(-1, cores[k].shape[2])
+    phi = phi[:, 0]                              # index = sum i_k 2^(Om-1-k)
+    I = np.array(list(itertools.product([0, 1], repeat=Om)))
+    S = rtt.all_configs(N)
+    C = np.zeros((2 ** N, 2 ** Om))
+    for a, s in enumerate(S):
+        ok = np.all(I == s[pi][None, :], axis=1)
+        C[a, ok] = 1.0
+    psi = C @ phi
+    assert np.allclose(rtt.amplitudes(cores, pi, S), psi, rtol=1e-12, atol=1e-15)
+    # C^T C is the projector prod (1 + V)/2 onto replica-consistent strings
+    P = C.T @ C
+    assert np.allclose(P @ P, P)
+
+
+def test_r1_reduces_to_mps_state():
+    """pi = identity: the oracle's amplitudes equal the MPS state vector built
+    by a chain of tensordots (Sec. 2.2.1, sigma^H = identity)."""
+    N = 7
+    cores = rand_cores(wl.open_bonds(N, 4), 14)
+    state = cores[0][:, 0, :]                      # (2, b)
+    for k in range(1, N):
+        state = np.tensordot(state, cores[k], axes=([-1], [1]))   # (..., 2, b)
+    state = state[..., 0]                           # axes s_0..s_{N-1}
+    S = rtt.all_configs(N)
+    ref = np.array([state[tuple(s)] for s in S])
+    assert np.allclose(rtt.amplitudes(cores, np.arange(N), S), ref, rtol=1e-12, atol=1e-15)
+
+
+def test_chi1_product_state_closed_form():
+    pi = wl.path_site_plus_perms(5, 2, 3)
+    cores = rand_cores(wl.open_bonds(10, 1), 15)
+    S = rtt.all_configs(5)
+    ref = np.ones(len(S))
+    for k in range(10):
+        ref *= cores[k][S[:, pi[k]], 0, 0]
+    assert np.allclose(rtt.amplitudes(cores, pi, S), ref, rtol=1e-13)
+
+
+def test_gauge_relabel_merge_invariances():
+    N, R, chi = 5, 2, 3
+    pi = wl.path_site_plus_perms(N, R, 4)
+    L = N * R
+    cores = rand_cores(wl.open_bonds(L, chi), 16)
+    S = rtt.all_configs(N)
+    psi = rtt.amplitudes(cores, pi, S)
+    # gauge on bond 4: A_3 -> A_3 G, A_4 -> G^-1 A_4
+    G = np.random.default_rng(1).standard_normal((chi, chi)) + 3 * np.eye(chi)
+    gc = [c.copy() for c in cores]
+    gc[3] = np.einsum("sab,bc->sac", gc[3], G)
+    gc[4] = np.einsum("ab,sbc->sac", np.linalg.inv(G), gc[4])
+    assert np.allclose(rtt.amplitudes(gc, pi, S), psi, rtol=1e-10)
+    # relabel spins by a permutation P: pi -> P(pi), s -> s o P^-1
+    P = np.array([3, 0, 4, 1, 2])
+    S2 = np.empty_like(S)
+    S2[:, P] = S
+    assert np.allclose(rtt.amplitudes(cores, P[pi], S2), psi, rtol=1e-13)
+    # merging two adjacent positions of the same spin into one core
+    pi_m = np.array([0, 0, 1, 2, 1, 2, 3, 4, 3, 4])
+    cm = rand_cores(wl.open_bonds(10, chi), 17)
+    merged = [np.stack([cm[0][s] @ cm[1][s] for s in range(2)])] + cm[2:]
+    assert np.allclose(rtt.amplitudes(cm, pi_m, S), rtt.amplitudes(merged, pi_m[1:], S),
+                       rtol=1e-12)
+
+
+def test_flip_ratio_properties():
+    N = 6
+    pi = np.array([0, 1, 2, 3, 0, 2, 1, 3])          # spins 4, 5 read by no position
+    cores = rand_cores(wl.open_bonds(8, 3), 18)
+    S = rtt.all_configs(N)
+    r = rtt.flip_ratios(cores, pi, S)
+    assert np.all(r[:, 4] == 1.0) and np.all(r[:, 5] == 1.0)
+    psi = rtt.amplitudes(cores, pi, S)
+    for j in range(N):
+        # table lookup of the flipped configuration
+        assert np.allclose(r[:, j], psi[np.arange(2 ** N) ^ (1 << j)] / psi, rtol=1e-12)
+        # flipping twice is the identity: r_j(s) r_j(s^j) = 1
+        rj_back = rtt.flip_ratios(cores, pi, rtt.flip(S, j))[:, j]
+        assert np.allclose(r[:, j] * rj_back, 1.0, rtol=1e-12)
+
+
+# ---------------------------------------------------------------- lattice / H
+def test_bonds_structure():
+    b = tfim.bonds(4, 4, True)
+    assert len(b) == 32
+    deg = np.bincount(b.ravel(), minlength=16)
+    assert np.all(deg == 4)
+    b3 = {tuple(sorted(x)) for x in tfim.bonds(3, 3, True).tolist()}
+    # site (x,y) -> y*3+x ; neighbours of the centre site 4 are 1, 3, 5, 7
+    assert {(1, 4), (3, 4), (4, 5), (4, 7)} <= b3 and len(b3) == 18
+    assert len(tfim.bonds(4, 4, False)) == 24
+    assert len(tfim.bonds(2, 2, True)) == 4       # side 2: no duplicate wrap bonds
+
+
+def test_1d_tfim_ground_energy_closed_form():
+    """Periodic chain (Ly = 1), even N: E0 = -sum_k sqrt(J^2 + h^2 - 2 J h cos k),
+    k = (2n+1) pi / N (Pfeuty 1970; the antiferromagnet maps to the ferromagnet
+    by flipping every other spin)."""
+    for N, h in [(8, 0.7), (10, 1.3)]:
+        e0, _ = tfim.ground_state(N, 1, 1.0, h, True)
+        k = (2 * np.arange(N) + 1) * np.pi / N
+        ref = -np.sum(np.sqrt(1 + h * h - 2 * h * np.cos(k)))
+        assert e0 == pytest.approx(ref, rel=1e-10)
+
+
+def test_2d_limits():
+    e0, _ = tfim.ground_state(4, 2, 1.0, 0.0, True)   # classical Neel: -#bonds
+    assert e0 == pytest.approx(-len(tfim.bonds(4, 2, True)), rel=1e-10)
+    e0, _ = tfim.ground_state(3, 3, 0.0, 2.0, True)   # J = 0: -h N
+    assert e0 == pytest.approx(-18.0, rel=1e-10)
+
+
+# ---------------------------------------------------------------- local energy
+def test_enumeration_identity_against_sparse_h():
+    """sum |psi|^2 E_loc / sum |psi|^2 = psi^T H psi / psi^T psi, H from Pauli
+    Kronecker products; pins local_energy (diagonal, sign of h, flips)."""
+    for (Lx, Ly, R, chi, seed) in [(3, 3, 2, 3, 21), (4, 3, 2, 2, 22), (3, 4, 3, 2, 23)]:
+        N = Lx * Ly
+        pi = wl.path_site_plus_perms(N, R, seed)
+        cores = rand_cores(wl.open_bonds(N * R, chi), seed)
+        J, h = 1.0, 3.04
+        e_enum = rtt.exact_energy(cores, pi, N, tfim.bonds(Lx, Ly), J, h)
+        H = tfim.sparse_hamiltonian(Lx, Ly, J, h)
+        psi = rtt.amplitudes(cores, pi, rtt.all_configs(N))
+        e_h = psi @ (H @ psi) / (psi @ psi)
+        assert e_enum == pytest.approx(e_h, rel=1e-11)
+        e0, _ = tfim.ground_state(Lx, Ly, J, h)
+        assert e_h >= e0 - 1e-9                         # variational bound
+
+
+@pytest.mark.parametrize("Lx,Ly", [(3, 3), (4, 4)])
+def test_zero_variance_on_exact_ground_state(Lx, Ly):
+    """E_loc(s) = E0 for every s when psi is the exact ground state, written as
+    an R = 1 train by TT-SVD and as an R = 2 train whose second block reads
+    every spin but does not depend on it."""
+    N = Lx * Ly
+    J, h = 1.0, 3.04
+    e0, v = tfim.ground_state(Lx, Ly, J, h)
+    cores = tt.tt_svd(v, N)
+    S = wl.random_spins(40, N, 31)
+    el = rtt.local_energy(cores, np.arange(N), S, tfim.bonds(Lx, Ly), J, h)
+    assert np.allclose(el, e0, rtol=1e-8)
+    # R = 2: block 2 cores have A[0] == A[1] (random, bond 2), gauge-scrambled
+    g = np.random.default_rng(5)
+    blk2 = []
+    for k in range(N):
+        a = 1 if k == 0 else 2
+        b = 1 if k == N - 1 else 2
+        M = g.standard_normal((a, b)) + (np.eye(a, b) * 2)
+        blk2.append(np.stack([M, M]))
+    last = cores[-1]
+    cores2 = cores[:-1] + [last] + blk2
+    pi2 = np.concatenate([np.arange(N), g.permutation(N)])
+    el2 = rtt.local_energy(cores2, pi2, S[:10], tfim.bonds(Lx, Ly), J, h)
+    assert np.allclose(el2, e0, rtol=1e-8)
+
+
+def test_product_state_energy_closed_form():
+    """chi = 1, R = 2: psi factorises over spins with a_j[s] = prod of the two
+    replica scalars; <H> = J sum m_i m_j - h sum x_i."""
+    Lx, Ly = 3, 3
+    N = 9
+    pi = wl.path_site_plus_perms(N, 2, 41)
+    cores = rand_cores(wl.open_bonds(18, 1), 42)
+    a = np.ones((N, 2))
+    for k in range(18):
+        a[pi[k]] *= cores[k][:, 0, 0]
+    n2 = a[:, 0] ** 2 + a[:, 1] ** 2
+    m = (a[:, 0] ** 2 - a[:, 1] ** 2) / n2
+    x = 2 * a[:, 0] * a[:, 1] / n2
+    b = tfim.bonds(Lx, Ly)
+    ref = 1.0 * np.sum(m[b[:, 0]] * m[b[:, 1]]) - 3.04 * np.sum(x)
+    assert rtt.exact_energy(cores, pi, N, b, 1.0, 3.04) == pytest.approx(ref, rel=1e-12)
+
+
+def test_mps_transfer_energy_matches_enumeration():
+    N = 9
+    cores = rand_cores(wl.open_bonds(N, 3), 51)
+    b = tfim.bonds(3, 3)
+    assert tt.mps_energy(cores, b, 1.0, 3.04) == pytest.approx(
+        rtt.exact_energy(cores, np.arange(N), N, b, 1.0, 3.04), rel=1e-11)
+
+
+# ---------------------------------------------------------------- linear combination
+def test_lincomb_pins():
+    N, R, chi = 5, 2, 3
+    pi = wl.path_site_plus_perms(N, R, 61)
+    terms = [rand_cores(wl.open_bonds(N * R, chi), 62 + t) for t in range(3)]
+    S = rtt.all_configs(N)
+    c = np.array([0.7, -1.3, 0.4])
+    e1 = rtt.lincomb_amplitudes(terms, [1.0, 0.0, 0.0], pi, S)
+    assert np.allclose(e1, rtt.amplitudes(terms[0], pi, S), rtol=1e-14)
+    same = rtt.lincomb_amplitudes([terms[0]] * 3, c, pi, S)
+    assert np.allclose(same, c.sum() * rtt.amplitudes(terms[0], pi, S), rtol=1e-12)
+    ds = tt.direct_sum(terms, c)
+    assert ds[1].shape == (2, 3 * chi, 3 * chi)
+    assert np.allclose(rtt.lincomb_amplitudes(terms, c, pi, S), rtt.amplitudes(ds, pi, S),
+                       rtol=1e-11, atol=1e-14)
+    assert np.allclose(rtt.lincomb_flip_ratios(terms, c, pi, S[:7]),
+                       rtt.flip_ratios(ds, pi, S[:7]), rtol=1e-10)
+
+
+# ---------------------------------------------------------------- MCMC
+def test_single_flip_sweep_is_stationary():
+    """Brute force on 3x3 (512 states): |psi|^2 is left-invariant under the full
+    one-sweep transition matrix, and the matrix is stochastic."""
+    N = 9
+    pi = wl.path_site_plus_perms(N, 2, 71)
+    cores = rand_cores(wl.open_bonds(18, 2), 72)
+    T = mcmc.transition_matrix(cores, pi, N)
+    p = rtt.amplitudes(cores, pi, rtt.all_configs(N)) ** 2
+    p /= p.sum()
+    assert np.allclose(T.sum(axis=1), 1.0)
+    assert np.allclose(p @ T, p, atol=1e-13)
+
+
+def test_metropolis_energy_within_3_sigma_of_exact():
+    Lx = Ly = 3
+    N = 9
+    pi = wl.path_site_plus_perms(N, 2, 81)
+    cores = rand_cores(wl.open_bonds(18, 3), 82)
+    b = tfim.bonds(Lx, Ly)
+    exact = rtt.exact_energy(cores, pi, N, b, 1.0, 3.04)
+    spins0 = wl.random_spins(64, N, 83)
+    _, series = mcmc.energy_series(cores, pi, spins0, seed=84, stream=0, n_burn=20,
+                                   n_meas=150, bonds=b, J=1.0, h=3.04)
+    mean, sigma, tau, var = stats.energy_estimate(series)
+    assert abs(mean - exact) < 3 * sigma, (mean, exact, sigma, tau)
+
+
+def test_metropolis_r1_n64_against_transfer_matrix_energy():
+    """8x8, R = 1, chi = 3: the chain's energy agrees with the exact MPS value
+    from transfer matrices (pins the estimator at 64 spins)."""
+    N = 64
+    pi = np.arange(N)
+    cores = rand_cores(wl.open_bonds(N, 3), 91)
+    b = tfim.bonds(8, 8)
+    exact = tt.mps_energy(cores, b, 1.0, 3.04)
+    _, series = mcmc.energy_series(cores, pi, wl.random_spins(48, N, 92), seed=93,
+                                   stream=0, n_burn=15, n_meas=40, bonds=b, J=1.0, h=3.04)
+    mean, sigma, tau, _ = stats.energy_estimate(series)
+    assert abs(mean - exact) < 3 * sigma, (mean, exact, sigma, tau)
+
+
+def test_proposal_order():
+    assert mcmc.proposal_order(np.array([2, 0, 2, 1, 0]), 4) == [2, 0, 1, 3]
+
+
+# ---------------------------------------------------------------- RNG / stats / quant
+def test_philox_matches_numpy():
+    for key in [(0, 0), (5, 7), (2 ** 63 + 11, 12345)]:
+        for ctr in [(0, 0, 0, 0), (3, 9, 1, 0), (2 ** 64 - 2, 5, 6, 7)]:
+            bg = np.random.Philox(key=np.array(key, dtype=np.uint64),
+                                  counter=np.array(ctr, dtype=np.uint64))
+            # numpy increments the counter before producing a block
+            nxt = list(ctr)
+            nxt[0] = (nxt[0] + 1) % 2 ** 64
+            if nxt[0] == 0:
+                nxt[1] += 1
+            got = philox.philox4x64_10(nxt, key)
+            assert list(got) == [int(x) for x in bg.random_raw(4)]
+    u = philox.uniform(1, 2, 3, 4, 5)
+    assert 0.0 <= u < 1.0
+
+
+def test_fsum_and_tau_int_ar1():
+    x = np.array([1e16, 1.0, -1e16, 1.0])
+    assert stats.fsum_mean(x) == 0.5
+    g = np.random.default_rng(7)
+    for rho in (0.0, 0.5, 0.8):
+        T, W = 20000, 8
+        e = g.standard_normal((T, W))
+        y = np.empty_like(e)
+        y[0] = e[0] / math.sqrt(1 - rho * rho)
+        for t in range(1, T):
+            y[t] = rho * y[t - 1] + e[t]
+        tau = stats.tau_int(y)
+        assert tau == pytest.approx((1 + rho) / (1 - rho), rel=0.1)
+        blk = stats.blocking_error(y[:, 0])
+        naive = math.sqrt(np.var(y[:, 0]) / T)
+        assert blk / naive == pytest.approx(math.sqrt((1 + rho) / (1 - rho)), rel=0.25)
+
+
+def test_quantisation():
+    # bf16 keeps 8 significant bits: ulp(1) = 2^-7; exact ties go to even
+    x = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, 1.0 + 3 * 2 ** -9])
+    q = quant.bf16_round(x)
+    assert list(q) == [1.0, 1.0, 1.0 + 2 ** -6, 1.0 + 2 ** -7]
+    core = np.array([[[1000.0, -0.5], [0.0, 3.0]], [[448.0 * 4, 1e-6], [7.0, -2.0]]])
+    deq, e, codes = quant.fp8_quantise(core)
+    assert e == 2 and np.all(np.isfinite(deq))
+    assert deq.max() == 1792.0
+    # every finite e4m3 code is exactly representable in bf16
+    import torch
+    allc = torch.arange(256, dtype=torch.uint8).view(torch.float8_e4m3fn).to(torch.float64)
+    fin = allc[torch.isfinite(allc)].numpy()
+    assert np.array_equal(quant.bf16_round(fin), fin)
