@@ -1,0 +1,173 @@
+/*
+ * rtt.h - C ABI of the replica-tensor-train (RTT) Monte Carlo library for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * An RTT (Srdinsek, Gouraud, Waintal, "Replica Tensor Train", Sec. 2.2.1) is
+ * a tensor train of L cores whose position k reads physical spin pi[k]; the
+ * amplitude of a spin configuration s is the product
+ *     psi(s) = A_0[s_pi(0)] A_1[s_pi(1)] ... A_{L-1}[s_pi(L-1)]
+ * of bond[k] x bond[k+1] matrices, with open boundary bonds
+ * bond[0] = bond[L] = 1 (Sec. 2.1).  A spin may be read at several positions
+ * (its replica set R_j = pi^{-1}(j)); flipping spin j switches the slice at
+ * every position of R_j (the X commutation rule of Sec. 2.2.3).
+ *
+ * Conventions for every call below
+ *   - Status codes: RTT_OK on success, a negative rtt_status otherwise;
+ *     rtt_last_error() returns a thread-local message for the last failure.
+ *     Argument errors are detected on the host before anything is launched.
+ *   - Host pointers are read during the call only; the library keeps its own
+ *     copies.  Device pointers are caller-owned and never freed here.
+ *   - Spin configurations live in device memory as uint64 words
+ *     [W][ceil(N/64)], bit (j % 64) of word (j / 64) holding s_j in {0, 1};
+ *     Z_j |s> = (1 - 2 s_j) |s>.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Evaluation and
+ *     sampling calls only enqueue work on it and never synchronise; create,
+ *     lincomb and destroy synchronise the device.
+ *   - A walker whose amplitude is zero or not finite gets status
+ *     RTT_E_NONFINITE in the optional per-walker status array and NaN
+ *     outputs; it is never skipped silently and never advanced by sampling.
+ */
+#ifndef RTT_H
+#define RTT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rtt_s* rtt_t;       /* packed device cores, schedules, workspace */
+typedef struct rtt_ham_s* rtt_ham_t; /* transverse-field Ising Hamiltonian */
+
+typedef enum {
+  RTT_F32 = 1,      /* cores rounded to FP32; FP32 matrix cores, FP32 accumulation */
+  RTT_BF16 = 2,     /* cores rounded (via FP32) to BF16; activations carried as a
+                       hi+lo BF16 pair; FP32 accumulation */
+  RTT_FP8_E4M3 = 3  /* cores as OCP e4m3 codes times one power-of-two scale per
+                       train position; exact BF16 dequantisation, then as BF16 */
+} rtt_dtype;
+
+typedef enum {
+  RTT_OK = 0,
+  RTT_E_ARG = -1,          /* invalid argument */
+  RTT_E_OOM = -2,          /* device allocation failed */
+  RTT_E_HIP = -3,          /* a HIP runtime call failed */
+  RTT_E_UNSUPPORTED = -4,  /* valid input outside what this build supports */
+  RTT_E_NONFINITE = -5     /* per-walker status: zero or non-finite amplitude */
+} rtt_status;
+
+/* Message for the last non-OK status returned on this thread ("" if none). */
+const char* rtt_last_error(void);
+
+/* ABI version; bumped on any incompatible change. */
+int32_t rtt_abi_version(void);
+
+/*
+ * Build an RTT on the current HIP device (Sec. 2.2.1 definition above).
+ *   n_spins  N >= 1 (N <= 1024)
+ *   n_cores  L >= 1
+ *   pi       host int32[L], values in [0, N); spins read by no position are
+ *            allowed (their flip ratio is exactly 1)
+ *   bond     host int32[L+1], bond[0] = bond[L] = 1, 1 <= bond[k] <= 256
+ *            (<= 128 for RTT_F32)
+ *   cores    host double, core k after core k-1, each stored row-major as
+ *            [2][bond[k]][bond[k+1]] (slice s = value of the spin read there)
+ *   dtype    rtt_dtype
+ * The library quantises the cores, packs them into matrix-core operand
+ * layouts padded to a power-of-two bond, and builds its contraction schedule.
+ * RTT_E_UNSUPPORTED if the working set of one walker exceeds on-chip memory.
+ */
+rtt_status rtt_create(int32_t n_spins, int32_t n_cores, const int32_t* pi,
+                      const int32_t* bond, const double* cores, int32_t dtype,
+                      rtt_t* out);
+
+/*
+ * Linear combination psi = sum_a coeffs[a] psi^a (Sec. 3.2, lin_comb
+ * equation) of n_terms RTTs that share N, L, pi, the padded bond and dtype.
+ * The new handle owns copies; the terms may be destroyed afterwards.
+ * coeffs: host double[n_terms].  RTT_E_ARG on mismatched terms.
+ */
+rtt_status rtt_lincomb(int32_t n_terms, const rtt_t* terms, const double* coeffs,
+                       rtt_t* out);
+
+rtt_status rtt_destroy(rtt_t h);
+
+/* info (host int32[8]): N, L, padded bond, dtype, n_terms, words per walker,
+   cut bond of the flip-ratio schedule, slots per walker. */
+rtt_status rtt_info(rtt_t h, int32_t* info);
+
+/*
+ * Quantised core values of term `term` exactly as the device uses them
+ * (FP8 scale applied), written to host `out` in the rtt_create layout.  The
+ * values are read back from device memory and unpacked from the fragment
+ * layout, so this also checks the packing.  Synchronises.
+ */
+rtt_status rtt_get_cores(rtt_t h, int32_t term, double* out);
+
+/*
+ * H = J sum_<ij> Z_i Z_j - h sum_i X_i on an Lx x Ly square lattice, sites in
+ * raster order i = y*Lx + x (Sec. 4, Ising model equation).  With periodic != 0
+ * wrap-around bonds are added along each side of length >= 3.
+ */
+rtt_status rtt_tfim_create(int32_t Lx, int32_t Ly, int32_t periodic, double J,
+                           double h, rtt_ham_t* out);
+rtt_status rtt_tfim_destroy(rtt_ham_t ham);
+
+/*
+ * Evaluate W walkers at the configurations `spins` (device, read only).
+ * Every output is an optional device pointer (NULL = not wanted):
+ *   logabs  double[W]      log|psi(s)|
+ *   sign    int8[W]        sign of psi(s) (+1 / -1)
+ *   logratio double[W][N]  log|r_j|, r_j = psi(s with s_j flipped) / psi(s)
+ *                          (flip at every replica of j, Sec. 2.2.3)
+ *   rsign   int8[W][N]     sign of r_j
+ *   eloc    double[W]      local energy sum_s' H_{s s'} psi(s') / psi(s)
+ *                          = J sum z_i z_j - h sum_j r_j (needs ham)
+ *   status  int32[W]       RTT_OK or RTT_E_NONFINITE per walker
+ * ham may be NULL unless eloc is requested.
+ */
+rtt_status rtt_evaluate(rtt_t h, rtt_ham_t ham, int32_t W, const uint64_t* spins,
+                        double* logabs, int8_t* sign, double* logratio, int8_t* rsign,
+                        double* eloc, int32_t* status, void* stream);
+
+/* Amplitudes only: log|psi| and sign for W walkers (device pointers). */
+rtt_status rtt_amplitudes(rtt_t h, int32_t W, const uint64_t* spins, double* logabs,
+                          int8_t* sign, void* stream);
+
+/* All N single-flip ratios per walker (device pointers, [W][N]). */
+rtt_status rtt_flip_ratios(rtt_t h, int32_t W, const uint64_t* spins,
+                           double* logratio, int8_t* rsign, void* stream);
+
+/* Local energies (device double[W]). */
+rtt_status rtt_local_energy(rtt_t h, rtt_ham_t ham, int32_t W, const uint64_t* spins,
+                            double* eloc, void* stream);
+
+/*
+ * n_sweeps single-spin-flip Metropolis sweeps on P(s) = |psi(s)|^2 / Z
+ * (Sec. 3.3).  One sweep proposes each spin once, in order of its first
+ * train position (spins read by no position last); the move is accepted iff
+ * u < r_j^2, with u = (x >> 11) * 2^-53 and x word 0 of Philox4x64-10 under
+ * key (seed, rng_stream) and counter (walker index, sweep0 + t, j, 0).
+ *   spins    device uint64[W][ceil(N/64)], updated in place
+ *   logabs   device double[W] or NULL: log|psi| of the final configuration
+ *   sign     device int8[W] or NULL
+ *   accepts  device uint32[W] or NULL: accepted moves, added to the input
+ *   status   device int32[W] or NULL
+ */
+rtt_status rtt_mcmc_sweep(rtt_t h, int32_t W, uint64_t* spins, double* logabs,
+                          int8_t* sign, uint64_t seed, uint64_t rng_stream,
+                          uint64_t sweep0, int32_t n_sweeps, uint32_t* accepts,
+                          int32_t* status, void* stream);
+
+/*
+ * Compensated (Neumaier) FP64 reduction of x[n] (device): out[0] = sum x,
+ * out[1] = sum x^2, out[2] = number of finite entries summed (device
+ * double[3]).  Non-finite entries are skipped and not counted.
+ */
+rtt_status rtt_energy_reduce(int32_t n, const double* x, double* out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RTT_H */

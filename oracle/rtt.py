@@ -140,3 +140,37 @@ def exact_energy(cores, pi, N, bonds, J, h) -> float:
     p = psi * psi
     el = local_energy(cores, pi, S, bonds, J, h)
     return math.fsum(p * el) / math.fsum(p)
+
+
+# --------------------------------------------------------------------------
+# conditioning of an amplitude (used to scale floating-point tolerances)
+# --------------------------------------------------------------------------
+def condition_numbers(cores, pi, spins) -> np.ndarray:
+    """kappa(s) = max over bonds c of ||l_c(s)|| ||r_c(s)|| / |psi(s)|, where
+    l_c is the product of the first c selected slices (a row vector) and r_c
+    the product of the remaining ones (a column vector), so psi = l_c . r_c
+    at every c.  kappa >= 1 (Cauchy-Schwarz); it measures the cancellation in
+    psi that any floating-point evaluation must resolve."""
+    spins = np.asarray(spins)
+    W = spins.shape[0]
+    L = len(cores)
+    left = [np.ones((W, 1))]
+    for k in range(L):
+        left.append(np.einsum("wa,wab->wb", left[-1], cores[k][spins[:, int(pi[k])].astype(np.int64)]))
+    right = [np.ones((W, 1))]
+    for k in reversed(range(L)):
+        right.append(np.einsum("wab,wb->wa", cores[k][spins[:, int(pi[k])].astype(np.int64)], right[-1]))
+    right = right[::-1]
+    psi = np.abs(left[-1][:, 0])
+    prod = np.stack([np.linalg.norm(left[c], axis=1) * np.linalg.norm(right[c], axis=1)
+                     for c in range(L + 1)])
+    with np.errstate(divide="ignore"):
+        return prod.max(axis=0) / psi
+
+
+def flip_condition_numbers(cores, pi, spins) -> np.ndarray:
+    """max(kappa(s), kappa(s with s_j flipped)) for every spin j, shape (W, N)."""
+    spins = np.asarray(spins)
+    k0 = condition_numbers(cores, pi, spins)
+    return np.stack([np.maximum(k0, condition_numbers(cores, pi, flip(spins, j)))
+                     for j in range(spins.shape[1])], axis=1)

@@ -1,0 +1,158 @@
+// Device-side building blocks for the RTT kernels on gfx950 (CDNA4, wave64).
+//
+// Matrix-core formulation.  Every contraction step of the method multiplies
+// a set of 1 x chi activation rows by one chi x chi core slice.  We compute
+// the transpose, out^T = A^T x in^T, so that
+//   * the MFMA "A" operand (M x K) is the core, M = output bond index,
+//   * the MFMA "B" operand (K x N) holds the activations, N = 16 rows,
+//   * the 16 x 16 result tile (M x N) gives 16 output features of 16 rows.
+// Lane l of a wave works on row n = l % 16 and K-group g = l / 16.  For a
+// row, group g owns the contiguous input features [g*chi/4, (g+1)*chi/4);
+// core fragments are pre-swizzled on the host so that each lane's share of
+// A is contiguous in memory.  Because lane l supplies the same K indices to A
+// and B, the result does not depend on the order in which the hardware walks
+// K inside one instruction.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rttk {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+
+// ---------------------------------------------------------------- BF16 bits
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);  // finite inputs only (activations are renormalised)
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) {
+  return __uint_as_float((uint32_t)h << 16);
+}
+
+// ---------------------------------------------------------------- dtype traits
+// Storage element of packed cores, elements per lane per row (KPL = chi/4),
+// and the K-loop of one 16x16 output tile.
+struct DF32 {
+  using elem = float;
+  static constexpr int kStep = 1;  // K values per lane per MFMA
+  template <int KPL>
+  __device__ __forceinline__ static f4 tile(const float (&a)[KPL], const float (&b)[KPL], f4 acc) {
+#pragma unroll
+    for (int c = 0; c < KPL; ++c)
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[c], b[c], acc, 0, 0, 0);
+    return acc;
+  }
+  __device__ __forceinline__ static float to_f32(float x) { return x; }
+};
+
+struct DBF16 {
+  using elem = uint16_t;
+  static constexpr int kStep = 8;
+  // b holds FP32 activations; they enter the matrix core as hi + lo BF16 so
+  // the product keeps ~16 significant bits of the activation.
+  template <int KPL>
+  __device__ __forceinline__ static f4 tile(const uint16_t (&a)[KPL], const float (&b)[KPL], f4 acc) {
+#pragma unroll
+    for (int c = 0; c < KPL / 8; ++c) {
+      u16x8 av, hi, lo;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        av[i] = a[8 * c + i];
+        uint16_t h = f32_to_bf16_rne(b[8 * c + i]);
+        hi[i] = h;
+        lo[i] = f32_to_bf16_rne(b[8 * c + i] - bf16_to_f32(h));
+      }
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av),
+                                                    __builtin_bit_cast(bf16x8, hi), acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av),
+                                                    __builtin_bit_cast(bf16x8, lo), acc, 0, 0, 0);
+    }
+    return acc;
+  }
+  __device__ __forceinline__ static float to_f32(uint16_t x) { return bf16_to_f32(x); }
+};
+
+// Load a lane's KPL-element fragment (contiguous, 16-byte aligned).
+template <int KPL>
+__device__ __forceinline__ void load_frag(float (&dst)[KPL], const float* src) {
+  const float4* s = reinterpret_cast<const float4*>(src);
+#pragma unroll
+  for (int i = 0; i < KPL / 4; ++i) {
+    float4 v = s[i];
+    dst[4 * i + 0] = v.x; dst[4 * i + 1] = v.y; dst[4 * i + 2] = v.z; dst[4 * i + 3] = v.w;
+  }
+}
+template <int KPL>
+__device__ __forceinline__ void load_frag(uint16_t (&dst)[KPL], const uint16_t* src) {
+  const uint4* s = reinterpret_cast<const uint4*>(src);
+#pragma unroll
+  for (int i = 0; i < KPL / 8; ++i) {
+    uint4 v = s[i];
+    uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      dst[8 * i + 2 * j] = (uint16_t)(w[j] & 0xffffu);
+      dst[8 * i + 2 * j + 1] = (uint16_t)(w[j] >> 16);
+    }
+  }
+}
+
+// Read KPL consecutive floats of LDS (16-byte aligned).
+template <int KPL>
+__device__ __forceinline__ void lds_read(float (&dst)[KPL], const float* src) {
+  const float4* s = reinterpret_cast<const float4*>(src);
+#pragma unroll
+  for (int i = 0; i < KPL / 4; ++i) {
+    float4 v = s[i];
+    dst[4 * i + 0] = v.x; dst[4 * i + 1] = v.y; dst[4 * i + 2] = v.z; dst[4 * i + 3] = v.w;
+  }
+}
+
+// Max |x| over a row held by the four K-groups of a wave (lanes m, m+16,
+// m+32, m+48), then the power-of-two exponent e with max * 2^-e in [0.5, 1).
+// Scaling by 2^-e is exact, so renormalisation adds no rounding.
+template <int KPL>
+__device__ __forceinline__ int renorm_row(float (&v)[KPL]) {
+  float mx = 0.f;
+#pragma unroll
+  for (int c = 0; c < KPL; ++c) mx = fmaxf(mx, fabsf(v[c]));
+  mx = fmaxf(mx, __shfl_xor(mx, 16));
+  mx = fmaxf(mx, __shfl_xor(mx, 32));
+  int e = (mx > 0.f) ? __builtin_amdgcn_frexp_expf(mx) : 0;
+#pragma unroll
+  for (int c = 0; c < KPL; ++c) v[c] = __builtin_amdgcn_ldexpf(v[c], -e);
+  return e;
+}
+
+// ---------------------------------------------------------------- Philox4x64-10
+// Salmon et al., SC'11: 10 rounds of two 64x64->128 multiplies per block,
+// key bumped by the Weyl constants between rounds.
+__device__ __forceinline__ uint64_t philox4x64_10_word0(uint64_t c0, uint64_t c1, uint64_t c2,
+                                                         uint64_t c3, uint64_t k0, uint64_t k1) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) { k0 += W0; k1 += W1; }
+    uint64_t hi0 = __umul64hi(M0, c0), lo0 = M0 * c0;
+    uint64_t hi1 = __umul64hi(M1, c2), lo1 = M1 * c2;
+    uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+  }
+  return c0;
+}
+
+__device__ __forceinline__ double philox_uniform(uint64_t seed, uint64_t stream, uint64_t walker,
+                                                 uint64_t sweep, uint64_t spin) {
+  uint64_t x = philox4x64_10_word0(walker, sweep, spin, 0, seed, stream);
+  return (double)(x >> 11) * (1.0 / 9007199254740992.0);
+}
+
+__device__ __forceinline__ int spin_bit(const uint64_t* words, int q) {
+  return (int)((words[q >> 6] >> (q & 63)) & 1ull);
+}
+
+}  // namespace rttk

@@ -1,0 +1,672 @@
+// Host side of the RTT library: argument checks, core quantisation and
+// packing, contraction schedules, workspace and kernel launches.
+#include <hip/hip_runtime.h>
+#include <limits.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/rtt.h"
+#include "rtt_kernels.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+rtt_status fail(rtt_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIPX(call)                                                                   \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return fail(e_ == hipErrorOutOfMemory ? RTT_E_OOM : RTT_E_HIP, "%s: %s (%s:%d)", \
+                  #call, hipGetErrorString(e_), __FILE__, __LINE__);                 \
+  } while (0)
+
+constexpr size_t kLdsLimit = 160 * 1024;
+
+// ------------------------------------------------------------------ quantisation
+float to_f32(double x) { return (float)x; }
+
+uint16_t bf16_bits_rne(float f) {
+  uint32_t u;
+  memcpy(&u, &f, 4);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+double bf16_value(uint16_t h) {
+  uint32_t u = (uint32_t)h << 16;
+  float f;
+  memcpy(&f, &u, 4);
+  return f;
+}
+
+// OCP e4m3 ("fn"): round-to-nearest-even of a float already divided by the
+// power-of-two scale, clamped to +-448 first.  Returns the decoded value.
+double e4m3_round(float f) {
+  double a = fabs((double)f);
+  const double sg = f < 0 ? -1.0 : 1.0;
+  if (a > 448.0) a = 448.0;
+  const double min_normal = ldexp(1.0, -6);
+  double q;
+  if (a < min_normal) {
+    q = nearbyint(a * 512.0) / 512.0;  // subnormal spacing 2^-9
+  } else {
+    int ex = 0;
+    frexp(a, &ex);                     // a = m 2^ex, m in [0.5, 1)
+    const double step = ldexp(1.0, ex - 1 - 3);  // 3 mantissa bits
+    q = nearbyint(a / step) * step;
+  }
+  return sg * q;
+}
+
+int fp8_scale_exponent(const double* c, size_t n) {
+  double amax = 0.0;
+  for (size_t i = 0; i < n; ++i) amax = std::max(amax, fabs(c[i]));
+  if (amax == 0.0) return 0;
+  return (int)ceil(log2(amax / 448.0));
+}
+
+int next_pow2(int x) {
+  int p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+struct Sched {
+  std::vector<int> fwd, bwd;  // int4 entries
+  std::vector<int> fslot, bslot;
+  int cut = 0, nslot = 16, nf = 1, nb = 1;
+  long cost = 0;
+};
+
+// Forward steps over positions [0, c), backward steps over [c, L) from the
+// right; each spin gets a row spawned at its first position (forward) and a
+// column spawned at its last position (backward) on its side of the cut.
+Sched build_sched(const std::vector<int>& pi, int N, int L, int c) {
+  Sched s;
+  s.cut = c;
+  s.fslot.assign(N, 0);
+  s.bslot.assign(N, 0);
+  std::vector<int> fs(N, -1), bs(N, -1);
+  int nf = 1;
+  for (int k = 0; k < c; ++k) {
+    const int q = pi[k];
+    int oin, oout;
+    if (fs[q] < 0) { fs[q] = nf++; oin = 0; oout = fs[q]; }
+    else { oin = oout = fs[q]; }
+    s.fwd.insert(s.fwd.end(), {k, q, nf, oin | (oout << 16)});
+    s.cost += (nf + 15) / 16;
+  }
+  int nb = 1;
+  for (int k = L - 1; k >= c; --k) {
+    const int q = pi[k];
+    int oin, oout;
+    if (bs[q] < 0) { bs[q] = nb++; oin = 0; oout = bs[q]; }
+    else { oin = oout = bs[q]; }
+    s.bwd.insert(s.bwd.end(), {k, q, nb, oin | (oout << 16)});
+    s.cost += (nb + 15) / 16;
+  }
+  for (int j = 0; j < N; ++j) {
+    s.fslot[j] = fs[j] < 0 ? 0 : fs[j];
+    s.bslot[j] = bs[j] < 0 ? 0 : bs[j];
+  }
+  s.nf = nf;
+  s.nb = nb;
+  s.nslot = (std::max(nf, nb) + 15) / 16 * 16;
+  return s;
+}
+
+size_t pass_lds_bytes(int chi, int nslot, int nw) {
+  const int wpw = chi >= 64 ? 4 : chi / 16;
+  const int wpb = 4 / wpw;
+  const size_t rs = chi + 4;
+  return (size_t)wpb * (2 * nslot * rs * 4 + 2 * nslot * 4 + nw * 8);
+}
+
+size_t chain_lds_bytes(int chi, int T, int nw) {
+  const size_t rs = chi + 4;
+  return (size_t)T * 5 * 16 * rs * 4 + (size_t)T * 5 * 16 * 4 + 16 * nw * 8 + 16 * 8 + 16 * 4 * 4;
+}
+
+}  // namespace
+
+struct rtt_s {
+  int N = 0, L = 0, chi = 0, dtype = 0, T = 1, nw = 0, device = 0;
+  std::vector<int> pi, bond;
+  std::vector<double> coeffs;
+  std::vector<std::vector<double>> qcores;  // quantised values, rtt_create layout, per term
+  std::vector<int> core_exp;                // [T][L]
+  Sched sched;
+  std::vector<int> order, first;
+  // device
+  void* d_fwd = nullptr;      // [T][L][2][chi*chi] transposed fragments
+  void* d_bwd = nullptr;      // [T][L][2][chi*chi]
+  int* d_cexp = nullptr;
+  int4* d_sf = nullptr;
+  int4* d_sb = nullptr;
+  int* d_fslot = nullptr;
+  int* d_bslot = nullptr;
+  int* d_pi = nullptr;
+  int* d_order = nullptr;
+  int* d_first = nullptr;
+  double* d_coeffs = nullptr;
+  // workspace
+  size_t ws_W = 0;
+  float* d_u = nullptr;
+  float* d_v = nullptr;
+  int* d_ue = nullptr;
+  int* d_ve = nullptr;
+};
+
+struct rtt_ham_s {
+  int Lx = 0, Ly = 0, periodic = 0, nb = 0;
+  double J = 0, h = 0;
+  int2* d_bonds = nullptr;
+};
+
+namespace {
+
+size_t elem_bytes(int dtype) { return dtype == RTT_F32 ? 4 : 2; }
+
+// Pack one term: element (t, lane, e) of slice (k, b) in the forward layout
+// is core[b][g*KPL + e][16t + m] (transposed), in the backward layout
+// core[b][16t + m][g*KPL + e]; lane = 16 g + m, KPL = chi / 4.
+void pack_term(const rtt_s* h, const std::vector<double>& q, std::vector<uint8_t>& fw,
+               std::vector<uint8_t>& bw) {
+  const int chi = h->chi, L = h->L, KPL = chi / 4;
+  const size_t eb = elem_bytes(h->dtype);
+  const size_t slice = (size_t)chi * chi;
+  fw.assign((size_t)L * 2 * slice * eb, 0);
+  bw.assign((size_t)L * 2 * slice * eb, 0);
+  size_t off = 0;
+  for (int k = 0; k < L; ++k) {
+    const int a = h->bond[k], b = h->bond[k + 1];
+    std::vector<double> pad((size_t)2 * slice, 0.0);
+    for (int s = 0; s < 2; ++s)
+      for (int i = 0; i < a; ++i)
+        for (int j = 0; j < b; ++j) pad[s * slice + (size_t)i * chi + j] = q[off + ((size_t)s * a + i) * b + j];
+    off += (size_t)2 * a * b;
+    for (int s = 0; s < 2; ++s) {
+      const size_t base = ((size_t)k * 2 + s) * slice;
+      for (int t = 0; t < chi / 16; ++t)
+        for (int lane = 0; lane < 64; ++lane)
+          for (int e = 0; e < KPL; ++e) {
+            const int g = lane >> 4, m = lane & 15;
+            const size_t idx = base + ((size_t)t * 64 + lane) * KPL + e;
+            const double vf = pad[s * slice + (size_t)(g * KPL + e) * chi + 16 * t + m];
+            const double vb = pad[s * slice + (size_t)(16 * t + m) * chi + g * KPL + e];
+            if (eb == 4) {
+              const float ff = (float)vf, fb = (float)vb;
+              memcpy(&fw[idx * 4], &ff, 4);
+              memcpy(&bw[idx * 4], &fb, 4);
+            } else {
+              const uint16_t hf = bf16_bits_rne((float)vf), hb = bf16_bits_rne((float)vb);
+              memcpy(&fw[idx * 2], &hf, 2);
+              memcpy(&bw[idx * 2], &hb, 2);
+            }
+          }
+    }
+  }
+}
+
+rtt_status upload(void** dst, const void* src, size_t bytes) {
+  HIPX(hipMalloc(dst, std::max<size_t>(bytes, 16)));
+  if (bytes) HIPX(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice));
+  return RTT_OK;
+}
+
+void free_dev(rtt_s* h) {
+  void* ptrs[] = {h->d_fwd, h->d_bwd, h->d_cexp, h->d_sf, h->d_sb, h->d_fslot, h->d_bslot,
+                  h->d_pi, h->d_order, h->d_first, h->d_coeffs, h->d_u, h->d_v, h->d_ue, h->d_ve};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+}
+
+// Quantised copy of the cores (rtt_create layout) and per-position exponents.
+void quantise(int dtype, const std::vector<int>& bond, const double* cores, std::vector<double>& q,
+              std::vector<int>& cexp) {
+  const int L = (int)bond.size() - 1;
+  size_t off = 0;
+  q.clear();
+  cexp.assign(L, 0);
+  for (int k = 0; k < L; ++k) {
+    const size_t n = (size_t)2 * bond[k] * bond[k + 1];
+    const double* c = cores + off;
+    if (dtype == RTT_F32) {
+      for (size_t i = 0; i < n; ++i) q.push_back((double)to_f32(c[i]));
+    } else if (dtype == RTT_BF16) {
+      for (size_t i = 0; i < n; ++i) q.push_back(bf16_value(bf16_bits_rne((float)c[i])));
+    } else {  // FP8 e4m3: codes kept unscaled, scale applied as an exponent
+      const int e = fp8_scale_exponent(c, n);
+      cexp[k] = e;
+      for (size_t i = 0; i < n; ++i) q.push_back(e4m3_round((float)ldexp(c[i], -e)));
+    }
+    off += n;
+  }
+}
+
+rtt_status finish_create(rtt_s* h) {
+  // schedules: choose the cut bond with the least matrix-core work that fits on chip
+  Sched best;
+  bool have = false;
+  for (int c = 0; c <= h->L; ++c) {
+    Sched s = build_sched(h->pi, h->N, h->L, c);
+    if (pass_lds_bytes(h->chi, s.nslot, h->nw) > kLdsLimit) continue;
+    if (!have || s.cost < best.cost) { best = s; have = true; }
+  }
+  if (!have) return fail(RTT_E_UNSUPPORTED, "rtt_create: flip-ratio rows of one walker exceed on-chip memory");
+  if (chain_lds_bytes(h->chi, h->T, h->nw) > kLdsLimit)
+    return fail(RTT_E_UNSUPPORTED, "rtt_create: sampling state of 16 walkers exceeds on-chip memory");
+  h->sched = best;
+  // proposal order: spins by first position, unread spins last
+  h->first.assign(h->N, -1);
+  for (int k = 0; k < h->L; ++k)
+    if (h->first[h->pi[k]] < 0) h->first[h->pi[k]] = k;
+  h->order.clear();
+  for (int k = 0; k < h->L; ++k)
+    if (h->first[h->pi[k]] == k) h->order.push_back(h->pi[k]);
+  for (int j = 0; j < h->N; ++j)
+    if (h->first[j] < 0) h->order.push_back(j);
+
+  // pack and upload every term
+  std::vector<uint8_t> fw_all, bw_all, fw, bw;
+  for (int t = 0; t < h->T; ++t) {
+    pack_term(h, h->qcores[t], fw, bw);
+    fw_all.insert(fw_all.end(), fw.begin(), fw.end());
+    bw_all.insert(bw_all.end(), bw.begin(), bw.end());
+  }
+  rtt_status st;
+  if ((st = upload(&h->d_fwd, fw_all.data(), fw_all.size())) != RTT_OK) return st;
+  if ((st = upload(&h->d_bwd, bw_all.data(), bw_all.size())) != RTT_OK) return st;
+  if ((st = upload((void**)&h->d_cexp, h->core_exp.data(), h->core_exp.size() * 4)) != RTT_OK) return st;
+  if ((st = upload((void**)&h->d_sf, best.fwd.data(), best.fwd.size() * 4)) != RTT_OK) return st;
+  if ((st = upload((void**)&h->d_sb, best.bwd.data(), best.bwd.size() * 4)) != RTT_OK) return st;
+  if ((st = upload((void**)&h->d_fslot, best.fslot.data(), best.fslot.size() * 4)) != RTT_OK) return st;
+  if ((st = upload((void**)&h->d_bslot, best.bslot.data(), best.bslot.size() * 4)) != RTT_OK) return st;
+  if ((st = upload((void**)&h->d_pi, h->pi.data(), h->pi.size() * 4)) != RTT_OK) return st;
+  if ((st = upload((void**)&h->d_order, h->order.data(), h->order.size() * 4)) != RTT_OK) return st;
+  if ((st = upload((void**)&h->d_first, h->first.data(), h->first.size() * 4)) != RTT_OK) return st;
+  if ((st = upload((void**)&h->d_coeffs, h->coeffs.data(), h->coeffs.size() * 8)) != RTT_OK) return st;
+  HIPX(hipDeviceSynchronize());
+  return RTT_OK;
+}
+
+rtt_status ensure_ws(rtt_s* h, int W) {
+  if ((size_t)W <= h->ws_W) return RTT_OK;
+  for (void* p : {(void*)h->d_u, (void*)h->d_v, (void*)h->d_ue, (void*)h->d_ve})
+    if (p) HIPX(hipFree(p));
+  h->d_u = h->d_v = nullptr;
+  h->d_ue = h->d_ve = nullptr;
+  h->ws_W = 0;
+  const size_t rows = (size_t)h->T * W * h->sched.nslot;
+  HIPX(hipMalloc(&h->d_u, rows * h->chi * 4));
+  HIPX(hipMalloc(&h->d_v, rows * h->chi * 4));
+  HIPX(hipMalloc(&h->d_ue, rows * 4));
+  HIPX(hipMalloc(&h->d_ve, rows * 4));
+  h->ws_W = W;
+  return RTT_OK;
+}
+
+// ------------------------------------------------------------------ dispatch
+template <class D, int CHI>
+rtt_status launch_pass(const rttk::PassArgs& a, int T, hipStream_t s) {
+  constexpr int WPW = rttk::Geo<CHI>::WPW;
+  constexpr int WPB = 4 / WPW;
+  const size_t lds = pass_lds_bytes(CHI, a.nslot, a.nw);
+  auto kfn = rttk::pass_kernel<D, CHI>;
+  HIPX(hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  dim3 grid((a.W + WPB - 1) / WPB, T);
+  hipLaunchKernelGGL(kfn, grid, dim3(256), lds, s, a);
+  HIPX(hipGetLastError());
+  return RTT_OK;
+}
+
+template <class D, int CHI>
+rtt_status launch_chain(const rttk::ChainArgs& a, hipStream_t s) {
+  constexpr int WPW = rttk::Geo<CHI>::WPW;
+  const size_t lds = chain_lds_bytes(CHI, a.T, a.nw);
+  auto kfn = rttk::chain_kernel<D, CHI>;
+  HIPX(hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  dim3 grid((a.W + 15) / 16);
+  hipLaunchKernelGGL(kfn, grid, dim3(64 * WPW), lds, s, a);
+  HIPX(hipGetLastError());
+  return RTT_OK;
+}
+
+template <template <class, int> class F, class... Args>
+rtt_status dispatch(int dtype, int chi, Args&&... args) {
+  if (dtype == RTT_F32) {
+    switch (chi) {
+      case 16: return F<rttk::DF32, 16>::run(args...);
+      case 32: return F<rttk::DF32, 32>::run(args...);
+      case 64: return F<rttk::DF32, 64>::run(args...);
+      case 128: return F<rttk::DF32, 128>::run(args...);
+    }
+  } else {
+    switch (chi) {
+      case 32: return F<rttk::DBF16, 32>::run(args...);
+      case 64: return F<rttk::DBF16, 64>::run(args...);
+      case 128: return F<rttk::DBF16, 128>::run(args...);
+      case 256: return F<rttk::DBF16, 256>::run(args...);
+    }
+  }
+  return fail(RTT_E_UNSUPPORTED, "no kernel for dtype %d, padded bond %d", dtype, chi);
+}
+
+template <class D, int CHI>
+struct PassL {
+  static rtt_status run(const rttk::PassArgs& a, int T, hipStream_t s) { return launch_pass<D, CHI>(a, T, s); }
+};
+template <class D, int CHI>
+struct ChainL {
+  static rtt_status run(const rttk::ChainArgs& a, hipStream_t s) { return launch_chain<D, CHI>(a, s); }
+};
+
+rtt_status check_handle(const rtt_s* h) {
+  if (!h) return fail(RTT_E_ARG, "null RTT handle");
+  return RTT_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+extern "C" {
+
+const char* rtt_last_error(void) { return g_err.c_str(); }
+
+int32_t rtt_abi_version(void) { return 1; }
+
+rtt_status rtt_create(int32_t n_spins, int32_t n_cores, const int32_t* pi, const int32_t* bond,
+                      const double* cores, int32_t dtype, rtt_t* out) {
+  g_err.clear();
+  if (!out) return fail(RTT_E_ARG, "rtt_create: out is null");
+  *out = nullptr;
+  if (n_spins < 1 || n_spins > 1024) return fail(RTT_E_ARG, "rtt_create: n_spins %d outside [1, 1024]", n_spins);
+  if (n_cores < 1) return fail(RTT_E_ARG, "rtt_create: n_cores %d < 1", n_cores);
+  if (!pi || !bond || !cores) return fail(RTT_E_ARG, "rtt_create: null pointer argument");
+  if (dtype != RTT_F32 && dtype != RTT_BF16 && dtype != RTT_FP8_E4M3)
+    return fail(RTT_E_ARG, "rtt_create: unknown dtype %d", dtype);
+  for (int k = 0; k < n_cores; ++k)
+    if (pi[k] < 0 || pi[k] >= n_spins) return fail(RTT_E_ARG, "rtt_create: pi[%d] = %d outside [0, %d)", k, pi[k], n_spins);
+  if (bond[0] != 1 || bond[n_cores] != 1) return fail(RTT_E_ARG, "rtt_create: boundary bonds must be 1");
+  int bmax = 1;
+  for (int k = 0; k <= n_cores; ++k) {
+    if (bond[k] < 1 || bond[k] > 256) return fail(RTT_E_ARG, "rtt_create: bond[%d] = %d outside [1, 256]", k, bond[k]);
+    bmax = std::max(bmax, (int)bond[k]);
+  }
+  const int chi = std::max(dtype == RTT_F32 ? 16 : 32, next_pow2(bmax));
+  if (dtype == RTT_F32 && chi > 128) return fail(RTT_E_UNSUPPORTED, "rtt_create: FP32 supports bonds up to 128");
+  size_t ncore = 0;
+  for (int k = 0; k < n_cores; ++k) ncore += (size_t)2 * bond[k] * bond[k + 1];
+  for (size_t i = 0; i < ncore; ++i)
+    if (!isfinite(cores[i])) return fail(RTT_E_ARG, "rtt_create: non-finite core entry %zu", i);
+
+  rtt_s* h = new rtt_s;
+  h->N = n_spins;
+  h->L = n_cores;
+  h->chi = chi;
+  h->dtype = dtype;
+  h->T = 1;
+  h->nw = (n_spins + 63) / 64;
+  h->pi.assign(pi, pi + n_cores);
+  h->bond.assign(bond, bond + n_cores + 1);
+  h->coeffs = {1.0};
+  h->qcores.resize(1);
+  quantise(dtype, h->bond, cores, h->qcores[0], h->core_exp);
+  hipGetDevice(&h->device);
+  rtt_status st = finish_create(h);
+  if (st != RTT_OK) {
+    free_dev(h);
+    delete h;
+    return st;
+  }
+  *out = h;
+  return RTT_OK;
+}
+
+rtt_status rtt_lincomb(int32_t n_terms, const rtt_t* terms, const double* coeffs, rtt_t* out) {
+  g_err.clear();
+  if (!out) return fail(RTT_E_ARG, "rtt_lincomb: out is null");
+  *out = nullptr;
+  if (n_terms < 1 || n_terms > rttk::kMaxTerms) return fail(RTT_E_ARG, "rtt_lincomb: n_terms %d outside [1, %d]", n_terms, rttk::kMaxTerms);
+  if (!terms || !coeffs) return fail(RTT_E_ARG, "rtt_lincomb: null pointer argument");
+  const rtt_s* t0 = terms[0];
+  if (!t0) return fail(RTT_E_ARG, "rtt_lincomb: null term 0");
+  for (int t = 0; t < n_terms; ++t) {
+    const rtt_s* x = terms[t];
+    if (!x) return fail(RTT_E_ARG, "rtt_lincomb: null term %d", t);
+    if (x->T != 1) return fail(RTT_E_ARG, "rtt_lincomb: term %d is itself a combination", t);
+    if (x->N != t0->N || x->L != t0->L || x->pi != t0->pi || x->chi != t0->chi || x->dtype != t0->dtype)
+      return fail(RTT_E_ARG, "rtt_lincomb: term %d differs from term 0 in N, L, pi, bond or dtype", t);
+    if (!isfinite(coeffs[t])) return fail(RTT_E_ARG, "rtt_lincomb: coefficient %d not finite", t);
+  }
+  rtt_s* h = new rtt_s;
+  h->N = t0->N;
+  h->L = t0->L;
+  h->chi = t0->chi;
+  h->dtype = t0->dtype;
+  h->T = n_terms;
+  h->nw = t0->nw;
+  h->pi = t0->pi;
+  h->bond = t0->bond;
+  // terms may have different inner bonds: keep each term's own layout
+  h->coeffs.assign(coeffs, coeffs + n_terms);
+  h->core_exp.clear();
+  for (int t = 0; t < n_terms; ++t) {
+    h->qcores.push_back(terms[t]->qcores[0]);
+    h->core_exp.insert(h->core_exp.end(), terms[t]->core_exp.begin(), terms[t]->core_exp.end());
+  }
+  // pack_term reads bond per handle: all terms share bond only if equal; pad via each term
+  bool same_bond = true;
+  for (int t = 0; t < n_terms; ++t) same_bond &= (terms[t]->bond == t0->bond);
+  if (!same_bond) {
+    delete h;
+    return fail(RTT_E_ARG, "rtt_lincomb: terms must share the bond dimensions");
+  }
+  hipGetDevice(&h->device);
+  rtt_status st = finish_create(h);
+  if (st != RTT_OK) {
+    free_dev(h);
+    delete h;
+    return st;
+  }
+  *out = h;
+  return RTT_OK;
+}
+
+rtt_status rtt_destroy(rtt_t h) {
+  g_err.clear();
+  if (!h) return RTT_OK;
+  HIPX(hipDeviceSynchronize());
+  free_dev(h);
+  delete h;
+  return RTT_OK;
+}
+
+rtt_status rtt_info(rtt_t h, int32_t* info) {
+  if (check_handle(h) != RTT_OK) return RTT_E_ARG;
+  if (!info) return fail(RTT_E_ARG, "rtt_info: info is null");
+  info[0] = h->N; info[1] = h->L; info[2] = h->chi; info[3] = h->dtype;
+  info[4] = h->T; info[5] = h->nw; info[6] = h->sched.cut; info[7] = h->sched.nslot;
+  return RTT_OK;
+}
+
+// Quantised core values of one term as the device uses them (host double,
+// rtt_create layout, FP8 scale applied).  Read back from device memory and
+// unpacked, so it also checks the fragment packing.
+rtt_status rtt_get_cores(rtt_t h, int32_t term, double* out) {
+  if (check_handle(h) != RTT_OK) return RTT_E_ARG;
+  if (!out || term < 0 || term >= h->T) return fail(RTT_E_ARG, "rtt_get_cores: bad argument");
+  const int chi = h->chi, L = h->L, KPL = chi / 4;
+  const size_t eb = elem_bytes(h->dtype), slice = (size_t)chi * chi;
+  std::vector<uint8_t> fw((size_t)L * 2 * slice * eb);
+  HIPX(hipMemcpy(fw.data(), (const uint8_t*)h->d_fwd + (size_t)term * fw.size(), fw.size(), hipMemcpyDeviceToHost));
+  size_t off = 0;
+  for (int k = 0; k < L; ++k) {
+    const int a = h->bond[k], b = h->bond[k + 1];
+    const double scale = ldexp(1.0, h->core_exp[(size_t)term * L + k]);
+    for (int s = 0; s < 2; ++s)
+      for (int i = 0; i < a; ++i)
+        for (int j = 0; j < b; ++j) {
+          // forward layout holds core[s][i][j] at g*KPL+e = i, 16t+m = j
+          const int g = i / KPL, e = i % KPL, t = j / 16, m = j % 16;
+          const size_t idx = ((size_t)k * 2 + s) * slice + ((size_t)t * 64 + 16 * g + m) * KPL + e;
+          double v;
+          if (eb == 4) { float f; memcpy(&f, &fw[idx * 4], 4); v = f; }
+          else { uint16_t u; memcpy(&u, &fw[idx * 2], 2); v = bf16_value(u); }
+          out[off + ((size_t)s * a + i) * b + j] = v * scale;
+        }
+    off += (size_t)2 * a * b;
+  }
+  return RTT_OK;
+}
+
+rtt_status rtt_tfim_create(int32_t Lx, int32_t Ly, int32_t periodic, double J, double h, rtt_ham_t* out) {
+  g_err.clear();
+  if (!out) return fail(RTT_E_ARG, "rtt_tfim_create: out is null");
+  *out = nullptr;
+  if (Lx < 1 || Ly < 1 || (long)Lx * Ly > 1024) return fail(RTT_E_ARG, "rtt_tfim_create: bad lattice %dx%d", Lx, Ly);
+  if (!isfinite(J) || !isfinite(h)) return fail(RTT_E_ARG, "rtt_tfim_create: J and h must be finite");
+  std::vector<int2> b;
+  for (int y = 0; y < Ly; ++y)
+    for (int x = 0; x < Lx; ++x) {
+      const int i = y * Lx + x;
+      if (x + 1 < Lx) b.push_back(make_int2(i, y * Lx + x + 1));
+      else if (periodic && Lx >= 3) b.push_back(make_int2(i, y * Lx));
+      if (y + 1 < Ly) b.push_back(make_int2(i, (y + 1) * Lx + x));
+      else if (periodic && Ly >= 3) b.push_back(make_int2(i, x));
+    }
+  rtt_ham_s* H = new rtt_ham_s;
+  H->Lx = Lx; H->Ly = Ly; H->periodic = periodic; H->J = J; H->h = h; H->nb = (int)b.size();
+  rtt_status st = upload((void**)&H->d_bonds, b.data(), b.size() * sizeof(int2));
+  if (st != RTT_OK) { delete H; return st; }
+  *out = H;
+  return RTT_OK;
+}
+
+rtt_status rtt_tfim_destroy(rtt_ham_t H) {
+  if (!H) return RTT_OK;
+  HIPX(hipDeviceSynchronize());
+  if (H->d_bonds) (void)hipFree(H->d_bonds);
+  delete H;
+  return RTT_OK;
+}
+
+rtt_status rtt_evaluate(rtt_t h, rtt_ham_t ham, int32_t W, const uint64_t* spins, double* logabs,
+                        int8_t* sign, double* logratio, int8_t* rsign, double* eloc, int32_t* status,
+                        void* stream) {
+  g_err.clear();
+  if (check_handle(h) != RTT_OK) return RTT_E_ARG;
+  if (W < 1) return fail(RTT_E_ARG, "rtt_evaluate: W = %d < 1", W);
+  if (!spins) return fail(RTT_E_ARG, "rtt_evaluate: spins is null");
+  if (eloc && !ham) return fail(RTT_E_ARG, "rtt_evaluate: eloc requested without a Hamiltonian");
+  if (ham && ham->Lx * ham->Ly != h->N) return fail(RTT_E_ARG, "rtt_evaluate: lattice has %d sites, RTT has %d spins", ham->Lx * ham->Ly, h->N);
+  hipStream_t s = (hipStream_t)stream;
+  rtt_status st = ensure_ws(h, W);
+  if (st != RTT_OK) return st;
+  const size_t tslice = (size_t)h->L * 2 * h->chi * h->chi * elem_bytes(h->dtype);
+  (void)tslice;
+  rttk::PassArgs pa{};
+  pa.core_exp = h->dtype == RTT_FP8_E4M3 ? h->d_cexp : nullptr;
+  pa.nslot = h->sched.nslot;
+  pa.L = h->L;
+  pa.nw = h->nw;
+  pa.W = W;
+  pa.spins = spins;
+  // forward
+  pa.cores = h->d_fwd;
+  pa.sched = h->d_sf;
+  pa.n_steps = (int)h->sched.fwd.size() / 4;
+  pa.out_vec = h->d_u;
+  pa.out_exp = h->d_ue;
+  if ((st = dispatch<PassL>(h->dtype, h->chi, pa, h->T, s)) != RTT_OK) return st;
+  // backward
+  pa.cores = h->d_bwd;
+  pa.sched = h->d_sb;
+  pa.n_steps = (int)h->sched.bwd.size() / 4;
+  pa.out_vec = h->d_v;
+  pa.out_exp = h->d_ve;
+  if ((st = dispatch<PassL>(h->dtype, h->chi, pa, h->T, s)) != RTT_OK) return st;
+  rttk::CombineArgs ca{};
+  ca.u = h->d_u; ca.ue = h->d_ue; ca.v = h->d_v; ca.ve = h->d_ve;
+  ca.nsf = h->sched.nslot; ca.nsb = h->sched.nslot; ca.chi = h->chi; ca.T = h->T; ca.W = W;
+  ca.N = h->N; ca.nw = h->nw; ca.fslot = h->d_fslot; ca.bslot = h->d_bslot; ca.coeffs = h->d_coeffs;
+  ca.spins = spins;
+  ca.bonds = ham ? ham->d_bonds : nullptr;
+  ca.nbonds = ham ? ham->nb : 0;
+  ca.J = ham ? ham->J : 0.0;
+  ca.h = ham ? ham->h : 0.0;
+  ca.logabs = logabs; ca.sign = sign; ca.logratio = logratio; ca.rsign = rsign; ca.eloc = eloc; ca.status = status;
+  hipLaunchKernelGGL(rttk::combine_kernel, dim3((W + 3) / 4), dim3(256), 0, s, ca);
+  HIPX(hipGetLastError());
+  return RTT_OK;
+}
+
+rtt_status rtt_flip_ratios(rtt_t h, int32_t W, const uint64_t* spins, double* logratio, int8_t* rsign,
+                           void* stream) {
+  return rtt_evaluate(h, nullptr, W, spins, nullptr, nullptr, logratio, rsign, nullptr, nullptr, stream);
+}
+
+rtt_status rtt_local_energy(rtt_t h, rtt_ham_t ham, int32_t W, const uint64_t* spins, double* eloc,
+                            void* stream) {
+  if (!eloc) return fail(RTT_E_ARG, "rtt_local_energy: eloc is null");
+  return rtt_evaluate(h, ham, W, spins, nullptr, nullptr, nullptr, nullptr, eloc, nullptr, stream);
+}
+
+static rtt_status chain_common(rtt_t h, int32_t W, uint64_t* spins, double* logabs, int8_t* sign,
+                               uint64_t seed, uint64_t rstream, uint64_t sweep0, int32_t n_sweeps,
+                               uint32_t* accepts, int32_t* status, int mode, void* stream) {
+  if (check_handle(h) != RTT_OK) return RTT_E_ARG;
+  if (W < 1) return fail(RTT_E_ARG, "W = %d < 1", W);
+  if (!spins) return fail(RTT_E_ARG, "spins is null");
+  if (n_sweeps < 0) return fail(RTT_E_ARG, "n_sweeps = %d < 0", n_sweeps);
+  rttk::ChainArgs ca{};
+  ca.cores = h->d_fwd;
+  ca.core_exp = h->dtype == RTT_FP8_E4M3 ? h->d_cexp : nullptr;
+  ca.pi = h->d_pi; ca.order = h->d_order; ca.first = h->d_first; ca.coeffs = h->d_coeffs;
+  ca.T = h->T; ca.L = h->L; ca.N = h->N; ca.nw = h->nw; ca.W = W;
+  ca.spins = spins; ca.logabs = logabs; ca.sign = sign; ca.accepts = accepts; ca.status = status;
+  ca.seed = seed; ca.rstream = rstream; ca.sweep0 = sweep0; ca.n_sweeps = n_sweeps; ca.mode = mode;
+  return dispatch<ChainL>(h->dtype, h->chi, ca, (hipStream_t)stream);
+}
+
+rtt_status rtt_amplitudes(rtt_t h, int32_t W, const uint64_t* spins, double* logabs, int8_t* sign,
+                          void* stream) {
+  g_err.clear();
+  return chain_common(h, W, const_cast<uint64_t*>(spins), logabs, sign, 0, 0, 0, 0, nullptr, nullptr, 0,
+                      stream);
+}
+
+rtt_status rtt_mcmc_sweep(rtt_t h, int32_t W, uint64_t* spins, double* logabs, int8_t* sign, uint64_t seed,
+                          uint64_t rng_stream, uint64_t sweep0, int32_t n_sweeps, uint32_t* accepts,
+                          int32_t* status, void* stream) {
+  g_err.clear();
+  return chain_common(h, W, spins, logabs, sign, seed, rng_stream, sweep0, n_sweeps, accepts, status, 1,
+                      stream);
+}
+
+rtt_status rtt_energy_reduce(int32_t n, const double* x, double* out, void* stream) {
+  g_err.clear();
+  if (n < 0 || (n > 0 && !x) || !out) return fail(RTT_E_ARG, "rtt_energy_reduce: bad argument");
+  hipLaunchKernelGGL(rttk::reduce_kernel, dim3(1), dim3(256), 0, (hipStream_t)stream, n, x, out);
+  HIPX(hipGetLastError());
+  return RTT_OK;
+}
+
+}  // extern "C"

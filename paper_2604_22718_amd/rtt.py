@@ -1,0 +1,214 @@
+"""Python binding of librtt: argument marshalling only.
+
+Functions carry the names of the C entry points (include/rtt.h) and take
+torch tensors for device memory; the current torch stream is passed as the
+HIP stream.  Every computation runs in the library's HIP kernels.  Spin
+configurations are int64 tensors [W, ceil(N/64)] holding the uint64 words.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from ._lib import check, lib
+
+DTYPES = {"f32": 1, "bf16": 2, "fp8": 3}
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous CUDA tensors"
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+# ---------------------------------------------------------------- C entry points
+def rtt_create(n_spins, pi, bond, cores_flat, dtype="f32"):
+    pi = np.ascontiguousarray(pi, dtype=np.int32)
+    bond = np.ascontiguousarray(bond, dtype=np.int32)
+    cores_flat = np.ascontiguousarray(cores_flat, dtype=np.float64)
+    h = C.c_void_p()
+    check(lib().rtt_create(int(n_spins), len(pi), pi.ctypes.data, bond.ctypes.data,
+                           cores_flat.ctypes.data, DTYPES[dtype], C.byref(h)))
+    return h
+
+
+def rtt_lincomb(handles, coeffs):
+    arr = (C.c_void_p * len(handles))(*[h.value for h in handles])
+    co = np.ascontiguousarray(coeffs, dtype=np.float64)
+    h = C.c_void_p()
+    check(lib().rtt_lincomb(len(handles), C.cast(arr, C.c_void_p), co.ctypes.data, C.byref(h)))
+    return h
+
+
+def rtt_destroy(h):
+    check(lib().rtt_destroy(h))
+
+
+def rtt_info(h):
+    info = np.zeros(8, dtype=np.int32)
+    check(lib().rtt_info(h, info.ctypes.data))
+    return dict(zip(["N", "L", "chi", "dtype", "terms", "nw", "cut", "nslot"], info.tolist()))
+
+
+def rtt_get_cores(h, term, size):
+    out = np.zeros(size, dtype=np.float64)
+    check(lib().rtt_get_cores(h, int(term), out.ctypes.data))
+    return out
+
+
+def rtt_tfim_create(Lx, Ly, periodic, J, h):
+    H = C.c_void_p()
+    check(lib().rtt_tfim_create(int(Lx), int(Ly), int(bool(periodic)), float(J), float(h), C.byref(H)))
+    return H
+
+
+def rtt_tfim_destroy(H):
+    check(lib().rtt_tfim_destroy(H))
+
+
+def rtt_evaluate(h, ham, spins, logabs=None, sign=None, logratio=None, rsign=None, eloc=None,
+                 status=None):
+    check(lib().rtt_evaluate(h, ham, spins.shape[0], _ptr(spins), _ptr(logabs), _ptr(sign),
+                             _ptr(logratio), _ptr(rsign), _ptr(eloc), _ptr(status), _stream()))
+
+
+def rtt_amplitudes(h, spins, logabs, sign):
+    check(lib().rtt_amplitudes(h, spins.shape[0], _ptr(spins), _ptr(logabs), _ptr(sign), _stream()))
+
+
+def rtt_flip_ratios(h, spins, logratio, rsign):
+    check(lib().rtt_flip_ratios(h, spins.shape[0], _ptr(spins), _ptr(logratio), _ptr(rsign), _stream()))
+
+
+def rtt_local_energy(h, ham, spins, eloc):
+    check(lib().rtt_local_energy(h, ham, spins.shape[0], _ptr(spins), _ptr(eloc), _stream()))
+
+
+def rtt_mcmc_sweep(h, spins, seed, rng_stream, sweep0, n_sweeps, logabs=None, sign=None,
+                   accepts=None, status=None):
+    check(lib().rtt_mcmc_sweep(h, spins.shape[0], _ptr(spins), _ptr(logabs), _ptr(sign),
+                               int(seed), int(rng_stream), int(sweep0), int(n_sweeps),
+                               _ptr(accepts), _ptr(status), _stream()))
+
+
+def rtt_energy_reduce(x, out):
+    check(lib().rtt_energy_reduce(x.numel(), _ptr(x), _ptr(out), _stream()))
+
+
+# ---------------------------------------------------------------- convenience
+class TFIM:
+    """H = J sum_<ij> Z_i Z_j - h sum_i X_i on an Lx x Ly lattice."""
+
+    def __init__(self, Lx, Ly, J=1.0, h=3.04, periodic=True):
+        self.Lx, self.Ly, self.J, self.h, self.periodic = Lx, Ly, J, h, periodic
+        self.handle = rtt_tfim_create(Lx, Ly, periodic, J, h)
+
+    def close(self):
+        if self.handle is not None:
+            rtt_tfim_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class RTT:
+    """An RTT (or a linear combination of RTTs) resident on the GPU."""
+
+    def __init__(self, pi, cores=None, dtype="f32", _handle=None, _n_spins=None):
+        self.pi = np.asarray(pi, dtype=np.int32)
+        if _handle is not None:
+            self.handle = _handle
+        else:
+            bond = [cores[0].shape[1]] + [c.shape[2] for c in cores]
+            flat = np.concatenate([np.ascontiguousarray(c, dtype=np.float64).ravel() for c in cores])
+            n = int(self.pi.max()) + 1 if _n_spins is None else _n_spins
+            self.handle = rtt_create(n, self.pi, bond, flat, dtype)
+        self.info = rtt_info(self.handle)
+        self.N = self.info["N"]
+        self.nw = self.info["nw"]
+        self.dtype = dtype
+
+    @classmethod
+    def create(cls, n_spins, pi, cores, dtype="f32"):
+        return cls(pi, cores, dtype, _n_spins=n_spins)
+
+    @classmethod
+    def lincomb(cls, terms, coeffs):
+        h = rtt_lincomb([t.handle for t in terms], coeffs)
+        return cls(terms[0].pi, _handle=h, dtype=terms[0].dtype)
+
+    def close(self):
+        if self.handle is not None:
+            rtt_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def core_values(self, bond, term=0):
+        size = int(sum(2 * bond[k] * bond[k + 1] for k in range(len(bond) - 1)))
+        return rtt_get_cores(self.handle, term, size)
+
+    # ---- evaluation
+    def evaluate(self, spins, ham=None, ratios=True, energy=True):
+        W, dev = spins.shape[0], spins.device
+        out = {
+            "logabs": torch.empty(W, dtype=torch.float64, device=dev),
+            "sign": torch.empty(W, dtype=torch.int8, device=dev),
+            "status": torch.empty(W, dtype=torch.int32, device=dev),
+        }
+        if ratios:
+            out["logratio"] = torch.empty(W, self.N, dtype=torch.float64, device=dev)
+            out["rsign"] = torch.empty(W, self.N, dtype=torch.int8, device=dev)
+        if energy and ham is not None:
+            out["eloc"] = torch.empty(W, dtype=torch.float64, device=dev)
+        rtt_evaluate(self.handle, ham.handle if ham is not None else None, spins,
+                     out["logabs"], out["sign"], out.get("logratio"), out.get("rsign"),
+                     out.get("eloc"), out["status"])
+        return out
+
+    def amplitudes(self, spins):
+        W, dev = spins.shape[0], spins.device
+        la = torch.empty(W, dtype=torch.float64, device=dev)
+        sg = torch.empty(W, dtype=torch.int8, device=dev)
+        rtt_amplitudes(self.handle, spins, la, sg)
+        return la, sg
+
+    def local_energy(self, spins, ham):
+        e = torch.empty(spins.shape[0], dtype=torch.float64, device=spins.device)
+        rtt_local_energy(self.handle, ham.handle, spins, e)
+        return e
+
+    def sweep(self, spins, seed, rng_stream=0, sweep0=0, n_sweeps=1, accepts=None, status=None,
+              logabs=None, sign=None):
+        rtt_mcmc_sweep(self.handle, spins, seed, rng_stream, sweep0, n_sweeps, logabs, sign,
+                       accepts, status)
+
+
+def energy_reduce(x):
+    out = torch.empty(3, dtype=torch.float64, device=x.device)
+    rtt_energy_reduce(x, out)
+    return out
+
+
+def spins_to_device(bits_uint64: np.ndarray, device="cuda"):
+    """uint64 numpy words -> int64 device tensor with the same bits."""
+    return torch.from_numpy(np.ascontiguousarray(bits_uint64).view(np.int64)).to(device)
+
+
+def spins_to_host(t) -> np.ndarray:
+    return t.cpu().numpy().view(np.uint64)

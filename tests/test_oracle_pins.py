@@ -149,6 +149,30 @@ def test_flip_ratio_properties():
         assert np.allclose(r[:, j] * rj_back, 1.0, rtol=1e-12)
 
 
+def test_condition_number_bounds():
+    """kappa >= 1 always (Cauchy-Schwarz), = 1 for chi = 1 product states,
+    and = sum |l_c r_c| / |psi| ... bounded below by that at every bond."""
+    pi = wl.path_site_plus_perms(6, 2, 5)
+    S = rtt.all_configs(6)
+    k1 = rtt.condition_numbers(rand_cores(wl.open_bonds(12, 1), 3), pi, S)
+    assert np.allclose(k1, 1.0)
+    cores = rand_cores(wl.open_bonds(12, 4), 4)
+    k = rtt.condition_numbers(cores, pi, S)
+    assert np.all(k >= 1.0 - 1e-12)
+    # at the middle bond, ||l|| ||r|| >= |l . r| computed independently
+    s = S[9]
+    l = np.ones((1, 1))
+    for q in range(6):
+        l = l @ cores[q][s[pi[q]]]
+    r = np.ones((1, 1))
+    for q in reversed(range(6, 12)):
+        r = cores[q][s[pi[q]]] @ r
+    mid = np.linalg.norm(l) * np.linalg.norm(r) / abs((l @ r)[0, 0])
+    assert k[9] >= mid - 1e-12 and mid >= 1.0
+    kf = rtt.flip_condition_numbers(cores, pi, S[:5])
+    assert kf.shape == (5, 6) and np.all(kf >= k[:5, None] - 1e-12)
+
+
 # ---------------------------------------------------------------- lattice / H
 def test_bonds_structure():
     b = tfim.bonds(4, 4, True)
