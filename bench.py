@@ -1,0 +1,251 @@
+#!/usr/bin/env python3
+"""Throughput of the RTT Monte Carlo hot path on one MI355X.
+
+One step = one single-spin-flip Metropolis sweep of every walker + local
+energies (all N flip ratios + diagonal) of every walker + the compensated
+FP64 energy reduction, on the 8x8 periodic TFIM workload (N = 64, R = 2,
+L = 128, chi = 64, 4096 walkers, h = 3.04; synthetic Gaussian cores).
+
+Prints one JSON line.  value = local-energy evaluations per second over the
+whole timed region (walkers x steps / time), inputs resident in HBM.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"f32": 157.3e12, "bf16": 2.5e15, "fp8": 2.5e15}  # dense MFMA FLOP/s (fp8 cores run as bf16)
+HBM_PEAK = 8.0e12
+METRIC = "local-energy evals/s & effective samples/s at fixed energy error vs FP64"
+
+
+def schedule_rowsteps(pi, N, L, cut):
+    """Useful row-vector x core products of the flip-ratio passes per walker:
+    forward over positions [0, cut) and backward over [cut, L), each step
+    advancing the base vector and every spawned flipped vector."""
+    fwd, seen = 0, set()
+    for k in range(cut):
+        seen.add(int(pi[k]))
+        fwd += 1 + len(seen)
+    bwd, seen = 0, set()
+    for k in range(L - 1, cut - 1, -1):
+        seen.add(int(pi[k]))
+        bwd += 1 + len(seen)
+    return fwd, bwd
+
+
+def sweep_rowsteps(pi, N, L):
+    """Row-vector x core products of one sweep per walker: the amplitude pass
+    (L) plus, for each proposal, the flipped row from its first position to
+    the end of the train."""
+    first = {}
+    for k, j in enumerate(pi):
+        first.setdefault(int(j), k)
+    return L + sum(L - f for f in first.values())
+
+
+def src_hash():
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2604_22718_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(kernel, workload):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current kernel sources; else None."""
+    p = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(p):
+        return None
+    d = json.load(open(p))
+    if d.get("src_hash") != src_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(w, n_walkers, n_steps):
+    """The FP64 oracle on the host, single-threaded BLAS: the same step on a
+    sample of the workload's walkers."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import mcmc, rtt as orc, tfim
+    pi, cores = w.pi(), w.cores()
+    bits = w.spins(n_walkers)
+    bonds = tfim.bonds(w.Lx, w.Ly)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        s = bits
+        for t in range(n_steps):
+            s, _, _ = mcmc.metropolis(cores, pi, s, seed=w.chain_seed, stream=0, sweep0=t, n_sweeps=1)
+            el = orc.local_energy(cores, pi, s, bonds, w.J, w.h)
+        dt = time.perf_counter() - t0
+    return {"value": n_walkers * n_steps / dt, "unit": "local-energy evals/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{n_walkers} walkers x {n_steps} steps (sweep + local energies) of the same "
+                      f"8x8 chi=64 workload, FP64 numpy, 1 BLAS thread, {dt:.1f} s",
+            "host_cpus_available": len(os.sched_getaffinity(0))}
+
+
+def run(dtype, steps, warmup, with_cpu):
+    import torch
+
+    from paper_2604_22718_amd import rtt as R
+    from paper_2604_22718_amd import workloads as wl
+    from oracle import rtt as orc, stats, tfim
+
+    w = wl.MEDIUM_8x8
+    pi, bond, cores = w.pi(), w.bond(), w.cores()
+    psi = R.RTT.create(w.N, pi, cores, dtype)
+    ham = R.TFIM(w.Lx, w.Ly, w.J, w.h)
+    bits = w.spins()
+    spins = R.spins_to_device(wl.pack_spins(bits))
+    W, N, L, chi = w.W, w.N, w.L, w.chi
+
+    # energy error vs FP64 on the seeded configurations (sample of walkers)
+    idx = np.array([0, 1, 2, 3, 1000, 2000, 3000, 4095])
+    e_gpu = psi.local_energy(spins, ham).cpu().numpy()[idx]
+    from oracle import quant
+    qc = quant.quantise_cores(cores, dtype)
+    e_ref = orc.local_energy(qc, pi, bits[idx], tfim.bonds(w.Lx, w.Ly), w.J, w.h)
+    e_ref_unq = orc.local_energy(cores, pi, bits[idx], tfim.bonds(w.Lx, w.Ly), w.J, w.h)
+    err = {
+        "eloc_max_rel_vs_fp64_same_cores": float(np.max(np.abs(e_gpu - e_ref) / np.abs(e_ref))),
+        "eloc_median_rel_vs_fp64_same_cores": float(np.median(np.abs(e_gpu - e_ref) / np.abs(e_ref))),
+        "eloc_max_rel_vs_fp64_unquantised_cores": float(np.max(np.abs(e_gpu - e_ref_unq) / np.abs(e_ref_unq))),
+        "sample_walkers": idx.tolist(),
+    }
+
+    eloc = torch.empty(W, dtype=torch.float64, device="cuda")
+    red = torch.empty(3, dtype=torch.float64, device="cuda")
+    acc = torch.zeros(W, dtype=torch.int32, device="cuda")
+    series = []
+
+    def step(t, ev=None):
+        if ev: ev[0].record()
+        psi.sweep(spins, seed=w.chain_seed, sweep0=t, n_sweeps=1, accepts=acc)
+        if ev: ev[1].record()
+        R.rtt_evaluate(psi.handle, ham.handle, spins, eloc=eloc)
+        if ev: ev[2].record()
+        R.rtt_energy_reduce(eloc, red)
+        if ev: ev[3].record()
+        series.append(red.clone())
+
+    for t in range(warmup):
+        step(t)
+    torch.cuda.synchronize()
+    series.clear()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in range(steps):
+        step(warmup + t, evs[t])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    sweep_ms = np.array([e[0].elapsed_time(e[1]) for e in evs])
+    eval_ms = np.array([e[1].elapsed_time(e[2]) for e in evs])
+    red_ms = np.array([e[2].elapsed_time(e[3]) for e in evs])
+
+    sums = torch.stack(series).cpu().numpy()          # (steps, 3)
+    means = sums[:, 0] / sums[:, 2]
+    var = float(np.mean(sums[:, 1] / sums[:, 2] - means ** 2))
+    tau = stats_tau(means)
+    energy = float(np.mean(means))
+    ess = W * steps / tau
+
+    info = R.rtt_info(psi.handle)
+    fwd, bwd = schedule_rowsteps(pi, N, L, info["cut"])
+    flops_row = 2.0 * chi * chi
+    le_flops = W * (fwd + bwd) * flops_row
+    sw_flops = W * sweep_rowsteps(pi, N, L) * flops_row
+    kernels = {
+        "chain_kernel (1 sweep)": {"ms": float(sweep_ms.mean()), "algorithmic_flops": sw_flops,
+                                   "tflops": sw_flops / (sweep_ms.mean() * 1e-3) / 1e12},
+        "pass_kernel x2 + combine (local energies)": {"ms": float(eval_ms.mean()),
+                                                      "algorithmic_flops": le_flops,
+                                                      "tflops": le_flops / (eval_ms.mean() * 1e-3) / 1e12},
+        "reduce_kernel": {"ms": float(red_ms.mean())},
+    }
+    dom = "chain_kernel" if sweep_ms.mean() >= eval_ms.mean() else "evaluate"
+    if dom == "chain_kernel":
+        ach, nm = sw_flops / (sweep_ms.mean() * 1e-3), "chain_kernel"
+    else:
+        ach, nm = le_flops / (eval_ms.mean() * 1e-3), "pass_kernel+combine"
+    roof = {"kernel": nm, "bound": "mfma", "achieved": ach / 1e12, "peak": PEAK[dtype] / 1e12,
+            "unit": "TFLOP/s", "frac": ach / PEAK[dtype],
+            "traffic": traffic_from_profile(nm, w.name)}
+    res = {
+        "metric": METRIC, "value": W * steps / dt, "unit": "local-energy evals/s",
+        "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": dt / steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+        "data": "synthetic",
+        "config": {"workload": w.name, "lattice": f"{w.Lx}x{w.Ly} periodic TFIM", "J": w.J, "h": w.h,
+                   "R": w.R, "L": L, "chi": chi, "walkers": W,
+                   "step": "1 Metropolis sweep + local energies of all walkers + FP64 reduction"},
+        "effective_samples_per_s": ess / dt, "tau_int_steps": tau,
+        "energy_per_site": energy / N, "var_eloc": var,
+        "acceptance": float(acc.sum().item()) / (W * N * (steps + warmup)),
+        "energy_error": err,
+        "kernels": kernels,
+        "roofline": roof,
+    }
+    psi.close()
+    ham.close()
+    return res
+
+
+def stats_tau(x):
+    """Integrated autocorrelation time of a 1-D series (Sokal window, c = 5)."""
+    x = np.asarray(x, dtype=np.float64)
+    n = len(x)
+    if n < 4:
+        return 1.0
+    d = x - x.mean()
+    c0 = np.mean(d * d)
+    if c0 == 0:
+        return 1.0
+    tau = 1.0
+    for M in range(1, n):
+        tau += 2.0 * np.mean(d[: n - M] * d[M:]) / c0
+        if M >= 5 * tau:
+            break
+    return max(tau, 1.0)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--dtype", default="f32", choices=["f32", "bf16", "fp8"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--also", default="bf16", help="second precision reported alongside ('' for none)")
+    a = ap.parse_args()
+    if a.gpus != 1:
+        print(f"bench.py measures one GPU only: this build has no multi-GPU path (asked for {a.gpus}).",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    res = run(a.dtype, a.steps, a.warmup, not a.no_cpu)
+    if a.also and a.also != a.dtype:
+        other = run(a.also, a.steps, a.warmup, False)
+        res["also"] = {k: other[k] for k in ("dtype", "value", "ms_per_step", "effective_samples_per_s",
+                                             "energy_error", "kernels", "roofline")}
+    if not a.no_cpu:
+        from paper_2604_22718_amd import workloads as wl
+        res["cpu_baseline"] = cpu_baseline(wl.MEDIUM_8x8, 64, 8)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

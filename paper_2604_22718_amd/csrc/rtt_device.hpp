@@ -33,47 +33,97 @@ __device__ __forceinline__ float bf16_to_f32(uint16_t h) {
 }
 
 // ---------------------------------------------------------------- dtype traits
-// Storage element of packed cores, elements per lane per row (KPL = chi/4),
-// and the K-loop of one 16x16 output tile.
+// Storage element of packed cores and the K-loop of one 16x16 output tile.
+// prep() turns a lane's KPL FP32 activations into MFMA B operands once;
+// mma() / mma2() run the K loop for one (or two, interleaved) core slices.
 struct DF32 {
   using elem = float;
-  static constexpr int kStep = 1;  // K values per lane per MFMA
   template <int KPL>
-  __device__ __forceinline__ static f4 tile(const float (&a)[KPL], const float (&b)[KPL], f4 acc) {
+  struct BOp { float v[KPL]; };
+  template <int KPL>
+  __device__ __forceinline__ static void prep(const float (&x)[KPL], BOp<KPL>& b) {
+#pragma unroll
+    for (int c = 0; c < KPL; ++c) b.v[c] = x[c];
+  }
+  template <int KPL>
+  __device__ __forceinline__ static f4 mma(const float (&a)[KPL], const BOp<KPL>& b, f4 acc) {
 #pragma unroll
     for (int c = 0; c < KPL; ++c)
-      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[c], b[c], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[c], b.v[c], acc, 0, 0, 0);
     return acc;
+  }
+  template <int KPL>
+  __device__ __forceinline__ static void mma2(const float (&a0)[KPL], const float (&a1)[KPL],
+                                              const BOp<KPL>& b, f4& c0, f4& c1) {
+#pragma unroll
+    for (int c = 0; c < KPL; ++c) {
+      c0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0[c], b.v[c], c0, 0, 0, 0);
+      c1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1[c], b.v[c], c1, 0, 0, 0);
+    }
   }
   __device__ __forceinline__ static float to_f32(float x) { return x; }
 };
 
+// BF16 cores.  FP32 activations enter the matrix cores as a hi + lo BF16
+// pair (two MFMAs), so each product keeps ~16 significant activation bits.
 struct DBF16 {
   using elem = uint16_t;
-  static constexpr int kStep = 8;
-  // b holds FP32 activations; they enter the matrix core as hi + lo BF16 so
-  // the product keeps ~16 significant bits of the activation.
   template <int KPL>
-  __device__ __forceinline__ static f4 tile(const uint16_t (&a)[KPL], const float (&b)[KPL], f4 acc) {
+  struct BOp { bf16x8 hi[KPL / 8], lo[KPL / 8]; };
+  template <int KPL>
+  __device__ __forceinline__ static void prep(const float (&x)[KPL], BOp<KPL>& b) {
 #pragma unroll
     for (int c = 0; c < KPL / 8; ++c) {
-      u16x8 av, hi, lo;
+      bf16x8 hi, lo;
 #pragma unroll
       for (int i = 0; i < 8; ++i) {
-        av[i] = a[8 * c + i];
-        uint16_t h = f32_to_bf16_rne(b[8 * c + i]);
+        const __bf16 h = (__bf16)x[8 * c + i];  // round to nearest even
         hi[i] = h;
-        lo[i] = f32_to_bf16_rne(b[8 * c + i] - bf16_to_f32(h));
+        lo[i] = (__bf16)(x[8 * c + i] - (float)h);
       }
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av),
-                                                    __builtin_bit_cast(bf16x8, hi), acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, av),
-                                                    __builtin_bit_cast(bf16x8, lo), acc, 0, 0, 0);
+      b.hi[c] = hi;
+      b.lo[c] = lo;
+    }
+  }
+  template <int KPL>
+  __device__ __forceinline__ static bf16x8 pack(const uint16_t (&a)[KPL], int c) {
+    u16x8 av;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) av[i] = a[8 * c + i];
+    return __builtin_bit_cast(bf16x8, av);
+  }
+  template <int KPL>
+  __device__ __forceinline__ static f4 mma(const uint16_t (&a)[KPL], const BOp<KPL>& b, f4 acc) {
+#pragma unroll
+    for (int c = 0; c < KPL / 8; ++c) {
+      const bf16x8 av = pack<KPL>(a, c);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b.hi[c], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b.lo[c], acc, 0, 0, 0);
     }
     return acc;
   }
+  template <int KPL>
+  __device__ __forceinline__ static void mma2(const uint16_t (&a0)[KPL], const uint16_t (&a1)[KPL],
+                                              const BOp<KPL>& b, f4& c0, f4& c1) {
+#pragma unroll
+    for (int c = 0; c < KPL / 8; ++c) {
+      const bf16x8 x0 = pack<KPL>(a0, c), x1 = pack<KPL>(a1, c);
+      c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x0, b.hi[c], c0, 0, 0, 0);
+      c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x1, b.hi[c], c1, 0, 0, 0);
+      c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x0, b.lo[c], c0, 0, 0, 0);
+      c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x1, b.lo[c], c1, 0, 0, 0);
+    }
+  }
   __device__ __forceinline__ static float to_f32(uint16_t x) { return bf16_to_f32(x); }
 };
+
+// Workgroup barrier that orders LDS only: global loads issued before it
+// (prefetched core fragments) stay in flight across it.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
 
 // Load a lane's KPL-element fragment (contiguous, 16-byte aligned).
 template <int KPL>
@@ -111,16 +161,34 @@ __device__ __forceinline__ void lds_read(float (&dst)[KPL], const float* src) {
   }
 }
 
-// Max |x| over a row held by the four K-groups of a wave (lanes m, m+16,
-// m+32, m+48), then the power-of-two exponent e with max * 2^-e in [0.5, 1).
-// Scaling by 2^-e is exact, so renormalisation adds no rounding.
+// Reductions over the four K-groups of a wave (lanes m, m+16, m+32, m+48)
+// with the gfx950 lane-swap instructions (no LDS crossbar round trip).
+__device__ __forceinline__ float group_max(float x) {
+  const unsigned u = __float_as_uint(x);
+  auto a = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+  x = fmaxf(__uint_as_float(a[0]), __uint_as_float(a[1]));
+  const unsigned v = __float_as_uint(x);
+  auto b = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+  return fmaxf(__uint_as_float(b[0]), __uint_as_float(b[1]));
+}
+__device__ __forceinline__ float group_sum(float x) {
+  const unsigned u = __float_as_uint(x);
+  auto a = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+  x = __uint_as_float(a[0]) + __uint_as_float(a[1]);
+  const unsigned v = __float_as_uint(x);
+  auto b = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+  return __uint_as_float(b[0]) + __uint_as_float(b[1]);
+}
+
+// Max |x| over a row held by the four K-groups, then the power-of-two
+// exponent e with max * 2^-e in [0.5, 1).  Scaling by 2^-e is exact, so
+// renormalisation adds no rounding.
 template <int KPL>
 __device__ __forceinline__ int renorm_row(float (&v)[KPL]) {
   float mx = 0.f;
 #pragma unroll
   for (int c = 0; c < KPL; ++c) mx = fmaxf(mx, fabsf(v[c]));
-  mx = fmaxf(mx, __shfl_xor(mx, 16));
-  mx = fmaxf(mx, __shfl_xor(mx, 32));
+  mx = group_max(mx);
   int e = (mx > 0.f) ? __builtin_amdgcn_frexp_expf(mx) : 0;
 #pragma unroll
   for (int c = 0; c < KPL; ++c) v[c] = __builtin_amdgcn_ldexpf(v[c], -e);

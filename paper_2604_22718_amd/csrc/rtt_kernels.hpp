@@ -82,19 +82,23 @@ __global__ void __launch_bounds__(256) pass_kernel(PassArgs a) {
   const E* cores = static_cast<const E*>(a.cores) + (size_t)term * a.L * 2 * CHI * CHI;
   const int* cexp_p = a.core_exp ? a.core_exp + (size_t)term * a.L : nullptr;
 
-  for (int s = 0; s < a.n_steps; ++s) {
+  // work items = (schedule step, output tile of this wave); the core
+  // fragments of item i+1 are loaded while item i computes
+  struct Frags { E m[KPL]; E o[KPL]; };
+  const int n_items = a.n_steps * MT;
+  auto load = [&](Frags& F, int item) {
+    const int s = item / MT, mt = item % MT;
     const int4 st = a.sched[s];
-    const int k = st.x, q = st.y, nact = st.z, odd = st.w;
-    const int bit = spin_bit(spw, q);
-    const E* Am = cores + ((size_t)k * 2 + bit) * (CHI * CHI) + (size_t)lane * KPL;
-    const E* Ao = cores + ((size_t)k * 2 + (bit ^ 1)) * (CHI * CHI) + (size_t)lane * KPL;
-    E fm[MT][KPL], fo[MT][KPL];
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
-      const int t = wv * MT + mt;
-      load_frag<KPL>(fm[mt], Am + (size_t)t * 64 * KPL);
-      load_frag<KPL>(fo[mt], Ao + (size_t)t * 64 * KPL);
-    }
+    const int bit = spin_bit(spw, st.y);
+    const size_t tile = ((size_t)(wv * MT + mt) * 64 + lane) * KPL;
+    load_frag<KPL>(F.m, cores + ((size_t)st.x * 2 + bit) * (CHI * CHI) + tile);
+    load_frag<KPL>(F.o, cores + ((size_t)st.x * 2 + (bit ^ 1)) * (CHI * CHI) + tile);
+  };
+  auto compute = [&](const Frags& F, int item) {
+    const int s = item / MT, mt = item % MT;
+    const int4 st = a.sched[s];
+    const int k = st.x, nact = st.z, odd = st.w;
+    const int t = wv * MT + mt;
     const int cexp = cexp_p ? cexp_p[k] : 0;
     const int ntile = (nact + 15) >> 4;
     for (int r = 0; r < ntile; ++r) {
@@ -102,37 +106,47 @@ __global__ void __launch_bounds__(256) pass_kernel(PassArgs a) {
       float v[KPL];
       lds_read<KPL>(v, cur + row * RS + g * KPL);
       const int e = renorm_row<KPL>(v);
-      if (wv == 0 && g == 0) exn[row] = exc[row] + e + cexp;
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        const int t = wv * MT + mt;
-        f4 acc = {0.f, 0.f, 0.f, 0.f};
-        acc = D::template tile<KPL>(fm[mt], v, acc);
-        *reinterpret_cast<float4*>(nxt + row * RS + 16 * t + 4 * g) =
-            make_float4(acc[0], acc[1], acc[2], acc[3]);
-      }
+      if (mt == 0 && wv == 0 && g == 0) exn[row] = exc[row] + e + cexp;
+      typename D::template BOp<KPL> bo;
+      D::template prep<KPL>(v, bo);
+      f4 acc = {0.f, 0.f, 0.f, 0.f};
+      acc = D::template mma<KPL>(F.m, bo, acc);
+      *reinterpret_cast<float4*>(nxt + row * RS + 16 * t + 4 * g) =
+          make_float4(acc[0], acc[1], acc[2], acc[3]);
     }
     {  // odd row on the vector ALUs: out[16t+m] = sum_k A[1-s][k][16t+m] in[k]
       const int oin = odd & 0xffff, oout = odd >> 16;
       float v[KPL];
       lds_read<KPL>(v, cur + oin * RS + g * KPL);
       const int e = renorm_row<KPL>(v);
+      float p = 0.f;
 #pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        const int t = wv * MT + mt;
-        float p = 0.f;
-#pragma unroll
-        for (int c = 0; c < KPL; ++c) p = fmaf(D::to_f32(fo[mt][c]), v[c], p);
-        p += __shfl_xor(p, 16);
-        p += __shfl_xor(p, 32);
-        if (g == 0) nxt[oout * RS + 16 * t + m] = p;
-      }
-      if (wv == 0 && lane == 0) exn[oout] = exc[oin] + e + cexp;
+      for (int c = 0; c < KPL; ++c) p = fmaf(D::to_f32(F.o[c]), v[c], p);
+      p += __shfl_xor(p, 16);
+      p += __shfl_xor(p, 32);
+      if (g == 0) nxt[oout * RS + 16 * t + m] = p;
+      if (mt == 0 && wv == 0 && lane == 0) exn[oout] = exc[oin] + e + cexp;
     }
-    __syncthreads();
-    float* tp = cur; cur = nxt; nxt = tp;
-    int* te = exc; exc = exn; exn = te;
+    if (mt == MT - 1) {
+      lds_barrier();
+      float* tp = cur; cur = nxt; nxt = tp;
+      int* te = exc; exc = exn; exn = te;
+    }
+  };
+  // prefetch on every path (clamped to the last item) so that the wait
+  // before the matrix ops never covers the item being prefetched
+  Frags FA, FB;
+  if (n_items > 0) {
+    load(FA, 0);
+    for (int i = 0; i < n_items; i += 2) {
+      load(FB, min(i + 1, n_items - 1));
+      compute(FA, i);
+      if (i + 1 >= n_items) break;
+      load(FA, min(i + 2, n_items - 1));
+      compute(FB, i + 1);
+    }
   }
+  __syncthreads();
 
   if (w_raw < a.W) {
     float* ov = a.out_vec + (((size_t)term * a.W + w) * nslot) * CHI;
@@ -249,145 +263,177 @@ __global__ void __launch_bounds__(256) combine_kernel(CombineArgs a) {
 // chain kernel: 16 walkers per block, amplitudes and Metropolis sweeps
 // ============================================================================
 struct ChainArgs {
-  const void* cores;        // [T][L][2][CHI*CHI] forward fragment layout
-  const int32_t* core_exp;  // [T][L] or null
-  const int32_t* pi;        // [L]
-  const int32_t* order;     // [N] proposal order
-  const int32_t* first;     // [N] first position of spin j, -1 if none
-  const double* coeffs;     // [T]
-  int T, L, N, nw, W;
+  const void* cores;         // [T][L][2][CHI*CHI] forward fragment layout (prescaled)
+  const int32_t* cesum;      // [T][L+1] prefix sums of the per-position scale exponents
+  const int32_t* pi;         // [L]
+  const uint64_t* rmask;     // [N][LW] bit k set iff position k reads spin j
+  const int32_t* order;      // [N] proposal order
+  const int32_t* first;      // [N] first position of spin j, -1 if none
+  const double* coeffs;      // [T]
+  int T, L, N, nw, LW, W;
   uint64_t* spins;
   double* logabs; int8_t* sign; uint32_t* accepts; int32_t* status;
   uint64_t seed, rstream, sweep0;
   int n_sweeps;
-  int mode;                 // 0: amplitudes only, 1: sweeps
+  int mode;                  // 0: amplitudes only, 1: sweeps
 };
 
-template <int CHI>
-struct ChainLds {
-  // per term: 5 row buffers (P prefix, U unflipped first step, F flipped
-  // first step, X/Y ping-pong) of 16 rows, and 5 x 16 exponents
-  static constexpr int kBufs = 5;
-  static constexpr int rows_floats() { return kBufs * 16 * Geo<CHI>::RS; }
-};
+constexpr int kRenormEvery = 4;  // steps between power-of-two renormalisations
 
-// One step for all 16 walkers (columns) of one term: both slices are applied
-// and each column keeps the slice of its own walker.  out2 (optional)
-// receives the other slice's product.
-template <class D, int CHI>
-__device__ __forceinline__ void chain_step(const typename D::elem* A0, const typename D::elem* A1,
-                                           int cexp, const float* in, const int* ein, float* out,
-                                           int* eout, float* out2, int* eout2, int bitn, int wv,
-                                           int lane) {
-  using G = Geo<CHI>;
-  constexpr int MT = G::MT, KPL = G::KPL, RS = G::RS;
-  const int g = lane >> 4, m = lane & 15;
-  float v[KPL];
-  lds_read<KPL>(v, in + m * RS + g * KPL);
-  const int e = renorm_row<KPL>(v);
-#pragma unroll
-  for (int mt = 0; mt < MT; ++mt) {
-    const int t = wv * MT + mt;
-    typename D::elem f0[KPL], f1[KPL];
-    load_frag<KPL>(f0, A0 + ((size_t)t * 64 + lane) * KPL);
-    load_frag<KPL>(f1, A1 + ((size_t)t * 64 + lane) * KPL);
-    f4 z = {0.f, 0.f, 0.f, 0.f};
-    const f4 a0 = D::template tile<KPL>(f0, v, z);
-    const f4 a1 = D::template tile<KPL>(f1, v, z);
-    const f4 sel = bitn ? a1 : a0;
-    *reinterpret_cast<float4*>(out + m * RS + 16 * t + 4 * g) = make_float4(sel[0], sel[1], sel[2], sel[3]);
-    if (out2) {
-      const f4 oth = bitn ? a0 : a1;
-      *reinterpret_cast<float4*>(out2 + m * RS + 16 * t + 4 * g) =
-          make_float4(oth[0], oth[1], oth[2], oth[3]);
-    }
+// Layout of the 16 walkers' state in LDS (offsets in bytes).
+struct ChainLayout {
+  int rows, exps, pm, sp, total;
+  __host__ __device__ ChainLayout(int chi, int T, int LW, int nw) {
+    const int rs = chi + 4;
+    rows = 0;                                   // float [T][5][16][rs]
+    exps = rows + T * 5 * 16 * rs * 4;          // int [3][T][16]: prefix, first step, running
+    pm = exps + 3 * T * 16 * 4;                 // uint64 [16][LW] position bits of the walker
+    pm = (pm + 7) & ~7;
+    sp = pm + 16 * LW * 8;                      // uint64 [16][nw] spins
+    total = sp + 16 * nw * 8;
   }
-  if (wv == 0 && g == 0) {
-    eout[m] = ein[m] + e + cexp;
-    if (eout2) eout2[m] = ein[m] + e + cexp;
-  }
-}
+};
 
 template <class D, int CHI>
 __global__ void __launch_bounds__(64 * Geo<CHI>::WPW) chain_kernel(ChainArgs a) {
   using E = typename D::elem;
   using G = Geo<CHI>;
-  constexpr int RS = G::RS;
+  constexpr int RS = G::RS, MT = G::MT, KPL = G::KPL;
   constexpr int BUF = 16 * RS;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int m = lane & 15;
+  const int g = lane >> 4, m = lane & 15;
   const int nthr = blockDim.x;
-  extern __shared__ __align__(16) float lds[];
-  const int T = a.T;
-  float* rows = lds;                                                  // [T][5][16][RS]
-  int* exps = reinterpret_cast<int*>(lds + T * 5 * BUF);              // [T][5][16]
-  uint64_t* sp = reinterpret_cast<uint64_t*>(exps + T * 5 * 16 + ((T * 5 * 16) & 1));  // [16][nw]
-  double* lab = reinterpret_cast<double*>(sp + 16 * a.nw);            // [16] log|psi|
-  int* sgn = reinterpret_cast<int*>(lab + 16);                        // [16]
-  int* stat = sgn + 16;                                               // [16]
-  int* flag = stat + 16;                                              // [16]
-  uint32_t* acc = reinterpret_cast<uint32_t*>(flag + 16);             // [16]
+  const int T = a.T, L = a.L, LW = a.LW, nw = a.nw;
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  const ChainLayout lay(CHI, T, LW, nw);
+  float* rows = reinterpret_cast<float*>(lds_raw + lay.rows);
+  int* Ep = reinterpret_cast<int*>(lds_raw + lay.exps);   // [T][16] prefix
+  int* Ef = Ep + T * 16;                                   // [T][16] after the first step
+  int* Er = Ef + T * 16;                                   // [T][16] running row
+  uint64_t* pm = reinterpret_cast<uint64_t*>(lds_raw + lay.pm);
+  uint64_t* sp = reinterpret_cast<uint64_t*>(lds_raw + lay.sp);
 
   enum { P = 0, U = 1, F = 2, X = 3, Y = 4 };
   auto buf = [&](int t, int b) { return rows + (t * 5 + b) * BUF; };
-  auto ebuf = [&](int t, int b) { return exps + (t * 5 + b) * 16; };
 
   const int w0 = blockIdx.x * 16;
+  const bool live = (w0 + m) < a.W;
   for (int i = threadIdx.x; i < T * 5 * BUF; i += nthr) rows[i] = 0.f;
-  for (int i = threadIdx.x; i < T * 5 * 16; i += nthr) exps[i] = 0;
-  for (int i = threadIdx.x; i < 16 * a.nw; i += nthr) {
-    const int n = i / a.nw, wd = i % a.nw;
-    sp[i] = (w0 + n < a.W) ? a.spins[(size_t)(w0 + n) * a.nw + wd] : 0ull;
-  }
-  if (threadIdx.x < 16) {
-    acc[threadIdx.x] = 0;
-    stat[threadIdx.x] = 0;
+  for (int i = threadIdx.x; i < 3 * T * 16; i += nthr) Ep[i] = 0;
+  for (int i = threadIdx.x; i < 16 * nw; i += nthr) {
+    const int n = i / nw, wd = i % nw;
+    sp[i] = (w0 + n < a.W) ? a.spins[(size_t)(w0 + n) * nw + wd] : 0ull;
   }
   __syncthreads();
+  for (int i = threadIdx.x; i < 16 * LW; i += nthr) {
+    const int n = i / LW, wd = i % LW;
+    uint64_t word = 0;
+    for (int b = 0; b < 64 && 64 * wd + b < L; ++b) {
+      const int q = a.pi[64 * wd + b];
+      word |= (uint64_t)spin_bit(sp + n * nw, q) << b;
+    }
+    pm[i] = word;
+  }
 
   const E* cores = static_cast<const E*>(a.cores);
-  auto slice = [&](int t, int k, int b) {
-    return cores + (((size_t)t * a.L + k) * 2 + b) * (CHI * CHI);
-  };
-  auto cexp_of = [&](int t, int k) { return a.core_exp ? a.core_exp[(size_t)t * a.L + k] : 0; };
+  const size_t lane_off = (size_t)lane * KPL;
+  struct Frags { E f0[KPL]; E f1[KPL]; };
+  typename D::template BOp<KPL> bo;
 
-  // reset the prefix of every term to the left boundary vector e_0
-  auto reset_prefix = [&]() {
-    for (int i = threadIdx.x; i < T * 16 * RS; i += nthr) {
-      const int t = i / (16 * RS), r = i % (16 * RS);
-      buf(t, P)[r] = (r % RS == 0) ? 1.f : 0.f;
-    }
-    for (int i = threadIdx.x; i < T * 16; i += nthr) ebuf(i / 16, P)[i % 16] = 0;
-  };
-
-  // advance rows in buffer `from` through positions [k0, k1) with spin jflip
-  // flipped; returns the buffer index holding the result (X or Y)
-  auto run = [&](int from, int k0, int k1, int jflip) {
-    int cur = from;
-    for (int k = k0; k < k1; ++k) {
-      const int q = a.pi[k];
-      const int bitn = spin_bit(sp + m * a.nw, q) ^ (q == jflip ? 1 : 0);
-      const int nxt = (cur == X) ? Y : X;
-      for (int t = 0; t < T; ++t)
-        chain_step<D, CHI>(slice(t, k, 0), slice(t, k, 1), cexp_of(t, k), buf(t, cur),
-                           ebuf(t, cur), buf(t, nxt), ebuf(t, nxt), nullptr, nullptr, bitn, wv,
-                           lane);
-      __syncthreads();
-      cur = nxt;
+  // Advance the rows of every term from buffer `from` through positions
+  // [k0, k1) with spin jflip flipped (-1: none).  Work items are (position,
+  // term, output tile) in that order; the two core fragments of the next
+  // item are loaded while the current one computes.  With `split` the first
+  // step stores the walker's own slice product in F and the other slice's
+  // in U.  Rows are renormalised every kRenormEvery steps; the running
+  // exponent sum lives in Er.  Returns the buffer holding the result.
+  auto segment = [&](int from, int k0, int k1, int jflip, bool split) -> int {
+    if (k1 <= k0) return from;
+    int cur = from, out = split ? F : X;
+    int bit = 0;
+    uint64_t word = 0;
+    const uint64_t* rmj = jflip >= 0 ? a.rmask + (size_t)jflip * LW : nullptr;
+    int k = k0, t = 0, mt = 0;
+    auto load = [&](Frags& Fr, int kk, int tt, int mm) {
+      const E* base = cores + (((size_t)tt * L + kk) * 2) * (CHI * CHI) +
+                      (size_t)(wv * MT + mm) * 64 * KPL + lane_off;
+      load_frag<KPL>(Fr.f0, base);
+      load_frag<KPL>(Fr.f1, base + CHI * CHI);
+    };
+    auto step = [&](const Frags& Fr) {
+      if (t == 0 && mt == 0 && (k == k0 || (k & 63) == 0)) {
+        word = pm[m * LW + (k >> 6)] ^ (rmj ? rmj[k >> 6] : 0ull);
+      }
+      if (t == 0 && mt == 0) bit = (int)((word >> (k & 63)) & 1ull);
+      if (mt == 0) {
+        float v[KPL];
+        lds_read<KPL>(v, buf(t, cur) + m * RS + g * KPL);
+        if ((k - k0) % kRenormEvery == 0) {
+          const int e = renorm_row<KPL>(v);
+          if (wv == 0 && g == 0) {
+            if (split && k == k0) {
+              const int ne = Ep[t * 16 + m] + e;
+              Ef[t * 16 + m] = ne;
+              Er[t * 16 + m] = ne;
+            } else {
+              Er[t * 16 + m] = (k == k0 ? Ep[t * 16 + m] : Er[t * 16 + m]) + e;
+            }
+          }
+        }
+        D::template prep<KPL>(v, bo);
+      }
+      f4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
+      D::template mma2<KPL>(Fr.f0, Fr.f1, bo, c0, c1);
+      const int tt = wv * MT + mt;
+      const f4 sel = bit ? c1 : c0;
+      *reinterpret_cast<float4*>(buf(t, out) + m * RS + 16 * tt + 4 * g) =
+          make_float4(sel[0], sel[1], sel[2], sel[3]);
+      if (split && k == k0) {
+        const f4 oth = bit ? c0 : c1;
+        *reinterpret_cast<float4*>(buf(t, U) + m * RS + 16 * tt + 4 * g) =
+            make_float4(oth[0], oth[1], oth[2], oth[3]);
+      }
+      if (mt == MT - 1 && t == T - 1) {
+        lds_barrier();
+        cur = out;
+        out = (cur == X) ? Y : X;
+      }
+      if (++mt == MT) { mt = 0; if (++t == T) { t = 0; ++k; } }
+    };
+    auto next_of = [&](int& kk, int& tt, int& mm) {
+      if (++mm == MT) { mm = 0; if (++tt == T) { tt = 0; ++kk; } }
+    };
+    // The prefetch is issued on every path (past the end it re-reads the
+    // last position) so the number of loads in flight is the same on all
+    // paths and the wait before the matrix ops only covers the current item.
+    Frags FA, FB;
+    load(FA, k, t, mt);
+    while (true) {
+      int nk = k, nt = t, nm = mt;
+      next_of(nk, nt, nm);
+      load(FB, nk < k1 ? nk : k1 - 1, nt, nm);
+      step(FA);
+      if (k >= k1) break;
+      nk = k; nt = t; nm = mt;
+      next_of(nk, nt, nm);
+      load(FA, nk < k1 ? nk : k1 - 1, nt, nm);
+      step(FB);
+      if (k >= k1) break;
     }
     return cur;
   };
 
-  // combined amplitude of walker n from feature 0 of buffer b of every term
-  auto amp = [&](int b, int n, double& labs, int& sg) {
+  // combined amplitude of this lane's walker from feature 0 of buffer b of
+  // every term: log|psi| and sign (every lane of every wave computes it)
+  auto amp = [&](int b, int kend, double& labs, int& sg) {
     double ms[kMaxTerms];
     int es[kMaxTerms];
     int emax = INT_MIN;
     for (int t = 0; t < T; ++t) {
       int ed = 0;
-      const double md = frexp((double)buf(t, b)[n * RS], &ed);
+      const double md = frexp((double)buf(t, b)[m * RS], &ed);
       ms[t] = a.coeffs[t] * md;
-      es[t] = ebuf(t, b)[n] + ed;
+      es[t] = Er[t * 16 + m] + a.cesum[(size_t)t * (L + 1) + kend] + ed;
       if (ms[t] != 0.0 && es[t] > emax) emax = es[t];
     }
     if (emax == INT_MIN) { labs = -INFINITY; sg = 0; return; }
@@ -401,18 +447,24 @@ __global__ void __launch_bounds__(64 * Geo<CHI>::WPW) chain_kernel(ChainArgs a) 
     sg = mS > 0 ? 1 : -1;
   };
 
-  // amplitude of the current configuration
+  auto reset_prefix = [&]() {
+    for (int i = threadIdx.x; i < T * 16 * RS; i += nthr) {
+      const int t = i / (16 * RS), r = i % (16 * RS);
+      buf(t, P)[r] = (r % RS == 0) ? 1.f : 0.f;
+    }
+    for (int i = threadIdx.x; i < T * 16; i += nthr) Ep[i] = 0;
+  };
+
+  // amplitude of the current configuration (identical in every lane of a walker)
   reset_prefix();
   __syncthreads();
+  double lab;
+  int sgn, stat;
+  uint32_t nacc = 0;
   {
-    const int fin = run(P, 0, a.L, -1);
-    if (threadIdx.x < 16) {
-      double l; int s;
-      amp(fin, threadIdx.x, l, s);
-      lab[threadIdx.x] = l;
-      sgn[threadIdx.x] = s;
-      stat[threadIdx.x] = (s != 0 && isfinite(l)) ? 0 : -5;
-    }
+    const int fin = segment(P, 0, L, -1, false);
+    amp(fin, L, lab, sgn);
+    stat = (sgn != 0 && isfinite(lab)) ? 0 : -5;
     __syncthreads();
   }
 
@@ -426,78 +478,58 @@ __global__ void __launch_bounds__(64 * Geo<CHI>::WPW) chain_kernel(ChainArgs a) 
         const int j = a.order[qi];
         const int f = a.first[j];
         if (f < 0) {  // spin read by no position: ratio 1, always accepted
-          if (threadIdx.x < 16 && w0 + threadIdx.x < a.W && stat[threadIdx.x] == 0) {
-            sp[threadIdx.x * a.nw + (j >> 6)] ^= (1ull << (j & 63));
-            acc[threadIdx.x] += 1;
+          if (live && stat == 0) {
+            nacc += 1;
+            if (wv == 0 && g == 0) sp[m * nw + (j >> 6)] ^= (1ull << (j & 63));
           }
           __syncthreads();
           continue;
         }
         if (pos < f) {  // bring the prefix up to position f
-          const int fin = run(P, pos, f, -1);
+          const int fin = segment(P, pos, f, -1, false);
           for (int i = threadIdx.x; i < T * 16 * RS; i += nthr) {
             const int t = i / (16 * RS), r = i % (16 * RS);
             buf(t, P)[r] = buf(t, fin)[r];
           }
-          for (int i = threadIdx.x; i < T * 16; i += nthr) ebuf(i / 16, P)[i % 16] = ebuf(i / 16, fin)[i % 16];
+          __syncthreads();
+          for (int i = threadIdx.x; i < T * 16; i += nthr) Ep[i] = Er[i];
           __syncthreads();
         }
-        {  // first step at f: F gets the flipped slice, U the current one
-          const int bitn = spin_bit(sp + m * a.nw, j) ^ 1;
-          for (int t = 0; t < T; ++t)
-            chain_step<D, CHI>(slice(t, f, 0), slice(t, f, 1), cexp_of(t, f), buf(t, P), ebuf(t, P),
-                               buf(t, F), ebuf(t, F), buf(t, U), ebuf(t, U), bitn, wv, lane);
-          __syncthreads();
-        }
-        int fin = F;
-        if (f + 1 < a.L) {
-          // run() ping-pongs X/Y; start from F by copying nothing: step F -> X first
-          int cur = F;
-          for (int k = f + 1; k < a.L; ++k) {
-            const int q = a.pi[k];
-            const int bitn = spin_bit(sp + m * a.nw, q) ^ (q == j ? 1 : 0);
-            const int nxt = (cur == X) ? Y : X;
-            for (int t = 0; t < T; ++t)
-              chain_step<D, CHI>(slice(t, k, 0), slice(t, k, 1), cexp_of(t, k), buf(t, cur),
-                                 ebuf(t, cur), buf(t, nxt), ebuf(t, nxt), nullptr, nullptr, bitn,
-                                 wv, lane);
-            __syncthreads();
-            cur = nxt;
-          }
-          fin = cur;
-        }
-        if (threadIdx.x < 16) {
-          const int n = threadIdx.x;
-          int accept = 0;
-          if (w0 + n < a.W && stat[n] == 0) {
-            double lnew; int snew;
-            amp(fin, n, lnew, snew);
-            if (isnan(lnew)) {
-              stat[n] = -5;
-            } else if (snew != 0) {
-              const double u = philox_uniform(a.seed, a.rstream, (uint64_t)(w0 + n), sweep, (uint64_t)j);
-              const double r2 = exp(2.0 * (lnew - lab[n]));
-              if (u < r2) {
-                accept = 1;
-                sp[n * a.nw + (j >> 6)] ^= (1ull << (j & 63));
-                lab[n] = lnew;
-                sgn[n] = snew;
-                acc[n] += 1;
-              }
+        // the flipped row from position f to the end; the first step also
+        // leaves the unflipped extension of the prefix in U
+        const int fin = segment(P, f, L, j, true);
+        int accept = 0;
+        if (live && stat == 0) {
+          double lnew; int snew;
+          amp(fin, L, lnew, snew);
+          if (isnan(lnew)) {
+            stat = -5;
+          } else if (snew != 0) {
+            const double u = philox_uniform(a.seed, a.rstream, (uint64_t)(w0 + m), sweep, (uint64_t)j);
+            if (u < exp(2.0 * (lnew - lab))) {
+              accept = 1;
+              lab = lnew;
+              sgn = snew;
+              nacc += 1;
             }
           }
-          flag[n] = accept;
         }
-        __syncthreads();
-        // prefix through position f with the decided value of s_j
-        for (int i = threadIdx.x; i < T * 16 * RS; i += nthr) {
-          const int t = i / (16 * RS), r = i % (16 * RS);
-          const int n = r / RS;
-          buf(t, P)[r] = flag[n] ? buf(t, F)[r] : buf(t, U)[r];
-        }
-        for (int i = threadIdx.x; i < T * 16; i += nthr) {
-          const int t = i / 16, n = i % 16;
-          ebuf(t, P)[n] = flag[n] ? ebuf(t, F)[n] : ebuf(t, U)[n];
+        // prefix through position f with the decided s_j: each lane copies
+        // the features it wrote in the first step
+        for (int t = 0; t < T; ++t)
+#pragma unroll
+          for (int mt = 0; mt < MT; ++mt) {
+            const int off = m * RS + 16 * (wv * MT + mt) + 4 * g;
+            *reinterpret_cast<float4*>(buf(t, P) + off) =
+                *reinterpret_cast<const float4*>(buf(t, accept ? F : U) + off);
+          }
+        if (wv == 0 && g == 0) {
+          for (int t = 0; t < T; ++t) Ep[t * 16 + m] = Ef[t * 16 + m];
+          if (accept) {
+            sp[m * nw + (j >> 6)] ^= (1ull << (j & 63));
+            const uint64_t* rmj = a.rmask + (size_t)j * LW;
+            for (int wd = 0; wd < LW; ++wd) pm[m * LW + wd] ^= rmj[wd];
+          }
         }
         __syncthreads();
         pos = f + 1;
@@ -506,17 +538,15 @@ __global__ void __launch_bounds__(64 * Geo<CHI>::WPW) chain_kernel(ChainArgs a) 
   }
 
   // write back
-  for (int i = threadIdx.x; i < 16 * a.nw; i += nthr) {
-    const int n = i / a.nw, wd = i % a.nw;
-    if (a.mode == 1 && w0 + n < a.W) a.spins[(size_t)(w0 + n) * a.nw + wd] = sp[i];
-  }
-  if (threadIdx.x < 16 && w0 + threadIdx.x < a.W) {
-    const int n = threadIdx.x, w = w0 + n;
-    const bool ok = stat[n] == 0;
-    if (a.logabs) a.logabs[w] = ok ? lab[n] : NAN;
-    if (a.sign) a.sign[w] = ok ? (int8_t)sgn[n] : 0;
-    if (a.accepts && a.mode == 1) a.accepts[w] += acc[n];
-    if (a.status) a.status[w] = stat[n];
+  if (wv == 0 && g == 0 && live) {
+    const int w = w0 + m;
+    if (a.mode == 1)
+      for (int wd = 0; wd < nw; ++wd) a.spins[(size_t)w * nw + wd] = sp[m * nw + wd];
+    const bool ok = stat == 0;
+    if (a.logabs) a.logabs[w] = ok ? lab : NAN;
+    if (a.sign) a.sign[w] = ok ? (int8_t)sgn : 0;
+    if (a.accepts && a.mode == 1) a.accepts[w] += nacc;
+    if (a.status) a.status[w] = stat;
   }
 }
 

@@ -137,9 +137,8 @@ size_t pass_lds_bytes(int chi, int nslot, int nw) {
   return (size_t)wpb * (2 * nslot * rs * 4 + 2 * nslot * 4 + nw * 8);
 }
 
-size_t chain_lds_bytes(int chi, int T, int nw) {
-  const size_t rs = chi + 4;
-  return (size_t)T * 5 * 16 * rs * 4 + (size_t)T * 5 * 16 * 4 + 16 * nw * 8 + 16 * 8 + 16 * 4 * 4;
+size_t chain_lds_bytes(int chi, int T, int L, int nw) {
+  return (size_t)rttk::ChainLayout(chi, T, (L + 63) / 64, nw).total;
 }
 
 }  // namespace
@@ -149,13 +148,17 @@ struct rtt_s {
   std::vector<int> pi, bond;
   std::vector<double> coeffs;
   std::vector<std::vector<double>> qcores;  // quantised values, rtt_create layout, per term
-  std::vector<int> core_exp;                // [T][L]
+  std::vector<int> core_exp;                // [T][L] power-of-two scale of each stored core
+  std::vector<int> cesum;                   // [T][L+1] prefix sums of core_exp
+  std::vector<uint64_t> rmask;              // [N][LW] replica positions of each spin
   Sched sched;
   std::vector<int> order, first;
   // device
   void* d_fwd = nullptr;      // [T][L][2][chi*chi] transposed fragments
   void* d_bwd = nullptr;      // [T][L][2][chi*chi]
   int* d_cexp = nullptr;
+  int* d_cesum = nullptr;
+  uint64_t* d_rmask = nullptr;
   int4* d_sf = nullptr;
   int4* d_sb = nullptr;
   int* d_fslot = nullptr;
@@ -185,7 +188,7 @@ size_t elem_bytes(int dtype) { return dtype == RTT_F32 ? 4 : 2; }
 // Pack one term: element (t, lane, e) of slice (k, b) in the forward layout
 // is core[b][g*KPL + e][16t + m] (transposed), in the backward layout
 // core[b][16t + m][g*KPL + e]; lane = 16 g + m, KPL = chi / 4.
-void pack_term(const rtt_s* h, const std::vector<double>& q, std::vector<uint8_t>& fw,
+void pack_term(const rtt_s* h, int term, const std::vector<double>& q, std::vector<uint8_t>& fw,
                std::vector<uint8_t>& bw) {
   const int chi = h->chi, L = h->L, KPL = chi / 4;
   const size_t eb = elem_bytes(h->dtype);
@@ -195,10 +198,12 @@ void pack_term(const rtt_s* h, const std::vector<double>& q, std::vector<uint8_t
   size_t off = 0;
   for (int k = 0; k < L; ++k) {
     const int a = h->bond[k], b = h->bond[k + 1];
+    const int ce = h->core_exp[(size_t)term * L + k];
     std::vector<double> pad((size_t)2 * slice, 0.0);
     for (int s = 0; s < 2; ++s)
       for (int i = 0; i < a; ++i)
-        for (int j = 0; j < b; ++j) pad[s * slice + (size_t)i * chi + j] = q[off + ((size_t)s * a + i) * b + j];
+        for (int j = 0; j < b; ++j)
+          pad[s * slice + (size_t)i * chi + j] = ldexp(q[off + ((size_t)s * a + i) * b + j], -ce);
     off += (size_t)2 * a * b;
     for (int s = 0; s < 2; ++s) {
       const size_t base = ((size_t)k * 2 + s) * slice;
@@ -230,7 +235,7 @@ rtt_status upload(void** dst, const void* src, size_t bytes) {
 }
 
 void free_dev(rtt_s* h) {
-  void* ptrs[] = {h->d_fwd, h->d_bwd, h->d_cexp, h->d_sf, h->d_sb, h->d_fslot, h->d_bslot,
+  void* ptrs[] = {h->d_fwd, h->d_bwd, h->d_cexp, h->d_cesum, h->d_rmask, h->d_sf, h->d_sb, h->d_fslot, h->d_bslot,
                   h->d_pi, h->d_order, h->d_first, h->d_coeffs, h->d_u, h->d_v, h->d_ue, h->d_ve};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -250,16 +255,42 @@ void quantise(int dtype, const std::vector<int>& bond, const double* cores, std:
       for (size_t i = 0; i < n; ++i) q.push_back((double)to_f32(c[i]));
     } else if (dtype == RTT_BF16) {
       for (size_t i = 0; i < n; ++i) q.push_back(bf16_value(bf16_bits_rne((float)c[i])));
-    } else {  // FP8 e4m3: codes kept unscaled, scale applied as an exponent
+    } else {  // FP8 e4m3: value = code * 2^e, one scale per position
       const int e = fp8_scale_exponent(c, n);
-      cexp[k] = e;
-      for (size_t i = 0; i < n; ++i) q.push_back(e4m3_round((float)ldexp(c[i], -e)));
+      for (size_t i = 0; i < n; ++i) q.push_back(ldexp(e4m3_round((float)ldexp(c[i], -e)), e));
     }
     off += n;
   }
 }
 
+// Every stored core is the quantised core times 2^-e_k, with e_k chosen so
+// that its largest entry lies in [0.5, 1): exact, and it bounds the growth
+// of a renormalised row to chi per step.  e_k is added back in the exponent
+// bookkeeping of the kernels.
+void prescale(rtt_s* h) {
+  h->core_exp.assign((size_t)h->T * h->L, 0);
+  h->cesum.assign((size_t)h->T * (h->L + 1), 0);
+  for (int t = 0; t < h->T; ++t) {
+    std::vector<double>& q = h->qcores[t];
+    size_t off = 0;
+    for (int k = 0; k < h->L; ++k) {
+      const size_t n = (size_t)2 * h->bond[k] * h->bond[k + 1];
+      double amax = 0.0;
+      for (size_t i = 0; i < n; ++i) amax = std::max(amax, fabs(q[off + i]));
+      int e = 0;
+      if (amax > 0.0) frexp(amax, &e);
+      h->core_exp[(size_t)t * h->L + k] = e;
+      h->cesum[(size_t)t * (h->L + 1) + k + 1] = h->cesum[(size_t)t * (h->L + 1) + k] + e;
+      off += n;
+    }
+  }
+}
+
 rtt_status finish_create(rtt_s* h) {
+  prescale(h);
+  const int LW = (h->L + 63) / 64;
+  h->rmask.assign((size_t)h->N * LW, 0ull);
+  for (int k = 0; k < h->L; ++k) h->rmask[(size_t)h->pi[k] * LW + k / 64] |= 1ull << (k % 64);
   // schedules: choose the cut bond with the least matrix-core work that fits on chip
   Sched best;
   bool have = false;
@@ -269,7 +300,7 @@ rtt_status finish_create(rtt_s* h) {
     if (!have || s.cost < best.cost) { best = s; have = true; }
   }
   if (!have) return fail(RTT_E_UNSUPPORTED, "rtt_create: flip-ratio rows of one walker exceed on-chip memory");
-  if (chain_lds_bytes(h->chi, h->T, h->nw) > kLdsLimit)
+  if (chain_lds_bytes(h->chi, h->T, h->L, h->nw) > kLdsLimit)
     return fail(RTT_E_UNSUPPORTED, "rtt_create: sampling state of 16 walkers exceeds on-chip memory");
   h->sched = best;
   // proposal order: spins by first position, unread spins last
@@ -285,7 +316,7 @@ rtt_status finish_create(rtt_s* h) {
   // pack and upload every term
   std::vector<uint8_t> fw_all, bw_all, fw, bw;
   for (int t = 0; t < h->T; ++t) {
-    pack_term(h, h->qcores[t], fw, bw);
+    pack_term(h, t, h->qcores[t], fw, bw);
     fw_all.insert(fw_all.end(), fw.begin(), fw.end());
     bw_all.insert(bw_all.end(), bw.begin(), bw.end());
   }
@@ -293,6 +324,8 @@ rtt_status finish_create(rtt_s* h) {
   if ((st = upload(&h->d_fwd, fw_all.data(), fw_all.size())) != RTT_OK) return st;
   if ((st = upload(&h->d_bwd, bw_all.data(), bw_all.size())) != RTT_OK) return st;
   if ((st = upload((void**)&h->d_cexp, h->core_exp.data(), h->core_exp.size() * 4)) != RTT_OK) return st;
+  if ((st = upload((void**)&h->d_cesum, h->cesum.data(), h->cesum.size() * 4)) != RTT_OK) return st;
+  if ((st = upload((void**)&h->d_rmask, h->rmask.data(), h->rmask.size() * 8)) != RTT_OK) return st;
   if ((st = upload((void**)&h->d_sf, best.fwd.data(), best.fwd.size() * 4)) != RTT_OK) return st;
   if ((st = upload((void**)&h->d_sb, best.bwd.data(), best.bwd.size() * 4)) != RTT_OK) return st;
   if ((st = upload((void**)&h->d_fslot, best.fslot.data(), best.fslot.size() * 4)) != RTT_OK) return st;
@@ -338,7 +371,7 @@ rtt_status launch_pass(const rttk::PassArgs& a, int T, hipStream_t s) {
 template <class D, int CHI>
 rtt_status launch_chain(const rttk::ChainArgs& a, hipStream_t s) {
   constexpr int WPW = rttk::Geo<CHI>::WPW;
-  const size_t lds = chain_lds_bytes(CHI, a.T, a.nw);
+  const size_t lds = chain_lds_bytes(CHI, a.T, a.L, a.nw);
   auto kfn = rttk::chain_kernel<D, CHI>;
   HIPX(hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   dim3 grid((a.W + 15) / 16);
@@ -429,7 +462,7 @@ rtt_status rtt_create(int32_t n_spins, int32_t n_cores, const int32_t* pi, const
   h->coeffs = {1.0};
   h->qcores.resize(1);
   quantise(dtype, h->bond, cores, h->qcores[0], h->core_exp);
-  hipGetDevice(&h->device);
+  (void)hipGetDevice(&h->device);
   rtt_status st = finish_create(h);
   if (st != RTT_OK) {
     free_dev(h);
@@ -467,11 +500,7 @@ rtt_status rtt_lincomb(int32_t n_terms, const rtt_t* terms, const double* coeffs
   h->bond = t0->bond;
   // terms may have different inner bonds: keep each term's own layout
   h->coeffs.assign(coeffs, coeffs + n_terms);
-  h->core_exp.clear();
-  for (int t = 0; t < n_terms; ++t) {
-    h->qcores.push_back(terms[t]->qcores[0]);
-    h->core_exp.insert(h->core_exp.end(), terms[t]->core_exp.begin(), terms[t]->core_exp.end());
-  }
+  for (int t = 0; t < n_terms; ++t) h->qcores.push_back(terms[t]->qcores[0]);
   // pack_term reads bond per handle: all terms share bond only if equal; pad via each term
   bool same_bond = true;
   for (int t = 0; t < n_terms; ++t) same_bond &= (terms[t]->bond == t0->bond);
@@ -479,7 +508,7 @@ rtt_status rtt_lincomb(int32_t n_terms, const rtt_t* terms, const double* coeffs
     delete h;
     return fail(RTT_E_ARG, "rtt_lincomb: terms must share the bond dimensions");
   }
-  hipGetDevice(&h->device);
+  (void)hipGetDevice(&h->device);
   rtt_status st = finish_create(h);
   if (st != RTT_OK) {
     free_dev(h);
@@ -583,7 +612,7 @@ rtt_status rtt_evaluate(rtt_t h, rtt_ham_t ham, int32_t W, const uint64_t* spins
   const size_t tslice = (size_t)h->L * 2 * h->chi * h->chi * elem_bytes(h->dtype);
   (void)tslice;
   rttk::PassArgs pa{};
-  pa.core_exp = h->dtype == RTT_FP8_E4M3 ? h->d_cexp : nullptr;
+  pa.core_exp = h->d_cexp;
   pa.nslot = h->sched.nslot;
   pa.L = h->L;
   pa.nw = h->nw;
@@ -638,9 +667,10 @@ static rtt_status chain_common(rtt_t h, int32_t W, uint64_t* spins, double* loga
   if (n_sweeps < 0) return fail(RTT_E_ARG, "n_sweeps = %d < 0", n_sweeps);
   rttk::ChainArgs ca{};
   ca.cores = h->d_fwd;
-  ca.core_exp = h->dtype == RTT_FP8_E4M3 ? h->d_cexp : nullptr;
+  ca.cesum = h->d_cesum;
+  ca.rmask = h->d_rmask;
   ca.pi = h->d_pi; ca.order = h->d_order; ca.first = h->d_first; ca.coeffs = h->d_coeffs;
-  ca.T = h->T; ca.L = h->L; ca.N = h->N; ca.nw = h->nw; ca.W = W;
+  ca.T = h->T; ca.L = h->L; ca.N = h->N; ca.nw = h->nw; ca.LW = (h->L + 63) / 64; ca.W = W;
   ca.spins = spins; ca.logabs = logabs; ca.sign = sign; ca.accepts = accepts; ca.status = status;
   ca.seed = seed; ca.rstream = rstream; ca.sweep0 = sweep0; ca.n_sweeps = n_sweeps; ca.mode = mode;
   return dispatch<ChainL>(h->dtype, h->chi, ca, (hipStream_t)stream);
