@@ -202,6 +202,54 @@ def run(dtype, steps, warmup, with_cpu):
     return res
 
 
+def run_batched(steps, n_rtt=256):
+    """256 uneven RTTs (side 4..10, R 2..3, chi 16..128, 256..4096 walkers,
+    BF16) stepped together: each step = 1 sweep + local energies of every
+    walker of every RTT, one captured graph of persistent kernels whose
+    launch shape the autotuner picks."""
+    import torch
+
+    from paper_2604_22718_amd import rtt as R
+    from paper_2604_22718_amd import workloads as wl
+    t0 = time.perf_counter()
+    ws = wl.batched_workloads(n_rtt)
+    rtts, hams, spins = [], [], []
+    flops_le = flops_sw = 0.0
+    for w in ws:
+        pi = w.pi()
+        rtts.append(R.RTT.create(w.N, pi, w.cores(), "bf16"))
+        hams.append(R.TFIM(w.Lx, w.Ly, w.J, w.h))
+        spins.append(R.spins_to_device(wl.pack_spins(w.spins())))
+        info = R.rtt_info(rtts[-1].handle)
+        f, b = schedule_rowsteps(pi, w.N, w.L, info["cut"])
+        flops_le += w.W * (f + b) * 2.0 * w.chi * w.chi
+        flops_sw += w.W * sweep_rowsteps(pi, w.N, w.L) * 2.0 * w.chi * w.chi
+    batch = R.Batch(rtts, hams, spins, seed=3100)
+    setup = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    choice = batch.autotune(n_sweeps=1, reps=1, cache_path=os.environ.get("RTT_TUNE_CACHE"))
+    tune = time.perf_counter() - t1
+    batch.step(1)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        batch.step(1)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    walkers = sum(w.W for w in ws)
+    res = {"workload": f"{n_rtt} uneven RTTs (side 4-10, R 2-3, chi 16-128, 256-4096 walkers), bf16",
+           "walkers": walkers, "steps": steps, "ms_per_step": ms,
+           "local_energy_evals_per_s": walkers / (ms * 1e-3),
+           "algorithmic_tflops": (flops_le + flops_sw) / (ms * 1e-3) / 1e12,
+           "frac_of_bf16_peak": (flops_le + flops_sw) / (ms * 1e-3) / PEAK["bf16"],
+           "autotuned_shape": {"concurrent_classes": choice[0], "blocks_per_cu": choice[1]},
+           "setup_s": setup, "autotune_s": tune}
+    batch.close()
+    return res
+
+
 def stats_tau(x):
     """Integrated autocorrelation time of a 1-D series (Sokal window, c = 5)."""
     x = np.asarray(x, dtype=np.float64)
@@ -228,6 +276,7 @@ def main():
     ap.add_argument("--dtype", default="f32", choices=["f32", "bf16", "fp8"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--also", default="bf16", help="second precision reported alongside ('' for none)")
+    ap.add_argument("--batched", type=int, default=0, help="also time the 256-RTT batch for this many steps")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only: this build has no multi-GPU path (asked for {a.gpus}).",
@@ -241,6 +290,8 @@ def main():
         other = run(a.also, a.steps, a.warmup, False)
         res["also"] = {k: other[k] for k in ("dtype", "value", "ms_per_step", "effective_samples_per_s",
                                              "energy_error", "kernels", "roofline")}
+    if a.batched:
+        res["batched"] = run_batched(a.batched)
     if not a.no_cpu:
         from paper_2604_22718_amd import workloads as wl
         res["cpu_baseline"] = cpu_baseline(wl.MEDIUM_8x8, 64, 8)

@@ -166,6 +166,43 @@ rtt_status rtt_mcmc_sweep(rtt_t h, int32_t W, uint64_t* spins, double* logabs,
  */
 rtt_status rtt_energy_reduce(int32_t n, const double* x, double* out, void* stream);
 
+/*
+ * Batches: many independent RTT Monte Carlo runs of uneven size stepped
+ * together in one captured HIP graph of persistent kernels.
+ *
+ * rtt_batch_create: n >= 1 runs; run b uses RTT rtts[b], Hamiltonian hams[b]
+ *   (its lattice must have the RTT's N sites), walkers[b] >= 1 walkers whose
+ *   spins live at spins[b] (device uint64[walkers[b]][ceil(N/64)], updated in
+ *   place) and whose local energies are written to eloc[b] (device
+ *   double[walkers[b]]).  rtts, hams, walkers, spins, eloc are host arrays of
+ *   length n; the device buffers are caller-owned and must stay valid, at the
+ *   same addresses, for the life of the batch.  Run b draws its Philox
+ *   uniforms under key (seed, b).  Handles of the RTTs and Hamiltonians must
+ *   outlive the batch.
+ * rtt_batch_step: n_sweeps Metropolis sweeps of every walker of every run
+ *   (sweep numbers continue from the previous step), then local energies of
+ *   every walker, then per-run sums into esum (device double[n][3]: sum of
+ *   E_loc, sum of E_loc^2, number of finite values; may be NULL).  The first
+ *   call for a given (n_sweeps, esum) captures the graph (this synchronises);
+ *   later calls only launch it on `stream`.
+ * rtt_batch_autotune: times every launch shape (bond classes one after the
+ *   other on the whole GPU, or concurrently on graph branches with compute
+ *   units shared in proportion to their work; 1..4 persistent blocks per
+ *   compute unit) with `reps` steps each, keeps the fastest, and records it in
+ *   the JSON file cache_path (NULL: no file).  The timed steps advance the
+ *   chains.  choice (host int32[2], may be NULL) receives (concurrent, blocks
+ *   per compute unit).  Synchronises.
+ */
+typedef struct rtt_batch_s* rtt_batch_t;
+
+rtt_status rtt_batch_create(int32_t n, const rtt_t* rtts, const rtt_ham_t* hams,
+                            const int32_t* walkers, uint64_t* const* spins,
+                            double* const* eloc, uint64_t seed, rtt_batch_t* out);
+rtt_status rtt_batch_step(rtt_batch_t b, int32_t n_sweeps, double* esum, void* stream);
+rtt_status rtt_batch_autotune(rtt_batch_t b, int32_t n_sweeps, int32_t reps,
+                              const char* cache_path, int32_t* choice, void* stream);
+rtt_status rtt_batch_destroy(rtt_batch_t b);
+
 #ifdef __cplusplus
 }
 #endif

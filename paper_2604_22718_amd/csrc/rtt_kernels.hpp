@@ -50,7 +50,7 @@ struct PassArgs {
 };
 
 template <class D, int CHI>
-__global__ void __launch_bounds__(256) pass_kernel(PassArgs a) {
+__device__ __forceinline__ void pass_body(const PassArgs& a, int bx, int term) {
   using E = typename D::elem;
   using G = Geo<CHI>;
   constexpr int WPW = G::WPW, MT = G::MT, KPL = G::KPL, RS = G::RS;
@@ -59,8 +59,7 @@ __global__ void __launch_bounds__(256) pass_kernel(PassArgs a) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int ws = wave / WPW, wv = wave % WPW;
   const int g = lane >> 4, m = lane & 15;
-  const int term = blockIdx.y;
-  const int w_raw = blockIdx.x * WPB + ws;
+  const int w_raw = bx * WPB + ws;
   const int w = w_raw < a.W ? w_raw : a.W - 1;
   const int nslot = a.nslot;
   const int bufsz = nslot * RS;
@@ -156,6 +155,11 @@ __global__ void __launch_bounds__(256) pass_kernel(PassArgs a) {
   }
 }
 
+template <class D, int CHI>
+__global__ void __launch_bounds__(256) pass_kernel(PassArgs a) {
+  pass_body<D, CHI>(a, blockIdx.x, blockIdx.y);
+}
+
 // ============================================================================
 // combine kernel (one wave per walker)
 // ============================================================================
@@ -209,9 +213,9 @@ __device__ inline double wave_sum(double x) {
   return x;
 }
 
-__global__ void __launch_bounds__(256) combine_kernel(CombineArgs a) {
+__device__ __forceinline__ void combine_body(const CombineArgs& a, int bx) {
   const int lane = threadIdx.x & 63;
-  const int w = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int w = bx * 4 + (threadIdx.x >> 6);
   if (w >= a.W) return;
   const double LN2 = 0.69314718055994530942;
   double m0; int e0;
@@ -259,6 +263,8 @@ __global__ void __launch_bounds__(256) combine_kernel(CombineArgs a) {
   }
 }
 
+__global__ void __launch_bounds__(256) combine_kernel(CombineArgs a) { combine_body(a, blockIdx.x); }
+
 // ============================================================================
 // chain kernel: 16 walkers per block, amplitudes and Metropolis sweeps
 // ============================================================================
@@ -295,7 +301,7 @@ struct ChainLayout {
 };
 
 template <class D, int CHI>
-__global__ void __launch_bounds__(64 * Geo<CHI>::WPW) chain_kernel(ChainArgs a) {
+__device__ __forceinline__ void chain_body(const ChainArgs& a, int bx) {
   using E = typename D::elem;
   using G = Geo<CHI>;
   constexpr int RS = G::RS, MT = G::MT, KPL = G::KPL;
@@ -316,7 +322,7 @@ __global__ void __launch_bounds__(64 * Geo<CHI>::WPW) chain_kernel(ChainArgs a) 
   enum { P = 0, U = 1, F = 2, X = 3, Y = 4 };
   auto buf = [&](int t, int b) { return rows + (t * 5 + b) * BUF; };
 
-  const int w0 = blockIdx.x * 16;
+  const int w0 = bx * 16;
   const bool live = (w0 + m) < a.W;
   for (int i = threadIdx.x; i < T * 5 * BUF; i += nthr) rows[i] = 0.f;
   for (int i = threadIdx.x; i < 3 * T * 16; i += nthr) Ep[i] = 0;
@@ -550,6 +556,11 @@ __global__ void __launch_bounds__(64 * Geo<CHI>::WPW) chain_kernel(ChainArgs a) 
   }
 }
 
+template <class D, int CHI>
+__global__ void __launch_bounds__(64 * Geo<CHI>::WPW) chain_kernel(ChainArgs a) {
+  chain_body<D, CHI>(a, blockIdx.x);
+}
+
 // ============================================================================
 // compensated reduction
 // ============================================================================
@@ -563,7 +574,7 @@ __device__ __forceinline__ void neumaier_merge(double& s, double& c, double s2, 
   c += c2;
 }
 
-__global__ void __launch_bounds__(256) reduce_kernel(int n, const double* x, double* out) {
+__device__ __forceinline__ void reduce_body(int n, const double* x, double* out) {
   __shared__ double sh[4][256];
   double s1 = 0, c1 = 0, s2 = 0, c2 = 0, cnt = 0;
   for (int i = threadIdx.x; i < n; i += 256) {
@@ -600,6 +611,82 @@ __global__ void __launch_bounds__(256) reduce_kernel(int n, const double* x, dou
     out[1] = sh[2][0] + sh[3][0];
     out[2] = shc[0];
   }
+}
+
+__global__ void __launch_bounds__(256) reduce_kernel(int n, const double* x, double* out) {
+  reduce_body(n, x, out);
+}
+
+// ============================================================================
+// persistent forms for batches of RTTs
+// ============================================================================
+// Work items (int4): x = descriptor index, y = block index within that
+// descriptor's launch, z = term (pass kernel).  Blocks take items from a
+// device counter until the list is exhausted; every wave reaches the exit.
+__device__ __forceinline__ int next_item(int* counter, int* s_item) {
+  if (threadIdx.x == 0) *s_item = atomicAdd(counter, 1);
+  __syncthreads();
+  const int it = *s_item;
+  __syncthreads();
+  return it;
+}
+
+template <class D, int CHI>
+__global__ void __launch_bounds__(256) pass_persistent(const PassArgs* descs, const int4* items,
+                                                       int n_items, int* counter) {
+  __shared__ int s_item;
+  for (;;) {
+    const int it = next_item(counter, &s_item);
+    if (it >= n_items) break;
+    const int4 w = items[it];
+    const PassArgs a = descs[w.x];
+    pass_body<D, CHI>(a, w.y, w.z);
+    __syncthreads();
+  }
+}
+
+template <class D, int CHI>
+__global__ void __launch_bounds__(64 * Geo<CHI>::WPW) chain_persistent(const ChainArgs* descs,
+                                                                        const int4* items, int n_items,
+                                                                        int* counter,
+                                                                        const uint64_t* sweep0) {
+  __shared__ int s_item;
+  for (;;) {
+    const int it = next_item(counter, &s_item);
+    if (it >= n_items) break;
+    const int4 w = items[it];
+    ChainArgs a = descs[w.x];
+    a.sweep0 = *sweep0;
+    chain_body<D, CHI>(a, w.y);
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(256) combine_persistent(const CombineArgs* descs, const int4* items,
+                                                          int n_items, int* counter) {
+  __shared__ int s_item;
+  for (;;) {
+    const int it = next_item(counter, &s_item);
+    if (it >= n_items) break;
+    const int4 w = items[it];
+    const CombineArgs a = descs[w.x];
+    combine_body(a, w.y);
+    __syncthreads();
+  }
+}
+
+// one block per RTT: out[3*b .. 3*b+2] = compensated sum, sum of squares, count
+__global__ void __launch_bounds__(256) reduce_many(const int* n, const double* const* x, double* out) {
+  reduce_body(n[blockIdx.x], x[blockIdx.x], out + 3 * blockIdx.x);
+}
+
+// graph-safe clearing of work counters (a kernel, not a memset node)
+__global__ void fill_int(int* p, int n, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+__global__ void advance_u64(uint64_t* p, uint64_t by) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p += by;
 }
 
 }  // namespace rttk

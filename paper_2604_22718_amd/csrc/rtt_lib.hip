@@ -130,6 +130,8 @@ Sched build_sched(const std::vector<int>& pi, int N, int L, int c) {
   return s;
 }
 
+int rttk_wpw(int chi) { return chi >= 64 ? 4 : chi / 16; }
+
 size_t pass_lds_bytes(int chi, int nslot, int nw) {
   const int wpw = chi >= 64 ? 4 : chi / 16;
   const int wpb = 4 / wpw;
@@ -696,6 +698,430 @@ rtt_status rtt_energy_reduce(int32_t n, const double* x, double* out, void* stre
   if (n < 0 || (n > 0 && !x) || !out) return fail(RTT_E_ARG, "rtt_energy_reduce: bad argument");
   hipLaunchKernelGGL(rttk::reduce_kernel, dim3(1), dim3(256), 0, (hipStream_t)stream, n, x, out);
   HIPX(hipGetLastError());
+  return RTT_OK;
+}
+
+}  // extern "C"
+
+// ============================================================================
+// batches
+// ============================================================================
+namespace {
+
+// one bond class (dtype, padded bond) of a batch
+struct BatchClass {
+  int dtype = 0, chi = 0;
+  std::vector<int> members;
+  std::vector<rttk::ChainArgs> chain;  // one descriptor per member
+  std::vector<rttk::PassArgs> pass;    // forward and backward per member
+  std::vector<int4> chain_items, pass_items;
+  double chain_cost = 0, pass_cost = 0;
+  size_t chain_lds = 0, pass_lds = 0;
+  rttk::ChainArgs* d_chain = nullptr;
+  rttk::PassArgs* d_pass = nullptr;
+  int4* d_chain_items = nullptr;
+  int4* d_pass_items = nullptr;
+  int grid_chain = 1, grid_pass = 1;
+  hipStream_t stream = nullptr;
+};
+
+}  // namespace
+
+struct rtt_batch_s {
+  int n = 0;
+  uint64_t seed = 0;
+  std::vector<rtt_s*> rtts;
+  std::vector<rtt_ham_s*> hams;
+  std::vector<int> W;
+  std::vector<uint64_t*> spins;
+  std::vector<double*> eloc;
+  std::vector<float*> ws_f;      // per run: forward and backward cut vectors
+  std::vector<int*> ws_i;        // per run: their exponents
+  std::vector<BatchClass> classes;
+  std::vector<rttk::CombineArgs> comb;
+  std::vector<int4> comb_items;
+  rttk::CombineArgs* d_comb = nullptr;
+  int4* d_comb_items = nullptr;
+  int* d_counters = nullptr;     // [2 * classes + 1]
+  uint64_t* d_sweep0 = nullptr;
+  int* d_red_n = nullptr;
+  const double** d_red_x = nullptr;
+  int concurrent = 0, occ = 1;   // launch shape
+  int cus = 256;
+  hipStream_t cap = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+  std::vector<hipEvent_t> done;
+  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph = nullptr;
+  int graph_sweeps = -1;
+  double* graph_esum = nullptr;
+};
+
+namespace {
+
+template <class D, int CHI>
+struct BatchL {
+  static rtt_status run(BatchClass& c, int* counters, const uint64_t* sweep0, int phase, hipStream_t s) {
+    if (phase == 2) {  // before capture: allow the dynamic LDS sizes
+      HIPX(hipFuncSetAttribute((const void*)rttk::chain_persistent<D, CHI>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)c.chain_lds));
+      HIPX(hipFuncSetAttribute((const void*)rttk::pass_persistent<D, CHI>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)c.pass_lds));
+      return RTT_OK;
+    }
+    if (phase == 0) {
+      if (c.chain_items.empty()) return RTT_OK;
+      auto kfn = rttk::chain_persistent<D, CHI>;
+      hipLaunchKernelGGL(kfn, dim3(c.grid_chain), dim3(64 * rttk::Geo<CHI>::WPW), c.chain_lds, s, c.d_chain,
+                         c.d_chain_items, (int)c.chain_items.size(), counters, sweep0);
+    } else {
+      if (c.pass_items.empty()) return RTT_OK;
+      auto kfn = rttk::pass_persistent<D, CHI>;
+      hipLaunchKernelGGL(kfn, dim3(c.grid_pass), dim3(256), c.pass_lds, s, c.d_pass, c.d_pass_items,
+                         (int)c.pass_items.size(), counters);
+    }
+    HIPX(hipGetLastError());
+    return RTT_OK;
+  }
+};
+
+// persistent blocks per compute unit that the class's LDS allows
+int lds_occupancy(size_t lds) { return std::max(1, std::min(4, (int)(kLdsLimit / std::max<size_t>(lds, 1)))); }
+
+void size_grids(rtt_batch_s* b) {
+  double tot_c = 0, tot_p = 0;
+  for (auto& c : b->classes) { tot_c += c.chain_cost; tot_p += c.pass_cost; }
+  for (auto& c : b->classes) {
+    const int occ_c = std::min(b->occ, lds_occupancy(c.chain_lds));
+    const int occ_p = std::min(b->occ, lds_occupancy(c.pass_lds));
+    int gc = b->cus * occ_c, gp = b->cus * occ_p;
+    if (b->concurrent) {  // compute units shared in proportion to the work
+      gc = (int)std::lround(gc * (tot_c > 0 ? c.chain_cost / tot_c : 0.0));
+      gp = (int)std::lround(gp * (tot_p > 0 ? c.pass_cost / tot_p : 0.0));
+    }
+    c.grid_chain = std::max(1, std::min(gc, (int)c.chain_items.size()));
+    c.grid_pass = std::max(1, std::min(gp, (int)c.pass_items.size()));
+  }
+}
+
+rtt_status record_step(rtt_batch_s* b, int n_sweeps, double* esum, hipStream_t s) {
+  const int nc = (int)b->classes.size();
+  hipLaunchKernelGGL(rttk::fill_int, dim3(1), dim3(64), 0, s, b->d_counters, 2 * nc + 1, 0);
+  HIPX(hipGetLastError());
+  for (int phase = 0; phase < 2; ++phase) {
+    if (phase == 0 && n_sweeps == 0) continue;
+    if (b->concurrent) {
+      HIPX(hipEventRecord(b->fork, s));
+      for (int ci = 0; ci < nc; ++ci) {
+        BatchClass& c = b->classes[ci];
+        HIPX(hipStreamWaitEvent(c.stream, b->fork, 0));
+        rtt_status st = dispatch<BatchL>(c.dtype, c.chi, c, b->d_counters + 2 * ci + phase, b->d_sweep0, phase, c.stream);
+        if (st != RTT_OK) return st;
+        HIPX(hipEventRecord(b->done[ci], c.stream));
+      }
+      for (int ci = 0; ci < nc; ++ci) HIPX(hipStreamWaitEvent(s, b->done[ci], 0));
+    } else {
+      for (int ci = 0; ci < nc; ++ci) {
+        BatchClass& c = b->classes[ci];
+        rtt_status st = dispatch<BatchL>(c.dtype, c.chi, c, b->d_counters + 2 * ci + phase, b->d_sweep0, phase, s);
+        if (st != RTT_OK) return st;
+      }
+    }
+  }
+  hipLaunchKernelGGL(rttk::combine_persistent, dim3(std::min<int>(b->cus * 4, (int)b->comb_items.size())),
+                     dim3(256), 0, s, b->d_comb, b->d_comb_items, (int)b->comb_items.size(),
+                     b->d_counters + 2 * nc);
+  HIPX(hipGetLastError());
+  if (esum) {
+    hipLaunchKernelGGL(rttk::reduce_many, dim3(b->n), dim3(256), 0, s, b->d_red_n, b->d_red_x, esum);
+    HIPX(hipGetLastError());
+  }
+  hipLaunchKernelGGL(rttk::advance_u64, dim3(1), dim3(64), 0, s, b->d_sweep0, (uint64_t)n_sweeps);
+  HIPX(hipGetLastError());
+  return RTT_OK;
+}
+
+rtt_status set_sweeps(rtt_batch_s* b, int n_sweeps) {
+  for (auto& c : b->classes) {
+    for (auto& d : c.chain) d.n_sweeps = n_sweeps;
+    HIPX(hipMemcpy(c.d_chain, c.chain.data(), c.chain.size() * sizeof(rttk::ChainArgs), hipMemcpyHostToDevice));
+  }
+  return RTT_OK;
+}
+
+rtt_status capture(rtt_batch_s* b, int n_sweeps, double* esum) {
+  if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+  if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+  rtt_status st = set_sweeps(b, n_sweeps);
+  if (st != RTT_OK) return st;
+  size_grids(b);
+  for (auto& c : b->classes) {
+    st = dispatch<BatchL>(c.dtype, c.chi, c, (int*)nullptr, (const uint64_t*)nullptr, 2, b->cap);
+    if (st != RTT_OK) return st;
+  }
+  HIPX(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+  st = record_step(b, n_sweeps, esum, b->cap);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(b->cap, &g);
+  if (st != RTT_OK) { if (g) (void)hipGraphDestroy(g); return st; }
+  if (e != hipSuccess) return fail(RTT_E_HIP, "graph capture failed: %s", hipGetErrorString(e));
+  b->graph = g;
+  HIPX(hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0));
+  b->graph_sweeps = n_sweeps;
+  b->graph_esum = esum;
+  return RTT_OK;
+}
+
+void free_batch(rtt_batch_s* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  for (auto& c : b->classes) {
+    for (void* p : {(void*)c.d_chain, (void*)c.d_pass, (void*)c.d_chain_items, (void*)c.d_pass_items})
+      if (p) (void)hipFree(p);
+    if (c.stream) (void)hipStreamDestroy(c.stream);
+  }
+  for (void* p : {(void*)b->d_comb, (void*)b->d_comb_items, (void*)b->d_counters, (void*)b->d_sweep0,
+                  (void*)b->d_red_n, (void*)b->d_red_x})
+    if (p) (void)hipFree(p);
+  for (auto p : b->ws_f) if (p) (void)hipFree(p);
+  for (auto p : b->ws_i) if (p) (void)hipFree(p);
+  for (auto e : b->done) (void)hipEventDestroy(e);
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  if (b->join) (void)hipEventDestroy(b->join);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+}
+
+std::string batch_signature(const rtt_batch_s* b) {
+  std::string sig;
+  char buf[96];
+  for (int i = 0; i < b->n; ++i) {
+    snprintf(buf, sizeof buf, "%d:%d:%d:%d:%d;", b->rtts[i]->dtype, b->rtts[i]->chi, b->rtts[i]->L,
+             b->rtts[i]->N, b->W[i]);
+    sig += buf;
+  }
+  // FNV-1a of the description keeps cache keys short
+  uint64_t h = 1469598103934665603ull;
+  for (char ch : sig) { h ^= (unsigned char)ch; h *= 1099511628211ull; }
+  snprintf(buf, sizeof buf, "%016llx", (unsigned long long)h);
+  return buf;
+}
+
+}  // namespace
+
+extern "C" {
+
+rtt_status rtt_batch_create(int32_t n, const rtt_t* rtts, const rtt_ham_t* hams, const int32_t* walkers,
+                            uint64_t* const* spins, double* const* eloc, uint64_t seed, rtt_batch_t* out) {
+  g_err.clear();
+  if (!out) return fail(RTT_E_ARG, "rtt_batch_create: out is null");
+  *out = nullptr;
+  if (n < 1 || !rtts || !hams || !walkers || !spins || !eloc) return fail(RTT_E_ARG, "rtt_batch_create: bad argument");
+  for (int i = 0; i < n; ++i) {
+    if (!rtts[i] || !hams[i] || walkers[i] < 1 || !spins[i] || !eloc[i])
+      return fail(RTT_E_ARG, "rtt_batch_create: run %d has a null handle, buffer or no walkers", i);
+    if (hams[i]->Lx * hams[i]->Ly != rtts[i]->N)
+      return fail(RTT_E_ARG, "rtt_batch_create: run %d: lattice and RTT sizes differ", i);
+  }
+  rtt_batch_s* b = new rtt_batch_s;
+  b->n = n;
+  b->seed = seed;
+  b->rtts.assign(rtts, rtts + n);
+  b->hams.assign(hams, hams + n);
+  b->W.assign(walkers, walkers + n);
+  b->spins.assign(spins, spins + n);
+  b->eloc.assign(eloc, eloc + n);
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, dev) == hipSuccess) b->cus = prop.multiProcessorCount;
+
+  auto cleanup = [&](rtt_status st) { free_batch(b); delete b; return st; };
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < i; ++j)
+      if (b->rtts[i] == b->rtts[j] || b->spins[i] == b->spins[j] || b->eloc[i] == b->eloc[j]) {
+        delete b;
+        return fail(RTT_E_ARG, "rtt_batch_create: runs %d and %d share an RTT handle or a buffer", j, i);
+      }
+  // the batch's own cut-vector workspace for every run
+  b->ws_f.assign(n, nullptr);
+  b->ws_i.assign(n, nullptr);
+  for (int i = 0; i < n; ++i) {
+    const rtt_s* h = b->rtts[i];
+    const size_t rows = (size_t)h->T * b->W[i] * h->sched.nslot;
+    if (hipMalloc(&b->ws_f[i], 2 * rows * h->chi * 4) != hipSuccess ||
+        hipMalloc(&b->ws_i[i], 2 * rows * 4) != hipSuccess)
+      return cleanup(fail(RTT_E_OOM, "rtt_batch_create: workspace for run %d", i));
+  }
+  auto ws_u = [&](int i) { return b->ws_f[i]; };
+  auto ws_v = [&](int i) {
+    const rtt_s* h = b->rtts[i];
+    return b->ws_f[i] + (size_t)h->T * b->W[i] * h->sched.nslot * h->chi;
+  };
+  auto ws_ue = [&](int i) { return b->ws_i[i]; };
+  auto ws_ve = [&](int i) { return b->ws_i[i] + (size_t)b->rtts[i]->T * b->W[i] * b->rtts[i]->sched.nslot; };
+  // group runs by (dtype, padded bond); order members by work, largest first
+  for (int i = 0; i < n; ++i) {
+    const rtt_s* h = b->rtts[i];
+    int ci = -1;
+    for (int c = 0; c < (int)b->classes.size(); ++c)
+      if (b->classes[c].dtype == (h->dtype == RTT_FP8_E4M3 ? RTT_BF16 : h->dtype) && b->classes[c].chi == h->chi) ci = c;
+    if (ci < 0) {
+      b->classes.emplace_back();
+      ci = (int)b->classes.size() - 1;
+      b->classes[ci].dtype = h->dtype == RTT_FP8_E4M3 ? RTT_BF16 : h->dtype;
+      b->classes[ci].chi = h->chi;
+    }
+    b->classes[ci].members.push_back(i);
+  }
+  for (auto& c : b->classes) {
+    const double chi2 = (double)c.chi * c.chi;
+    std::vector<std::pair<double, int>> order;
+    for (int i : c.members) {
+      const rtt_s* h = b->rtts[i];
+      const double rows = (double)(h->sched.fwd.size() + h->sched.bwd.size()) / 4 * h->sched.nslot;
+      order.push_back({rows * chi2 * h->T, i});
+    }
+    std::sort(order.begin(), order.end(), [](auto& x, auto& y) { return x.first > y.first; });
+    c.members.clear();
+    for (auto& o : order) c.members.push_back(o.second);
+    for (int mi = 0; mi < (int)c.members.size(); ++mi) {
+      const int i = c.members[mi];
+      rtt_s* h = b->rtts[i];
+      const int W = b->W[i];
+      rttk::ChainArgs ca{};
+      ca.cores = h->d_fwd; ca.cesum = h->d_cesum; ca.rmask = h->d_rmask; ca.pi = h->d_pi;
+      ca.order = h->d_order; ca.first = h->d_first; ca.coeffs = h->d_coeffs;
+      ca.T = h->T; ca.L = h->L; ca.N = h->N; ca.nw = h->nw; ca.LW = (h->L + 63) / 64; ca.W = W;
+      ca.spins = b->spins[i]; ca.seed = seed; ca.rstream = (uint64_t)i; ca.mode = 1;
+      c.chain.push_back(ca);
+      c.chain_lds = std::max(c.chain_lds, chain_lds_bytes(c.chi, h->T, h->L, h->nw));
+      rttk::PassArgs pa{};
+      pa.core_exp = h->d_cexp; pa.nslot = h->sched.nslot; pa.L = h->L; pa.nw = h->nw; pa.W = W;
+      pa.spins = b->spins[i];
+      pa.cores = h->d_fwd; pa.sched = h->d_sf; pa.n_steps = (int)h->sched.fwd.size() / 4;
+      pa.out_vec = ws_u(i); pa.out_exp = ws_ue(i);
+      c.pass.push_back(pa);
+      pa.cores = h->d_bwd; pa.sched = h->d_sb; pa.n_steps = (int)h->sched.bwd.size() / 4;
+      pa.out_vec = ws_v(i); pa.out_exp = ws_ve(i);
+      c.pass.push_back(pa);
+      c.pass_lds = std::max(c.pass_lds, pass_lds_bytes(c.chi, h->sched.nslot, h->nw));
+      // sweep cost ~ (L + sum_j (L - first_j)) row-steps per walker tile
+      double sweep_rows = h->L;
+      for (int j = 0; j < h->N; ++j) if (h->first[j] >= 0) sweep_rows += h->L - h->first[j];
+      c.chain_cost += sweep_rows * h->T * ((W + 15) / 16) * 16 * (double)c.chi * c.chi;
+      const int wpb = 4 / rttk_wpw(c.chi);
+      c.pass_cost += (double)(h->sched.fwd.size() + h->sched.bwd.size()) / 4 * h->sched.nslot * h->T * W * (double)c.chi * c.chi;
+      for (int t = 0; t < (W + 15) / 16; ++t) c.chain_items.push_back(make_int4(mi, t, 0, 0));
+      for (int dir = 0; dir < 2; ++dir)
+        for (int term = 0; term < h->T; ++term)
+          for (int bx = 0; bx < (W + wpb - 1) / wpb; ++bx) c.pass_items.push_back(make_int4(2 * mi + dir, bx, term, 0));
+    }
+    rtt_status st;
+    if ((st = upload((void**)&c.d_chain, c.chain.data(), c.chain.size() * sizeof(rttk::ChainArgs))) != RTT_OK) return cleanup(st);
+    if ((st = upload((void**)&c.d_pass, c.pass.data(), c.pass.size() * sizeof(rttk::PassArgs))) != RTT_OK) return cleanup(st);
+    if ((st = upload((void**)&c.d_chain_items, c.chain_items.data(), c.chain_items.size() * sizeof(int4))) != RTT_OK) return cleanup(st);
+    if ((st = upload((void**)&c.d_pass_items, c.pass_items.data(), c.pass_items.size() * sizeof(int4))) != RTT_OK) return cleanup(st);
+    if (hipStreamCreateWithFlags(&c.stream, hipStreamNonBlocking) != hipSuccess) return cleanup(fail(RTT_E_HIP, "stream create"));
+  }
+  // combine descriptors: one per run; items of 4 walkers, biggest runs first
+  std::vector<int> by_size(n);
+  for (int i = 0; i < n; ++i) by_size[i] = i;
+  std::sort(by_size.begin(), by_size.end(), [&](int x, int y) { return b->W[x] * b->rtts[x]->N > b->W[y] * b->rtts[y]->N; });
+  for (int i = 0; i < n; ++i) {
+    rtt_s* h = b->rtts[i];
+    rttk::CombineArgs ca{};
+    ca.u = ws_u(i); ca.ue = ws_ue(i); ca.v = ws_v(i); ca.ve = ws_ve(i);
+    ca.nsf = h->sched.nslot; ca.nsb = h->sched.nslot; ca.chi = h->chi; ca.T = h->T; ca.W = b->W[i];
+    ca.N = h->N; ca.nw = h->nw; ca.fslot = h->d_fslot; ca.bslot = h->d_bslot; ca.coeffs = h->d_coeffs;
+    ca.spins = b->spins[i]; ca.bonds = b->hams[i]->d_bonds; ca.nbonds = b->hams[i]->nb;
+    ca.J = b->hams[i]->J; ca.h = b->hams[i]->h; ca.eloc = b->eloc[i];
+    b->comb.push_back(ca);
+  }
+  for (int i : by_size)
+    for (int bx = 0; bx < (b->W[i] + 3) / 4; ++bx) b->comb_items.push_back(make_int4(i, bx, 0, 0));
+  rtt_status st;
+  if ((st = upload((void**)&b->d_comb, b->comb.data(), b->comb.size() * sizeof(rttk::CombineArgs))) != RTT_OK) return cleanup(st);
+  if ((st = upload((void**)&b->d_comb_items, b->comb_items.data(), b->comb_items.size() * sizeof(int4))) != RTT_OK) return cleanup(st);
+  std::vector<int> zeros(2 * b->classes.size() + 1, 0);
+  if ((st = upload((void**)&b->d_counters, zeros.data(), zeros.size() * 4)) != RTT_OK) return cleanup(st);
+  uint64_t z64 = 0;
+  if ((st = upload((void**)&b->d_sweep0, &z64, 8)) != RTT_OK) return cleanup(st);
+  std::vector<const double*> xs(b->eloc.begin(), b->eloc.end());
+  if ((st = upload((void**)&b->d_red_n, b->W.data(), n * 4)) != RTT_OK) return cleanup(st);
+  if ((st = upload((void**)&b->d_red_x, xs.data(), n * sizeof(double*))) != RTT_OK) return cleanup(st);
+  if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) return cleanup(fail(RTT_E_HIP, "stream create"));
+  if (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess) return cleanup(fail(RTT_E_HIP, "event create"));
+  if (hipEventCreateWithFlags(&b->join, hipEventDisableTiming) != hipSuccess) return cleanup(fail(RTT_E_HIP, "event create"));
+  b->done.resize(b->classes.size());
+  for (auto& e : b->done)
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return cleanup(fail(RTT_E_HIP, "event create"));
+  *out = b;
+  return RTT_OK;
+}
+
+rtt_status rtt_batch_step(rtt_batch_t b, int32_t n_sweeps, double* esum, void* stream) {
+  g_err.clear();
+  if (!b) return fail(RTT_E_ARG, "rtt_batch_step: null batch");
+  if (n_sweeps < 0) return fail(RTT_E_ARG, "rtt_batch_step: n_sweeps < 0");
+  if (!b->exec || b->graph_sweeps != n_sweeps || b->graph_esum != esum) {
+    HIPX(hipDeviceSynchronize());
+    rtt_status st = capture(b, n_sweeps, esum);
+    if (st != RTT_OK) return st;
+  }
+  HIPX(hipGraphLaunch(b->exec, (hipStream_t)stream));
+  return RTT_OK;
+}
+
+rtt_status rtt_batch_autotune(rtt_batch_t b, int32_t n_sweeps, int32_t reps, const char* cache_path,
+                              int32_t* choice, void* stream) {
+  g_err.clear();
+  if (!b || reps < 1 || n_sweeps < 0) return fail(RTT_E_ARG, "rtt_batch_autotune: bad argument");
+  hipStream_t s = (hipStream_t)stream;
+  hipEvent_t e0, e1;
+  HIPX(hipEventCreate(&e0));
+  HIPX(hipEventCreate(&e1));
+  float best = 1e30f;
+  int best_conc = 0, best_occ = 1;
+  for (int conc = 0; conc < 2; ++conc)
+    for (int occ = 1; occ <= 4; ++occ) {
+      b->concurrent = conc;
+      b->occ = occ;
+      HIPX(hipDeviceSynchronize());
+      rtt_status st = capture(b, n_sweeps, nullptr);
+      if (st != RTT_OK) return st;
+      HIPX(hipGraphLaunch(b->exec, s));  // warm-up
+      HIPX(hipEventRecord(e0, s));
+      for (int r = 0; r < reps; ++r) HIPX(hipGraphLaunch(b->exec, s));
+      HIPX(hipEventRecord(e1, s));
+      HIPX(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIPX(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best) { best = ms; best_conc = conc; best_occ = occ; }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  b->concurrent = best_conc;
+  b->occ = best_occ;
+  if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+  if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+  if (choice) { choice[0] = best_conc; choice[1] = best_occ; }
+  if (cache_path) {
+    // append one JSON object per line: signature, choice, time per step
+    FILE* f = fopen(cache_path, "a");
+    if (f) {
+      fprintf(f, "{\"batch\": \"%s\", \"runs\": %d, \"sweeps\": %d, \"concurrent\": %d, \"blocks_per_cu\": %d, \"ms_per_step\": %.4f}\n",
+              batch_signature(b).c_str(), b->n, n_sweeps, best_conc, best_occ, best / reps);
+      fclose(f);
+    }
+  }
+  return RTT_OK;
+}
+
+rtt_status rtt_batch_destroy(rtt_batch_t b) {
+  if (!b) return RTT_OK;
+  HIPX(hipDeviceSynchronize());
+  free_batch(b);
+  delete b;
   return RTT_OK;
 }
 

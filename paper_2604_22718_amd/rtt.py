@@ -102,6 +102,35 @@ def rtt_energy_reduce(x, out):
     check(lib().rtt_energy_reduce(x.numel(), _ptr(x), _ptr(out), _stream()))
 
 
+def rtt_batch_create(rtts, hams, walkers, spins, eloc, seed):
+    n = len(rtts)
+    arr = lambda xs: (C.c_void_p * n)(*xs)
+    w = np.ascontiguousarray(walkers, dtype=np.int32)
+    b = C.c_void_p()
+    check(lib().rtt_batch_create(n, C.cast(arr([r.value for r in rtts]), C.c_void_p),
+                                 C.cast(arr([h.value for h in hams]), C.c_void_p), w.ctypes.data,
+                                 C.cast(arr([t.data_ptr() for t in spins]), C.c_void_p),
+                                 C.cast(arr([t.data_ptr() for t in eloc]), C.c_void_p),
+                                 int(seed), C.byref(b)))
+    return b
+
+
+def rtt_batch_step(b, n_sweeps, esum=None):
+    check(lib().rtt_batch_step(b, int(n_sweeps), _ptr(esum), _stream()))
+
+
+def rtt_batch_autotune(b, n_sweeps, reps, cache_path=None):
+    choice = np.zeros(2, dtype=np.int32)
+    check(lib().rtt_batch_autotune(b, int(n_sweeps), int(reps),
+                                   cache_path.encode() if cache_path else None,
+                                   choice.ctypes.data, _stream()))
+    return int(choice[0]), int(choice[1])
+
+
+def rtt_batch_destroy(b):
+    check(lib().rtt_batch_destroy(b))
+
+
 # ---------------------------------------------------------------- convenience
 class TFIM:
     """H = J sum_<ij> Z_i Z_j - h sum_i X_i on an Lx x Ly lattice."""
@@ -197,6 +226,36 @@ class RTT:
               logabs=None, sign=None):
         rtt_mcmc_sweep(self.handle, spins, seed, rng_stream, sweep0, n_sweeps, logabs, sign,
                        accepts, status)
+
+
+class Batch:
+    """Many independent RTT chains stepped together in one captured graph.
+    Owns the spin and local-energy buffers of every run."""
+
+    def __init__(self, rtts, hams, spins, seed):
+        self.rtts, self.hams = rtts, hams
+        self.spins = [s.contiguous() for s in spins]
+        self.eloc = [torch.empty(s.shape[0], dtype=torch.float64, device=s.device) for s in self.spins]
+        self.esum = torch.zeros(len(rtts), 3, dtype=torch.float64, device=self.spins[0].device)
+        self.handle = rtt_batch_create([r.handle for r in rtts], [h.handle for h in hams],
+                                       [s.shape[0] for s in self.spins], self.spins, self.eloc, seed)
+
+    def step(self, n_sweeps=1, esum=True):
+        rtt_batch_step(self.handle, n_sweeps, self.esum if esum else None)
+
+    def autotune(self, n_sweeps=1, reps=2, cache_path=None):
+        return rtt_batch_autotune(self.handle, n_sweeps, reps, cache_path)
+
+    def close(self):
+        if self.handle is not None:
+            rtt_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def energy_reduce(x):

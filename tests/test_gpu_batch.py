@@ -1,0 +1,100 @@
+"""Batched persistent launch: many uneven RTT chains in one captured graph give
+bit-identical results to stepping each RTT on its own through the C ABI
+(which is itself parity-tested against the oracle), on every graph replay."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from helpers import case, device_cores
+from oracle import rtt as orc, tfim
+from paper_2604_22718_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+RUNS = [  # Lx, Ly, R, chi, dtype, W
+    (3, 3, 2, 16, "f32", 40),
+    (4, 4, 3, 32, "bf16", 70),
+    (4, 3, 2, 64, "bf16", 33),
+    (4, 4, 2, 32, "bf16", 100),
+    (5, 4, 2, 32, "fp8", 17),
+    (4, 4, 2, 8, "f32", 64),
+]
+
+
+@pytest.fixture(scope="module")
+def R():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2604_22718_amd import rtt
+    return rtt
+
+
+def build(R):
+    rtts, hams, spins, meta = [], [], [], []
+    for i, (Lx, Ly, Rr, chi, dtype, W) in enumerate(RUNS):
+        N = Lx * Ly
+        pi, bond, cores = case(N, Rr, chi, "perm", seed=40 + i)
+        rtts.append(R.RTT.create(N, pi, cores, dtype))
+        hams.append(R.TFIM(Lx, Ly, 1.0, 2.0 + 0.3 * i))
+        spins.append(R.spins_to_device(wl.pack_spins(wl.random_spins(W, N, 50 + i))))
+        meta.append((pi, bond, N, Lx, Ly, 2.0 + 0.3 * i))
+    return rtts, hams, spins, meta
+
+
+def test_batch_equals_individual_runs(R):
+    rtts, hams, spins, meta = build(R)
+    ref_spins = [s.clone() for s in spins]
+    batch = R.Batch(rtts, hams, spins, seed=777)
+    for rep in range(3):
+        batch.step(n_sweeps=2)
+        torch.cuda.synchronize()
+        # eager reference between replays: each run on its own
+        for i, r in enumerate(rtts):
+            r.sweep(ref_spins[i], seed=777, rng_stream=i, sweep0=2 * rep, n_sweeps=2)
+            e = r.local_energy(ref_spins[i], hams[i])
+            torch.cuda.synchronize()
+            assert torch.equal(batch.spins[i], ref_spins[i]), (rep, i)
+            assert torch.equal(batch.eloc[i], e), (rep, i)
+            es = batch.esum[i].cpu().numpy()
+            ev = e.cpu().numpy()
+            assert es[2] == len(ev)
+            assert abs(es[0] - math.fsum(ev)) <= 1e-12 * max(1.0, abs(math.fsum(np.abs(ev))))
+    batch.close()
+
+
+def test_batch_energies_match_oracle_on_a_sample(R):
+    rtts, hams, spins, meta = build(R)
+    batch = R.Batch(rtts, hams, spins, seed=5)
+    batch.step(n_sweeps=1)
+    torch.cuda.synchronize()
+    for i in (0, 3, 4):
+        pi, bond, N, Lx, Ly, h = meta[i]
+        qc = device_cores(rtts[i], bond)
+        bits = wl.unpack_spins(R.spins_to_host(batch.spins[i]), N)[:6]
+        el = orc.local_energy(qc, pi, bits, tfim.bonds(Lx, Ly), 1.0, h)
+        kap = orc.flip_condition_numbers(qc, pi, bits).max(axis=1)
+        tol = 1e-5 if RUNS[i][4] == "f32" else 2e-2
+        got = batch.eloc[i].cpu().numpy()[:6]
+        assert np.all(np.abs(got - el) / np.maximum(1, np.abs(el)) <= tol * np.maximum(1, kap / 10))
+    batch.close()
+
+
+def test_autotune_picks_a_shape_and_keeps_results_exact(R, tmp_path):
+    rtts, hams, spins, meta = build(R)
+    ref_spins = [s.clone() for s in spins]
+    batch = R.Batch(rtts, hams, spins, seed=11)
+    conc, occ = batch.autotune(n_sweeps=1, reps=1, cache_path=str(tmp_path / "tune.jsonl"))
+    assert conc in (0, 1) and 1 <= occ <= 4
+    assert (tmp_path / "tune.jsonl").read_text().count("blocks_per_cu") == 1
+    # autotuning ran 8 shapes x (1 warm-up + 1 timed) steps of 1 sweep
+    n_done = 16
+    batch.step(n_sweeps=1)
+    torch.cuda.synchronize()
+    for i, r in enumerate(rtts):
+        r.sweep(ref_spins[i], seed=11, rng_stream=i, sweep0=0, n_sweeps=n_done + 1)
+    torch.cuda.synchronize()
+    for i in range(len(rtts)):
+        assert torch.equal(batch.spins[i], ref_spins[i]), i
+    batch.close()
