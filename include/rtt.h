@@ -203,6 +203,64 @@ rtt_status rtt_batch_autotune(rtt_batch_t b, int32_t n_sweeps, int32_t reps,
                               const char* cache_path, int32_t* choice, void* stream);
 rtt_status rtt_batch_destroy(rtt_batch_t b);
 
+/*
+ * Learned multi-spin proposal (a sampler for P = |psi|^2 / Z, Sec. 3.3; the
+ * paper leaves the proposal open).  Network: input z = 1 - 2 s on the
+ * periodic Lx x Ly lattice (Lx, Ly >= 3, Lx*Ly <= 256), three 3x3 circular
+ * convolutions with 32 channels and SiLU, a 1x1 head with 9 outputs per
+ * site: o[0] centre logits, o[1..8] logits of the move size k = 1..8.
+ * params (host double[19113]): W1[32][1][3][3], b1[32], W2[32][32][3][3], b2,
+ * W3[32][32][3][3], b3, Wh[9][32], bh[9], row-major, concatenated.  The
+ * library keeps FP32 master weights and uses them rounded to BF16 (FP32
+ * accumulation) in every forward pass.
+ * A move samples a centre c ~ softmax(o[0]) and k ~ softmax(o[1..8][c]) and
+ * flips the first k sites of the spiral (dx,dy) = (0,0),(1,0),(1,1),(0,1),
+ * (-1,1),(-1,0),(-1,-1),(0,-1) around c.  It is accepted iff
+ *   u < |psi(s')/psi(s)|^2 q(S|s') / q(S|s),
+ * q(S|.) being the exact probability of the flipped set S (summed over every
+ * (c', k) giving S).  Uniforms: word 0 of Philox4x64-10, key (seed,
+ * rng_stream), counter (walker, step, 2^32 + i, 0), i = 0 centre, 1 size,
+ * 2 acceptance; inverse-CDF sampling.
+ */
+typedef struct rtt_net_s* rtt_net_t;
+
+rtt_status rtt_net_create(int32_t Lx, int32_t Ly, const double* params, rtt_net_t* out);
+rtt_status rtt_net_destroy(rtt_net_t net);
+/* which = 0: FP32 master weights, 1: the BF16-rounded weights in use (host double[19113]) */
+rtt_status rtt_net_get_params(rtt_net_t net, int32_t which, double* out);
+/* head outputs for W configurations: device float[W][9][Lx*Ly] */
+rtt_status rtt_net_forward(rtt_net_t net, int32_t W, const uint64_t* spins, float* out, void* stream);
+/*
+ * One learned-proposal Metropolis-Hastings step for W walkers.
+ *   spins   device uint64[W][ceil(N/64)], updated in place
+ *   logabs, sign  device in/out: log|psi| and sign of the current spins
+ *           (e.g. from rtt_amplitudes or rtt_mcmc_sweep); updated on acceptance
+ *   moves   device int32[W] or NULL: c | (k << 16) proposed
+ *   accept_prob device float[W] or NULL: min(1, MH ratio)
+ *   before  device uint64[W][ceil(N/64)] or NULL: the states the moves were
+ *           proposed at (the training inputs)
+ *   accepts device uint32[W] or NULL (incremented), status int32[W] or NULL
+ */
+rtt_status rtt_mh_learned_step(rtt_t h, rtt_net_t net, int32_t W, uint64_t* spins, double* logabs,
+                               int8_t* sign, uint64_t seed, uint64_t rng_stream, uint64_t step,
+                               int32_t* moves, float* accept_prob, uint64_t* before,
+                               uint32_t* accepts, int32_t* status, void* stream);
+/*
+ * Gradient (device float[19113]) of sum_b c_b log q(c_b, k_b | s_b) with
+ * c_b = -(accept_prob_b * k_b - baseline) / B: the score-function estimate
+ * of minus the expected accepted move size.  spins are the states s_b the
+ * moves were proposed at.  baseline is the library's running mean of
+ * accept_prob * k.
+ */
+rtt_status rtt_net_grad(rtt_net_t net, int32_t B, const uint64_t* spins, const int32_t* moves,
+                        const float* accept_prob, float* grad, void* stream);
+/* One training step: the gradient above, then the baseline update
+   (0.9 old + 0.1 batch mean) and one Adam step (beta1, beta2, eps) on the
+   master weights with learning rate lr. */
+rtt_status rtt_net_train(rtt_net_t net, int32_t B, const uint64_t* spins, const int32_t* moves,
+                         const float* accept_prob, float lr, float beta1, float beta2, float eps,
+                         void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -36,6 +36,14 @@ SIGNATURES = {
     "rtt_batch_step": (C.c_int, [P, C.c_int32, P, P]),
     "rtt_batch_autotune": (C.c_int, [P, C.c_int32, C.c_int32, C.c_char_p, P, P]),
     "rtt_batch_destroy": (C.c_int, [P]),
+    "rtt_net_create": (C.c_int, [C.c_int32, C.c_int32, P, C.POINTER(P)]),
+    "rtt_net_destroy": (C.c_int, [P]),
+    "rtt_net_get_params": (C.c_int, [P, C.c_int32, P]),
+    "rtt_net_forward": (C.c_int, [P, C.c_int32, P, P, P]),
+    "rtt_mh_learned_step": (C.c_int, [P, P, C.c_int32, P, P, P, C.c_uint64, C.c_uint64, C.c_uint64,
+                                      P, P, P, P, P, P]),
+    "rtt_net_grad": (C.c_int, [P, C.c_int32, P, P, P, P, P]),
+    "rtt_net_train": (C.c_int, [P, C.c_int32, P, P, P, C.c_float, C.c_float, C.c_float, C.c_float, P]),
 }
 
 

@@ -13,6 +13,7 @@
 
 #include "../../include/rtt.h"
 #include "rtt_kernels.hpp"
+#include "rtt_net.hpp"
 
 namespace {
 
@@ -1122,6 +1123,211 @@ rtt_status rtt_batch_destroy(rtt_batch_t b) {
   HIPX(hipDeviceSynchronize());
   free_batch(b);
   delete b;
+  return RTT_OK;
+}
+
+}  // extern "C"
+
+// ============================================================================
+// learned proposal
+// ============================================================================
+struct rtt_net_s {
+  int Lx = 0, Ly = 0, N = 0, nw = 0;
+  float* d_master = nullptr;
+  float* d_infer = nullptr;
+  float* d_m = nullptr;
+  float* d_v = nullptr;
+  float* d_grad = nullptr;
+  double* d_baseline = nullptr;
+  int t = 0;
+  int W_ws = 0, B_ws = 0;
+  uint64_t* d_prop = nullptr;
+  int* d_moves = nullptr;
+  double* d_lqf = nullptr;
+  double* d_lqr = nullptr;
+  double* d_la = nullptr;
+  int8_t* d_sg = nullptr;
+  int32_t* d_st = nullptr;
+  float* d_partial = nullptr;
+};
+
+namespace {
+
+void free_net(rtt_net_s* n) {
+  for (void* p : {(void*)n->d_master, (void*)n->d_infer, (void*)n->d_m, (void*)n->d_v, (void*)n->d_grad,
+                  (void*)n->d_baseline, (void*)n->d_prop, (void*)n->d_moves, (void*)n->d_lqf,
+                  (void*)n->d_lqr, (void*)n->d_la, (void*)n->d_sg, (void*)n->d_st, (void*)n->d_partial})
+    if (p) (void)hipFree(p);
+}
+
+rtt_status net_ws(rtt_net_s* n, int W) {
+  if (W <= n->W_ws) return RTT_OK;
+  for (void* p : {(void*)n->d_prop, (void*)n->d_moves, (void*)n->d_lqf, (void*)n->d_lqr, (void*)n->d_la,
+                  (void*)n->d_sg, (void*)n->d_st})
+    if (p) HIPX(hipFree(p));
+  HIPX(hipMalloc(&n->d_prop, (size_t)W * n->nw * 8));
+  HIPX(hipMalloc(&n->d_moves, (size_t)W * 4));
+  HIPX(hipMalloc(&n->d_lqf, (size_t)W * 8));
+  HIPX(hipMalloc(&n->d_lqr, (size_t)W * 8));
+  HIPX(hipMalloc(&n->d_la, (size_t)W * 8));
+  HIPX(hipMalloc(&n->d_sg, (size_t)W));
+  HIPX(hipMalloc(&n->d_st, (size_t)W * 4));
+  n->W_ws = W;
+  return RTT_OK;
+}
+
+rtt_status net_set_lds(const void* f, size_t bytes) {
+  HIPX(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  return RTT_OK;
+}
+
+rtt_status net_grad_launch(rtt_net_s* n, int B, const uint64_t* spins, const int32_t* moves,
+                           const float* accept_prob, float* grad, hipStream_t s) {
+  if (B > n->B_ws) {
+    if (n->d_partial) HIPX(hipFree(n->d_partial));
+    n->d_partial = nullptr;
+    n->B_ws = 0;
+    HIPX(hipMalloc(&n->d_partial, (size_t)B * rttk::kNetParams * 4));
+    n->B_ws = B;
+  }
+  rttk::NetGradArgs ga{};
+  ga.P = n->d_infer; ga.Lx = n->Lx; ga.Ly = n->Ly; ga.nw = n->nw; ga.B = B;
+  ga.spins = spins; ga.moves = moves; ga.accept_prob = accept_prob; ga.baseline = n->d_baseline;
+  ga.partial = n->d_partial;
+  const size_t lds = rttk::net_grad_lds_bytes(n->N);
+  rtt_status st = net_set_lds((const void*)rttk::net_grad_kernel, lds);
+  if (st != RTT_OK) return st;
+  hipLaunchKernelGGL(rttk::net_grad_kernel, dim3(B), dim3(256), lds, s, ga);
+  HIPX(hipGetLastError());
+  hipLaunchKernelGGL(rttk::net_reduce_kernel, dim3((rttk::kNetParams + 255) / 256), dim3(256), 0, s,
+                     n->d_partial, B, grad);
+  HIPX(hipGetLastError());
+  return RTT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rtt_status rtt_net_create(int32_t Lx, int32_t Ly, const double* params, rtt_net_t* out) {
+  g_err.clear();
+  if (!out) return fail(RTT_E_ARG, "rtt_net_create: out is null");
+  *out = nullptr;
+  if (Lx < 3 || Ly < 3 || Lx * Ly > 256) return fail(RTT_E_ARG, "rtt_net_create: lattice %dx%d (need sides >= 3, <= 256 sites)", Lx, Ly);
+  if (!params) return fail(RTT_E_ARG, "rtt_net_create: params is null");
+  std::vector<float> m(rttk::kNetParams), inf(rttk::kNetParams);
+  for (int p = 0; p < rttk::kNetParams; ++p) {
+    if (!isfinite(params[p])) return fail(RTT_E_ARG, "rtt_net_create: parameter %d not finite", p);
+    m[p] = (float)params[p];
+    inf[p] = (float)bf16_value(bf16_bits_rne(m[p]));
+  }
+  rtt_net_s* n = new rtt_net_s;
+  n->Lx = Lx; n->Ly = Ly; n->N = Lx * Ly; n->nw = (n->N + 63) / 64;
+  std::vector<float> zeros(rttk::kNetParams, 0.f);
+  double zb = 0.0;
+  rtt_status st;
+  if ((st = upload((void**)&n->d_master, m.data(), m.size() * 4)) != RTT_OK ||
+      (st = upload((void**)&n->d_infer, inf.data(), inf.size() * 4)) != RTT_OK ||
+      (st = upload((void**)&n->d_m, zeros.data(), zeros.size() * 4)) != RTT_OK ||
+      (st = upload((void**)&n->d_v, zeros.data(), zeros.size() * 4)) != RTT_OK ||
+      (st = upload((void**)&n->d_grad, zeros.data(), zeros.size() * 4)) != RTT_OK ||
+      (st = upload((void**)&n->d_baseline, &zb, 8)) != RTT_OK) {
+    free_net(n);
+    delete n;
+    return st;
+  }
+  *out = n;
+  return RTT_OK;
+}
+
+rtt_status rtt_net_destroy(rtt_net_t n) {
+  if (!n) return RTT_OK;
+  HIPX(hipDeviceSynchronize());
+  free_net(n);
+  delete n;
+  return RTT_OK;
+}
+
+rtt_status rtt_net_get_params(rtt_net_t n, int32_t which, double* out) {
+  g_err.clear();
+  if (!n || !out || which < 0 || which > 1) return fail(RTT_E_ARG, "rtt_net_get_params: bad argument");
+  std::vector<float> h(rttk::kNetParams);
+  HIPX(hipDeviceSynchronize());
+  HIPX(hipMemcpy(h.data(), which == 0 ? n->d_master : n->d_infer, h.size() * 4, hipMemcpyDeviceToHost));
+  for (int p = 0; p < rttk::kNetParams; ++p) out[p] = h[p];
+  return RTT_OK;
+}
+
+rtt_status rtt_net_forward(rtt_net_t n, int32_t W, const uint64_t* spins, float* out, void* stream) {
+  g_err.clear();
+  if (!n || W < 1 || !spins || !out) return fail(RTT_E_ARG, "rtt_net_forward: bad argument");
+  rttk::NetMoveArgs a{};
+  a.P = n->d_infer; a.Lx = n->Lx; a.Ly = n->Ly; a.nw = n->nw; a.W = W; a.spins = spins; a.out = out;
+  const size_t lds = rttk::net_lds_bytes(n->N);
+  rtt_status st = net_set_lds((const void*)rttk::net_forward_kernel, lds);
+  if (st != RTT_OK) return st;
+  hipLaunchKernelGGL(rttk::net_forward_kernel, dim3(W), dim3(256), lds, (hipStream_t)stream, a);
+  HIPX(hipGetLastError());
+  return RTT_OK;
+}
+
+rtt_status rtt_mh_learned_step(rtt_t h, rtt_net_t n, int32_t W, uint64_t* spins, double* logabs,
+                               int8_t* sign, uint64_t seed, uint64_t rng_stream, uint64_t step,
+                               int32_t* moves, float* accept_prob, uint64_t* before,
+                               uint32_t* accepts, int32_t* status, void* stream) {
+  g_err.clear();
+  if (check_handle(h) != RTT_OK) return RTT_E_ARG;
+  if (!n || W < 1 || !spins || !logabs || !sign) return fail(RTT_E_ARG, "rtt_mh_learned_step: bad argument");
+  if (n->N != h->N) return fail(RTT_E_ARG, "rtt_mh_learned_step: network has %d sites, RTT %d spins", n->N, h->N);
+  hipStream_t s = (hipStream_t)stream;
+  rtt_status st = net_ws(n, W);
+  if (st != RTT_OK) return st;
+  rttk::NetMoveArgs a{};
+  a.P = n->d_infer; a.Lx = n->Lx; a.Ly = n->Ly; a.nw = n->nw; a.W = W; a.spins = spins;
+  a.prop = n->d_prop; a.moves = moves ? moves : n->d_moves; a.lqf = n->d_lqf; a.lqr = n->d_lqr;
+  a.seed = seed; a.rstream = rng_stream; a.step = step; a.before = before;
+  const size_t lds = rttk::net_lds_bytes(n->N);
+  if ((st = net_set_lds((const void*)rttk::net_propose_kernel, lds)) != RTT_OK) return st;
+  if ((st = net_set_lds((const void*)rttk::net_reverse_kernel, lds)) != RTT_OK) return st;
+  hipLaunchKernelGGL(rttk::net_propose_kernel, dim3(W), dim3(256), lds, s, a);
+  HIPX(hipGetLastError());
+  hipLaunchKernelGGL(rttk::net_reverse_kernel, dim3(W), dim3(256), lds, s, a);
+  HIPX(hipGetLastError());
+  st = chain_common(h, W, n->d_prop, n->d_la, n->d_sg, 0, 0, 0, 0, nullptr, n->d_st, 0, stream);
+  if (st != RTT_OK) return st;
+  rttk::NetAcceptArgs c{};
+  c.W = W; c.nw = n->nw; c.spins = spins; c.prop = n->d_prop; c.logabs = logabs; c.sign = sign;
+  c.la_new = n->d_la; c.sg_new = n->d_sg; c.st_new = n->d_st; c.lqf = n->d_lqf; c.lqr = n->d_lqr;
+  c.moves = a.moves; c.accept_prob = accept_prob; c.accepts = accepts; c.status = status;
+  c.seed = seed; c.rstream = rng_stream; c.step = step;
+  hipLaunchKernelGGL(rttk::net_accept_kernel, dim3((W + 255) / 256), dim3(256), 0, s, c);
+  HIPX(hipGetLastError());
+  return RTT_OK;
+}
+
+rtt_status rtt_net_grad(rtt_net_t n, int32_t B, const uint64_t* spins, const int32_t* moves,
+                        const float* accept_prob, float* grad, void* stream) {
+  g_err.clear();
+  if (!n || B < 1 || !spins || !moves || !accept_prob || !grad) return fail(RTT_E_ARG, "rtt_net_grad: bad argument");
+  return net_grad_launch(n, B, spins, moves, accept_prob, grad, (hipStream_t)stream);
+}
+
+rtt_status rtt_net_train(rtt_net_t n, int32_t B, const uint64_t* spins, const int32_t* moves,
+                         const float* accept_prob, float lr, float beta1, float beta2, float eps,
+                         void* stream) {
+  g_err.clear();
+  if (!n || B < 1 || !spins || !moves || !accept_prob) return fail(RTT_E_ARG, "rtt_net_train: bad argument");
+  if (!(lr >= 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+    return fail(RTT_E_ARG, "rtt_net_train: bad optimiser constants");
+  hipStream_t s = (hipStream_t)stream;
+  rtt_status st = net_grad_launch(n, B, spins, moves, accept_prob, n->d_grad, s);
+  if (st != RTT_OK) return st;
+  hipLaunchKernelGGL(rttk::net_baseline_kernel, dim3(1), dim3(256), 0, s, accept_prob, moves, B, n->d_baseline);
+  HIPX(hipGetLastError());
+  n->t += 1;
+  hipLaunchKernelGGL(rttk::net_adam_kernel, dim3((rttk::kNetParams + 255) / 256), dim3(256), 0, s, n->d_master,
+                     n->d_infer, n->d_m, n->d_v, n->d_grad, lr, beta1, beta2, eps, n->t);
+  HIPX(hipGetLastError());
   return RTT_OK;
 }
 

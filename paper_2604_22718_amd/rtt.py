@@ -131,6 +131,48 @@ def rtt_batch_destroy(b):
     check(lib().rtt_batch_destroy(b))
 
 
+N_NET_PARAMS = 19113
+
+
+def rtt_net_create(Lx, Ly, params):
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    assert p.size == N_NET_PARAMS
+    h = C.c_void_p()
+    check(lib().rtt_net_create(int(Lx), int(Ly), p.ctypes.data, C.byref(h)))
+    return h
+
+
+def rtt_net_destroy(h):
+    check(lib().rtt_net_destroy(h))
+
+
+def rtt_net_get_params(h, which=0):
+    out = np.zeros(N_NET_PARAMS, dtype=np.float64)
+    check(lib().rtt_net_get_params(h, int(which), out.ctypes.data))
+    return out
+
+
+def rtt_net_forward(h, spins, out):
+    check(lib().rtt_net_forward(h, spins.shape[0], _ptr(spins), _ptr(out), _stream()))
+
+
+def rtt_mh_learned_step(rtt_h, net_h, spins, logabs, sign, seed, rng_stream, step, moves=None,
+                        accept_prob=None, before=None, accepts=None, status=None):
+    check(lib().rtt_mh_learned_step(rtt_h, net_h, spins.shape[0], _ptr(spins), _ptr(logabs), _ptr(sign),
+                                    int(seed), int(rng_stream), int(step), _ptr(moves), _ptr(accept_prob),
+                                    _ptr(before), _ptr(accepts), _ptr(status), _stream()))
+
+
+def rtt_net_grad(h, spins, moves, accept_prob, grad):
+    check(lib().rtt_net_grad(h, spins.shape[0], _ptr(spins), _ptr(moves), _ptr(accept_prob), _ptr(grad),
+                             _stream()))
+
+
+def rtt_net_train(h, spins, moves, accept_prob, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    check(lib().rtt_net_train(h, spins.shape[0], _ptr(spins), _ptr(moves), _ptr(accept_prob),
+                              float(lr), float(beta1), float(beta2), float(eps), _stream()))
+
+
 # ---------------------------------------------------------------- convenience
 class TFIM:
     """H = J sum_<ij> Z_i Z_j - h sum_i X_i on an Lx x Ly lattice."""
@@ -226,6 +268,68 @@ class RTT:
               logabs=None, sign=None):
         rtt_mcmc_sweep(self.handle, spins, seed, rng_stream, sweep0, n_sweeps, logabs, sign,
                        accepts, status)
+
+
+class Net:
+    """Learned multi-spin proposal network resident on the GPU."""
+
+    def __init__(self, Lx, Ly, params):
+        self.Lx, self.Ly, self.N = Lx, Ly, Lx * Ly
+        self.handle = rtt_net_create(Lx, Ly, params)
+
+    def params(self, which=0):
+        return rtt_net_get_params(self.handle, which)
+
+    def forward(self, spins):
+        out = torch.empty(spins.shape[0], 9, self.N, dtype=torch.float32, device=spins.device)
+        rtt_net_forward(self.handle, spins, out)
+        return out
+
+    def close(self):
+        if self.handle is not None:
+            rtt_net_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class LearnedChain:
+    """Walkers sampled by single-flip sweeps and learned multi-spin moves;
+    all arithmetic in the library's kernels, this class only sequences calls
+    and owns the buffers."""
+
+    def __init__(self, psi, net, spins, seed, rng_stream=0):
+        self.psi, self.net, self.seed, self.rs = psi, net, seed, rng_stream
+        self.spins = spins
+        W, dev = spins.shape[0], spins.device
+        self.logabs = torch.empty(W, dtype=torch.float64, device=dev)
+        self.sign = torch.empty(W, dtype=torch.int8, device=dev)
+        self.moves = torch.empty(W, dtype=torch.int32, device=dev)
+        self.aprob = torch.empty(W, dtype=torch.float32, device=dev)
+        self.before = torch.empty_like(spins)
+        self.acc_flip = torch.zeros(W, dtype=torch.int32, device=dev)
+        self.acc_learn = torch.zeros(W, dtype=torch.int32, device=dev)
+        self.sweeps = 0
+        self.steps = 0
+        rtt_amplitudes(psi.handle, spins, self.logabs, self.sign)
+
+    def sweep(self, n=1):
+        rtt_mcmc_sweep(self.psi.handle, self.spins, self.seed, self.rs, self.sweeps, n,
+                       self.logabs, self.sign, self.acc_flip)
+        self.sweeps += n
+
+    def learned_step(self):
+        rtt_mh_learned_step(self.psi.handle, self.net.handle, self.spins, self.logabs, self.sign,
+                            self.seed, self.rs, self.steps, self.moves, self.aprob, self.before,
+                            self.acc_learn)
+        self.steps += 1
+
+    def train(self, lr=1e-3):
+        rtt_net_train(self.net.handle, self.before, self.moves, self.aprob, lr)
 
 
 class Batch:

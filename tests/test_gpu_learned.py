@@ -1,0 +1,181 @@
+"""Learned multi-spin proposal on the GPU against the FP64 oracle: network
+outputs, REINFORCE gradients, Adam, the MH step's moves and decisions,
+unbiasedness of the mixed chain, and what training gains."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from helpers import device_cores
+from oracle import mcmc, net as onet, rtt as orc, stats, tfim
+from paper_2604_22718_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def R():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2604_22718_amd import rtt
+    return rtt
+
+
+def params(seed, scale=0.2):
+    return onet.init_params(seed) + scale * np.random.default_rng(seed).standard_normal(onet.N_PARAMS)
+
+
+@pytest.mark.parametrize("Lx,Ly", [(4, 4), (5, 3), (10, 10), (16, 16)])
+def test_forward_matches_oracle(R, Lx, Ly):
+    net = R.Net(Lx, Ly, params(1))
+    p16 = net.params(1)                      # the BF16-rounded weights in use
+    assert np.array_equal(p16, torch.tensor(net.params(0)).to(torch.float32)
+                          .to(torch.bfloat16).to(torch.float64).numpy())
+    bits = wl.random_spins(5, Lx * Ly, 2)
+    out = net.forward(R.spins_to_device(wl.pack_spins(bits))).cpu().numpy()
+    ref = onet.forward(p16, bits, Lx, Ly)
+    err = np.abs(out - ref).max() / np.abs(ref).max()
+    assert err < 2e-6, err
+
+
+def test_gradient_matches_oracle(R):
+    Lx, Ly, B = 5, 4, 6
+    net = R.Net(Lx, Ly, params(3))
+    p16 = net.params(1)
+    bits = wl.random_spins(B, Lx * Ly, 4)
+    g = np.random.default_rng(5)
+    moves = [(int(g.integers(0, Lx * Ly)), int(g.integers(1, 9))) for _ in range(B)]
+    aprob = g.uniform(0, 1, B).astype(np.float32)
+    mv = torch.tensor([c | (k << 16) for c, k in moves], dtype=torch.int32, device="cuda")
+    grad = torch.zeros(onet.N_PARAMS, dtype=torch.float32, device="cuda")
+    R.rtt_net_grad(net.handle, R.spins_to_device(wl.pack_spins(bits)), mv,
+                   torch.from_numpy(aprob).cuda(), grad)
+    coef = -(aprob.astype(np.float64) * np.array([k for _, k in moves]) - 0.0) / B
+    ref = onet.reinforce_grad(p16, bits, moves, coef, Lx, Ly)
+    got = grad.cpu().numpy()
+    rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+    assert rel < 1e-5, rel
+    assert np.abs(got - ref).max() < 1e-4 * np.abs(ref).max()
+
+
+def test_adam_step_matches_oracle(R):
+    Lx, Ly, B = 4, 4, 4
+    p0 = params(7)
+    net = R.Net(Lx, Ly, p0)
+    master0 = net.params(0)
+    p16 = net.params(1)
+    bits = wl.random_spins(B, 16, 8)
+    moves = [(3, 2), (0, 8), (15, 1), (9, 5)]
+    aprob = np.array([0.3, 0.9, 0.1, 0.5], dtype=np.float32)
+    mv = torch.tensor([c | (k << 16) for c, k in moves], dtype=torch.int32, device="cuda")
+    R.rtt_net_train(net.handle, R.spins_to_device(wl.pack_spins(bits)), mv,
+                    torch.from_numpy(aprob).cuda(), lr=1e-3)
+    torch.cuda.synchronize()
+    coef = -(aprob.astype(np.float64) * np.array([k for _, k in moves])) / B
+    g = onet.reinforce_grad(p16, bits, moves, coef, Lx, Ly)
+    want, _, _ = onet.adam(master0, np.zeros_like(g), np.zeros_like(g), g, 1, lr=1e-3)
+    got = net.params(0)
+    # first Adam step moves each weight by ~lr in the direction of -grad
+    big = np.abs(g) > 1e-3 * np.abs(g).max()
+    assert np.allclose(got[big], want[big], atol=2e-6)
+    assert np.all(np.abs(got - master0) <= 1e-3 * (1 + 1e-5))
+
+
+def test_learned_step_matches_oracle(R):
+    """Same seeds: GPU and oracle propose the same moves and make the same
+    accept decisions, except where a uniform falls within 1e-5 of a cut."""
+    Lx, Ly, Rr, chi, W = 4, 4, 2, 8, 48
+    N = 16
+    pi = wl.path_site_plus_perms(N, Rr, 12)
+    bond = wl.open_bonds(N * Rr, chi)
+    cores = wl.gaussian_cores(bond, 13)
+    psi = R.RTT.create(N, pi, cores, "f32")
+    qc = device_cores(psi, bond)
+    net = R.Net(Lx, Ly, params(14, 0.5))
+    p16 = net.params(1)
+    bits = wl.random_spins(W, N, 15)
+    spins = R.spins_to_device(wl.pack_spins(bits))
+    ch = R.LearnedChain(psi, net, spins, seed=99, rng_stream=3)
+    ch.learned_step()
+    torch.cuda.synchronize()
+    got_moves = ch.moves.cpu().numpy()
+    got_bits = wl.unpack_spins(R.spins_to_host(ch.spins), N)
+    amp = lambda S: orc.amplitudes(qc, pi, S)
+    ref_bits, ref_moves, a, acc, margin = onet.mh_step(p16, amp, bits, Lx, Ly, seed=99, stream=3, step=0)
+    # sampling near-ties: recompute the cumulative distributions in FP64
+    o = onet.forward(p16, bits, Lx, Ly)
+    clean = np.abs(margin) > 1e-5
+    for b in range(W):
+        pc = np.cumsum(np.exp(onet.log_softmax(o[b, 0], 0)))
+        uc = onet.uniform(99, 3, b, 0, 0)
+        c, k = ref_moves[b]
+        pk = np.cumsum(np.exp(onet.log_softmax(o[b, 1:9, c], 0)))
+        uk = onet.uniform(99, 3, b, 0, 1)
+        if np.min(np.abs(pc - uc)) < 1e-5 or np.min(np.abs(pk - uk)) < 1e-5:
+            clean[b] = False
+    assert clean.sum() >= W - 2
+    for b in np.where(clean)[0]:
+        c, k = ref_moves[b]
+        assert got_moves[b] == (c | (k << 16)), b
+    assert np.array_equal(got_bits[clean], ref_bits[clean])
+    assert 0 < acc.sum() < W          # some moves accepted, some rejected
+
+
+def test_mixed_chain_is_unbiased(R):
+    """4x4, R=2, chi=8: single-flip sweeps alternating with learned moves
+    (fixed random network) reproduce the exact <H> within 3 sigma."""
+    w = wl.SMALL_4x4
+    pi, bond, cores = w.pi(), w.bond(), w.cores()
+    psi = R.RTT.create(w.N, pi, cores, "f32")
+    qc = device_cores(psi, bond)
+    exact = orc.exact_energy(qc, pi, w.N, tfim.bonds(4, 4), w.J, w.h)
+    ham = R.TFIM(4, 4, w.J, w.h)
+    net = R.Net(4, 4, params(21, 0.5))
+    ch = R.LearnedChain(psi, net, R.spins_to_device(wl.pack_spins(wl.random_spins(256, 16, 22))), seed=23)
+    for _ in range(20):
+        ch.sweep(1)
+        for _ in range(4):
+            ch.learned_step()
+    series = []
+    for _ in range(150):
+        ch.sweep(1)
+        for _ in range(4):
+            ch.learned_step()
+        series.append(psi.local_energy(ch.spins, ham))
+    E = torch.stack(series).cpu().numpy()
+    mean, sigma, tau, _ = stats.energy_estimate(E)
+    print(f"mixed chain <E> {mean:.5f} +- {sigma:.5f} exact {exact:.5f} tau {tau:.2f}")
+    assert abs(mean - exact) < 3 * sigma
+    assert ch.acc_learn.sum().item() > 0
+
+
+def test_training_increases_accepted_move_size(R):
+    """Online training on the chain's own states raises the mean accepted
+    move size E[a k] of the learned proposal (6x6, R=2, chi=16)."""
+    Lx = Ly = 6
+    N = 36
+    pi = wl.path_site_plus_perms(N, 2, 31)
+    cores = wl.gaussian_cores(wl.open_bonds(2 * N, 16), 32)
+    psi = R.RTT.create(N, pi, cores, "f32")
+    net = R.Net(Lx, Ly, onet.init_params(33))
+    ch = R.LearnedChain(psi, net, R.spins_to_device(wl.pack_spins(wl.random_spins(1024, N, 34))), seed=35)
+    ch.sweep(10)
+
+    def measure(n=20):
+        vals = []
+        for _ in range(n):
+            ch.learned_step()
+            k = (ch.moves >> 16).to(torch.float32)
+            vals.append((ch.aprob * k).mean())
+        return torch.stack(vals).mean().item()
+
+    before = measure()
+    for it in range(300):
+        ch.learned_step()
+        ch.train(lr=3e-3)
+        if it % 10 == 0:
+            ch.sweep(1)
+    after = measure()
+    print(f"E[a k] before {before:.4f} after {after:.4f}")
+    assert after > 1.2 * before
