@@ -250,6 +250,67 @@ def run_batched(steps, n_rtt=256):
     return res
 
 
+def run_learned(n_meas=30, train_steps=150, learned_per_sweep=4):
+    """10x10, R=3, chi=128, 8192 walkers, BF16: effective samples/s of
+    single-flip sweeps alone vs single-flip sweeps + learned multi-spin moves
+    (network trained online on the chain, then frozen), same GPU."""
+    import torch
+
+    from oracle import net as onet_init  # seeded initial weights only
+    from paper_2604_22718_amd import rtt as R
+    from paper_2604_22718_amd import workloads as wl
+    w = wl.LARGE_10x10
+    psi = R.RTT.create(w.N, w.pi(), w.cores(), "bf16")
+    ham = R.TFIM(w.Lx, w.Ly, w.J, w.h)
+    net = R.Net(w.Lx, w.Ly, onet_init.init_params(4004))
+    out = {"workload": w.name, "walkers": w.W}
+    spins0 = R.spins_to_device(wl.pack_spins(w.spins()))
+    # burn-in and online training
+    ch = R.LearnedChain(psi, net, spins0.clone(), seed=w.chain_seed)
+    t0 = time.perf_counter()
+    ch.sweep(5)
+    for it in range(train_steps):
+        ch.learned_step()
+        ch.train(lr=2e-3)
+        if it % 10 == 9:
+            ch.sweep(1)
+    torch.cuda.synchronize()
+    out["train_s"] = time.perf_counter() - t0
+    out["train_steps"] = train_steps
+
+    def measure(learned):
+        c = R.LearnedChain(psi, net, ch.spins.clone(), seed=w.chain_seed + 17, rng_stream=1 + int(learned))
+        c.sweep(2)
+        torch.cuda.synchronize()
+        series = []
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(n_meas):
+            c.sweep(1)
+            if learned:
+                for _ in range(learned_per_sweep):
+                    c.learned_step()
+            series.append(psi.local_energy(c.spins, ham).mean())
+        ev1.record()
+        torch.cuda.synchronize()
+        secs = ev0.elapsed_time(ev1) * 1e-3
+        e = torch.stack(series).cpu().numpy()
+        tau = stats_tau(e)
+        res = {"seconds": secs, "tau_int_measurements": tau, "energy_per_site": float(e.mean()) / w.N,
+               "effective_samples_per_s": w.W * n_meas / tau / secs,
+               "single_flip_acceptance": c.acc_flip.sum().item() / (w.W * w.N * (n_meas + 2))}
+        if learned:
+            res["learned_acceptance"] = c.acc_learn.sum().item() / (w.W * learned_per_sweep * n_meas)
+        return res
+
+    out["single_flip"] = measure(False)
+    out["single_flip_plus_learned"] = measure(True)
+    out["learned_moves_per_sweep"] = learned_per_sweep
+    out["ess_gain"] = (out["single_flip_plus_learned"]["effective_samples_per_s"]
+                       / out["single_flip"]["effective_samples_per_s"])
+    return out
+
+
 def stats_tau(x):
     """Integrated autocorrelation time of a 1-D series (Sokal window, c = 5)."""
     x = np.asarray(x, dtype=np.float64)
@@ -277,6 +338,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--also", default="bf16", help="second precision reported alongside ('' for none)")
     ap.add_argument("--batched", type=int, default=0, help="also time the 256-RTT batch for this many steps")
+    ap.add_argument("--learned", action="store_true", help="also compare learned-proposal ESS/s (10x10, chi=128)")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only: this build has no multi-GPU path (asked for {a.gpus}).",
@@ -292,6 +354,8 @@ def main():
                                              "energy_error", "kernels", "roofline")}
     if a.batched:
         res["batched"] = run_batched(a.batched)
+    if a.learned:
+        res["learned"] = run_learned()
     if not a.no_cpu:
         from paper_2604_22718_amd import workloads as wl
         res["cpu_baseline"] = cpu_baseline(wl.MEDIUM_8x8, 64, 8)

@@ -92,8 +92,9 @@ rtt_status rtt_lincomb(int32_t n_terms, const rtt_t* terms, const double* coeffs
 
 rtt_status rtt_destroy(rtt_t h);
 
-/* info (host int32[8]): N, L, padded bond, dtype, n_terms, words per walker,
-   cut bond of the flip-ratio schedule, slots per walker. */
+/* info (host int32[9]): N, L, padded bond, dtype, n_terms, words per walker,
+   cut bond of the flip-ratio schedule, rows per walker and row group, row
+   groups. */
 rtt_status rtt_info(rtt_t h, int32_t* info);
 
 /*

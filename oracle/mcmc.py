@@ -34,21 +34,23 @@ def uniforms(seed, stream, walker_ids, sweep, spin) -> np.ndarray:
 
 
 def metropolis(cores, pi, spins, seed: int, stream: int = 0, sweep0: int = 0,
-               n_sweeps: int = 1, walker_ids=None, record: bool = False):
+               n_sweeps: int = 1, walker_ids=None, record: bool = False, amp_fn=None):
     """Run ``n_sweeps`` sweeps from ``spins`` (W, N).  Returns the final spins,
     per-walker accept counts and, with ``record``, per-decision margins
-    u - r^2 (shape (n_sweeps, N, W)) for near-tie detection."""
+    u - r^2 (shape (n_sweeps, N, W)) for near-tie detection.  ``amp_fn``
+    replaces the single-train amplitude (e.g. a linear combination)."""
     s = np.array(spins, dtype=np.uint8, copy=True)
     W, N = s.shape
     wid = np.arange(W) if walker_ids is None else np.asarray(walker_ids)
     order = proposal_order(pi, N)
+    amp = amp_fn or (lambda S: amplitudes(cores, pi, S))
     accepts = np.zeros(W, dtype=np.int64)
     margins = np.zeros((n_sweeps, N, W)) if record else None
     for t in range(n_sweeps):
         sweep = sweep0 + t
         for qi, j in enumerate(order):
-            psi = amplitudes(cores, pi, s)
-            psi_new = amplitudes(cores, pi, flip(s, j))
+            psi = amp(s)
+            psi_new = amp(flip(s, j))
             r = psi_new / psi
             u = uniforms(seed, stream, wid, sweep, j)
             acc = u < r * r

@@ -109,13 +109,15 @@ def lincomb_amplitudes(terms, coeffs, pi, spins) -> np.ndarray:
     return tot
 
 
-def lincomb_flip_ratios(terms, coeffs, pi, spins) -> np.ndarray:
+def lincomb_flip_ratios(terms, coeffs, pi, spins, which=None) -> np.ndarray:
+    """Ratios of the summed amplitudes; ``which`` restricts to a subset of spins."""
     spins = np.asarray(spins)
     W, N = spins.shape
+    js = range(N) if which is None else which
     base = lincomb_amplitudes(terms, coeffs, pi, spins)
-    out = np.empty((W, N))
-    for j in range(N):
-        out[:, j] = lincomb_amplitudes(terms, coeffs, pi, flip(spins, j)) / base
+    out = np.empty((W, len(js)))
+    for col, j in enumerate(js):
+        out[:, col] = lincomb_amplitudes(terms, coeffs, pi, flip(spins, j)) / base
     return out
 
 

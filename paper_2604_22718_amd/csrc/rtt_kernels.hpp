@@ -40,17 +40,18 @@ struct Geo {
 struct PassArgs {
   const void* cores;        // [T][L][2][CHI*CHI], fragment layout of this direction
   const int32_t* core_exp;  // [T][L] power-of-two scale exponents, or null
-  const int4* sched;
-  int n_steps;
-  int nslot;                // rows per walker, multiple of 16
+  const int4* sched;        // schedules of all row groups, concatenated
+  const int2* gsteps;       // [ng] (first entry, number of entries) of each group
+  int ng;                   // row groups: spins are split so a group's rows fit on chip
+  int nslot;                // rows per walker and group, multiple of 16
   int L, nw, W;
   const uint64_t* spins;    // [W][nw]
-  float* out_vec;           // [T][W][nslot][CHI]
-  int32_t* out_exp;         // [T][W][nslot]
+  float* out_vec;           // [T][ng][W][nslot][CHI]
+  int32_t* out_exp;         // [T][ng][W][nslot]
 };
 
 template <class D, int CHI>
-__device__ __forceinline__ void pass_body(const PassArgs& a, int bx, int term) {
+__device__ __forceinline__ void pass_body(const PassArgs& a, int bx, int ty) {
   using E = typename D::elem;
   using G = Geo<CHI>;
   constexpr int WPW = G::WPW, MT = G::MT, KPL = G::KPL, RS = G::RS;
@@ -78,16 +79,19 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int bx, int term) {
   if (tid_w == 0) cur[0] = 1.f;  // boundary vector e_0 in the base slot
   __syncthreads();
 
+  const int term = ty / a.ng, grp = ty % a.ng;
   const E* cores = static_cast<const E*>(a.cores) + (size_t)term * a.L * 2 * CHI * CHI;
   const int* cexp_p = a.core_exp ? a.core_exp + (size_t)term * a.L : nullptr;
+  const int2 gs = a.gsteps[grp];
+  const int4* sched = a.sched + gs.x;
 
   // work items = (schedule step, output tile of this wave); the core
   // fragments of item i+1 are loaded while item i computes
   struct Frags { E m[KPL]; E o[KPL]; };
-  const int n_items = a.n_steps * MT;
+  const int n_items = gs.y * MT;
   auto load = [&](Frags& F, int item) {
     const int s = item / MT, mt = item % MT;
-    const int4 st = a.sched[s];
+    const int4 st = sched[s];
     const int bit = spin_bit(spw, st.y);
     const size_t tile = ((size_t)(wv * MT + mt) * 64 + lane) * KPL;
     load_frag<KPL>(F.m, cores + ((size_t)st.x * 2 + bit) * (CHI * CHI) + tile);
@@ -95,7 +99,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int bx, int term) {
   };
   auto compute = [&](const Frags& F, int item) {
     const int s = item / MT, mt = item % MT;
-    const int4 st = a.sched[s];
+    const int4 st = sched[s];
     const int k = st.x, nact = st.z, odd = st.w;
     const int t = wv * MT + mt;
     const int cexp = cexp_p ? cexp_p[k] : 0;
@@ -113,7 +117,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int bx, int term) {
       *reinterpret_cast<float4*>(nxt + row * RS + 16 * t + 4 * g) =
           make_float4(acc[0], acc[1], acc[2], acc[3]);
     }
-    {  // odd row on the vector ALUs: out[16t+m] = sum_k A[1-s][k][16t+m] in[k]
+    if (odd >= 0) {  // odd row on the vector ALUs: out[16t+m] = sum_k A[1-s][k][16t+m] in[k]
       const int oin = odd & 0xffff, oout = odd >> 16;
       float v[KPL];
       lds_read<KPL>(v, cur + oin * RS + g * KPL);
@@ -148,27 +152,28 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int bx, int term) {
   __syncthreads();
 
   if (w_raw < a.W) {
-    float* ov = a.out_vec + (((size_t)term * a.W + w) * nslot) * CHI;
+    float* ov = a.out_vec + (((size_t)ty * a.W + w) * nslot) * CHI;
     for (int i = tid_w; i < nslot * CHI; i += NT_W) ov[i] = cur[(i / CHI) * RS + (i % CHI)];
-    int32_t* oe = a.out_exp + ((size_t)term * a.W + w) * nslot;
+    int32_t* oe = a.out_exp + ((size_t)ty * a.W + w) * nslot;
     for (int i = tid_w; i < nslot; i += NT_W) oe[i] = exc[i];
   }
 }
 
 template <class D, int CHI>
 __global__ void __launch_bounds__(256) pass_kernel(PassArgs a) {
-  pass_body<D, CHI>(a, blockIdx.x, blockIdx.y);
+  pass_body<D, CHI>(a, blockIdx.x, blockIdx.y);  // y = term * ng + group
 }
 
 // ============================================================================
 // combine kernel (one wave per walker)
 // ============================================================================
 struct CombineArgs {
-  const float* u; const int32_t* ue;  // forward  [T][W][nsf][chi], [T][W][nsf]
-  const float* v; const int32_t* ve;  // backward [T][W][nsb][chi], [T][W][nsb]
-  int nsf, nsb, chi, T, W, N, nw;
-  const int32_t* fslot;               // [N] forward slot of spin j (0 = base)
-  const int32_t* bslot;               // [N] backward slot of spin j (0 = base)
+  const float* u; const int32_t* ue;  // forward  [T][ng][W][nsf][chi], [T][ng][W][nsf]
+  const float* v; const int32_t* ve;  // backward [T][ng][W][nsb][chi], [T][ng][W][nsb]
+  int nsf, nsb, chi, T, W, N, nw, ng;
+  const int32_t* fslot;               // [N] forward slot of spin j in its group (0 = base)
+  const int32_t* bslot;               // [N] backward slot of spin j in its group (0 = base)
+  const int32_t* grp;                 // [N] row group of spin j
   const double* coeffs;               // [T]
   const uint64_t* spins;
   const int2* bonds; int nbonds; double J, h;
@@ -176,14 +181,15 @@ struct CombineArgs {
 };
 
 // value = mant * 2^ex with |mant| in [0.5, 1) (mant = 0 for zero)
-__device__ inline void combined_value(const CombineArgs& a, int w, int fs, int bs, double& mant,
-                                      int& ex) {
+__device__ inline void combined_value(const CombineArgs& a, int w, int gi, int fs, int bs,
+                                      double& mant, int& ex) {
   double ms[kMaxTerms];
   int es[kMaxTerms];
   int emax = INT_MIN;
   for (int t = 0; t < a.T; ++t) {
-    const float* pu = a.u + (((size_t)t * a.W + w) * a.nsf + fs) * a.chi;
-    const float* pv = a.v + (((size_t)t * a.W + w) * a.nsb + bs) * a.chi;
+    const size_t ty = (size_t)t * a.ng + gi;
+    const float* pu = a.u + ((ty * a.W + w) * a.nsf + fs) * a.chi;
+    const float* pv = a.v + ((ty * a.W + w) * a.nsb + bs) * a.chi;
     double d = 0.0;
     for (int f = 0; f < a.chi; f += 4) {
       const float4 x = *reinterpret_cast<const float4*>(pu + f);
@@ -196,7 +202,7 @@ __device__ inline void combined_value(const CombineArgs& a, int w, int fs, int b
     int ed = 0;
     const double md = frexp(d, &ed);
     ms[t] = a.coeffs[t] * md;
-    es[t] = a.ue[((size_t)t * a.W + w) * a.nsf + fs] + a.ve[((size_t)t * a.W + w) * a.nsb + bs] + ed;
+    es[t] = a.ue[(ty * a.W + w) * a.nsf + fs] + a.ve[(ty * a.W + w) * a.nsb + bs] + ed;
     if (ms[t] != 0.0 && es[t] > emax) emax = es[t];
   }
   if (emax == INT_MIN) { mant = 0.0; ex = 0; return; }
@@ -219,7 +225,7 @@ __device__ __forceinline__ void combine_body(const CombineArgs& a, int bx) {
   if (w >= a.W) return;
   const double LN2 = 0.69314718055994530942;
   double m0; int e0;
-  combined_value(a, w, 0, 0, m0, e0);
+  combined_value(a, w, 0, 0, 0, m0, e0);
   const bool ok = (m0 != 0.0) && isfinite(m0);
   const double lab0 = ok ? log(fabs(m0)) + e0 * LN2 : NAN;
   if (lane == 0) {
@@ -237,7 +243,7 @@ __device__ __forceinline__ void combine_body(const CombineArgs& a, int bx) {
         lr = 0.0; sg = 1; r = 1.0;
       } else {
         double mj; int ej;
-        combined_value(a, w, fs, bs, mj, ej);
+        combined_value(a, w, a.grp[j], fs, bs, mj, ej);
         if (mj == 0.0) { lr = -INFINITY; sg = 1; r = 0.0; }
         else {
           lr = log(fabs(mj)) - log(fabs(m0)) + (double)(ej - e0) * LN2;
@@ -286,16 +292,24 @@ struct ChainArgs {
 
 constexpr int kRenormEvery = 4;  // steps between power-of-two renormalisations
 
-// Layout of the 16 walkers' state in LDS (offsets in bytes).
+// Layout of the 16 walkers' state in LDS (offsets in bytes).  All terms of
+// a linear combination advance together (5 row buffers per term: prefix P,
+// first-step products U and F, ping-pong X and Y) when that fits; otherwise
+// ("sequential") each term keeps only its prefix and the terms share F, X, Y,
+// one term at a time, the prefix being advanced after the decision.
 struct ChainLayout {
-  int rows, exps, pm, sp, total;
+  int rows, exps, vals, pm, sp, total;
+  bool seq;
   __host__ __device__ ChainLayout(int chi, int T, int LW, int nw) {
     const int rs = chi + 4;
-    rows = 0;                                   // float [T][5][16][rs]
-    exps = rows + T * 5 * 16 * rs * 4;          // int [3][T][16]: prefix, first step, running
-    pm = exps + 3 * T * 16 * 4;                 // uint64 [16][LW] position bits of the walker
+    const int tail = 3 * T * 16 * 4 + T * 16 * 8 + 8 + 16 * LW * 8 + 16 * nw * 8;
+    seq = (T * 5 * 16 * rs * 4 + tail) > 160 * 1024;
+    rows = 0;                                          // float rows
+    exps = rows + (seq ? T + 3 : 5 * T) * 16 * rs * 4; // int [3][T][16]: prefix, first step, running
+    vals = exps + 3 * T * 16 * 4;                      // float [T][16] final values, int [T][16] exponents
+    pm = vals + T * 16 * 8;
     pm = (pm + 7) & ~7;
-    sp = pm + 16 * LW * 8;                      // uint64 [16][nw] spins
+    sp = pm + 16 * LW * 8;                             // uint64 [16][LW] position bits; [16][nw] spins
     total = sp + 16 * nw * 8;
   }
 };
@@ -316,11 +330,17 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx) {
   int* Ep = reinterpret_cast<int*>(lds_raw + lay.exps);   // [T][16] prefix
   int* Ef = Ep + T * 16;                                   // [T][16] after the first step
   int* Er = Ef + T * 16;                                   // [T][16] running row
+  float* fval = reinterpret_cast<float*>(lds_raw + lay.vals);   // [T][16] final feature 0
+  int* fexp = reinterpret_cast<int*>(fval + T * 16);           // [T][16] its exponent
   uint64_t* pm = reinterpret_cast<uint64_t*>(lds_raw + lay.pm);
   uint64_t* sp = reinterpret_cast<uint64_t*>(lds_raw + lay.sp);
+  const bool seq = lay.seq;
 
   enum { P = 0, U = 1, F = 2, X = 3, Y = 4 };
-  auto buf = [&](int t, int b) { return rows + (t * 5 + b) * BUF; };
+  auto buf = [&](int t, int b) {
+    if (!seq) return rows + (t * 5 + b) * BUF;
+    return b == P ? rows + t * BUF : rows + (T + b - F) * BUF;  // U is not used then
+  };
 
   const int w0 = bx * 16;
   const bool live = (w0 + m) < a.W;
@@ -353,13 +373,14 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx) {
   // step stores the walker's own slice product in F and the other slice's
   // in U.  Rows are renormalised every kRenormEvery steps; the running
   // exponent sum lives in Er.  Returns the buffer holding the result.
-  auto segment = [&](int from, int k0, int k1, int jflip, bool split) -> int {
+  auto segment = [&](int from, int k0, int k1, int jflip, bool split, int t0, int tn) -> int {
     if (k1 <= k0) return from;
     int cur = from, out = split ? F : X;
     int bit = 0;
     uint64_t word = 0;
     const uint64_t* rmj = jflip >= 0 ? a.rmask + (size_t)jflip * LW : nullptr;
-    int k = k0, t = 0, mt = 0;
+    const int tend = t0 + tn;
+    int k = k0, t = t0, mt = 0;
     auto load = [&](Frags& Fr, int kk, int tt, int mm) {
       const E* base = cores + (((size_t)tt * L + kk) * 2) * (CHI * CHI) +
                       (size_t)(wv * MT + mm) * 64 * KPL + lane_off;
@@ -367,10 +388,10 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx) {
       load_frag<KPL>(Fr.f1, base + CHI * CHI);
     };
     auto step = [&](const Frags& Fr) {
-      if (t == 0 && mt == 0 && (k == k0 || (k & 63) == 0)) {
+      if (t == t0 && mt == 0 && (k == k0 || (k & 63) == 0)) {
         word = pm[m * LW + (k >> 6)] ^ (rmj ? rmj[k >> 6] : 0ull);
       }
-      if (t == 0 && mt == 0) bit = (int)((word >> (k & 63)) & 1ull);
+      if (t == t0 && mt == 0) bit = (int)((word >> (k & 63)) & 1ull);
       if (mt == 0) {
         float v[KPL];
         lds_read<KPL>(v, buf(t, cur) + m * RS + g * KPL);
@@ -399,15 +420,15 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx) {
         *reinterpret_cast<float4*>(buf(t, U) + m * RS + 16 * tt + 4 * g) =
             make_float4(oth[0], oth[1], oth[2], oth[3]);
       }
-      if (mt == MT - 1 && t == T - 1) {
+      if (mt == MT - 1 && t == tend - 1) {
         lds_barrier();
         cur = out;
         out = (cur == X) ? Y : X;
       }
-      if (++mt == MT) { mt = 0; if (++t == T) { t = 0; ++k; } }
+      if (++mt == MT) { mt = 0; if (++t == tend) { t = t0; ++k; } }
     };
     auto next_of = [&](int& kk, int& tt, int& mm) {
-      if (++mm == MT) { mm = 0; if (++tt == T) { tt = 0; ++kk; } }
+      if (++mm == MT) { mm = 0; if (++tt == tend) { tt = t0; ++kk; } }
     };
     // The prefetch is issued on every path (past the end it re-reads the
     // last position) so the number of loads in flight is the same on all
@@ -429,17 +450,26 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx) {
     return cur;
   };
 
-  // combined amplitude of this lane's walker from feature 0 of buffer b of
-  // every term: log|psi| and sign (every lane of every wave computes it)
-  auto amp = [&](int b, int kend, double& labs, int& sg) {
+  // record feature 0 of buffer b (the end of the train) for terms [t0, t0+tn)
+  auto record = [&](int b, int t0, int tn) {
+    if (wv == 0 && g == 0)
+      for (int t = t0; t < t0 + tn; ++t) {
+        fval[t * 16 + m] = buf(t, b)[m * RS];
+        fexp[t * 16 + m] = Er[t * 16 + m] + a.cesum[(size_t)t * (L + 1) + L];
+      }
+    __syncthreads();
+  };
+  // combined amplitude of this lane's walker from the recorded values:
+  // log|psi| and sign (every lane of every wave computes it)
+  auto amp = [&](double& labs, int& sg) {
     double ms[kMaxTerms];
     int es[kMaxTerms];
     int emax = INT_MIN;
     for (int t = 0; t < T; ++t) {
       int ed = 0;
-      const double md = frexp((double)buf(t, b)[m * RS], &ed);
+      const double md = frexp((double)fval[t * 16 + m], &ed);
       ms[t] = a.coeffs[t] * md;
-      es[t] = Er[t * 16 + m] + a.cesum[(size_t)t * (L + 1) + kend] + ed;
+      es[t] = fexp[t * 16 + m] + ed;
       if (ms[t] != 0.0 && es[t] > emax) emax = es[t];
     }
     if (emax == INT_MIN) { labs = -INFINITY; sg = 0; return; }
@@ -467,12 +497,15 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx) {
   double lab;
   int sgn, stat;
   uint32_t nacc = 0;
-  {
-    const int fin = segment(P, 0, L, -1, false);
-    amp(fin, L, lab, sgn);
-    stat = (sgn != 0 && isfinite(lab)) ? 0 : -5;
-    __syncthreads();
+  if (!seq) {
+    const int fin = segment(P, 0, L, -1, false, 0, T);
+    record(fin, 0, T);
+  } else {
+    for (int t = 0; t < T; ++t) record(segment(P, 0, L, -1, false, t, 1), t, 1);
   }
+  amp(lab, sgn);
+  stat = (sgn != 0 && isfinite(lab)) ? 0 : -5;
+  __syncthreads();
 
   if (a.mode == 1) {
     for (int ts = 0; ts < a.n_sweeps; ++ts) {
@@ -491,23 +524,32 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx) {
           __syncthreads();
           continue;
         }
-        if (pos < f) {  // bring the prefix up to position f
-          const int fin = segment(P, pos, f, -1, false);
-          for (int i = threadIdx.x; i < T * 16 * RS; i += nthr) {
-            const int t = i / (16 * RS), r = i % (16 * RS);
+        // bring the prefix of terms [t0, t0+tn) from pos up to position kk
+        auto advance_prefix = [&](int kk, int t0, int tn) {
+          const int fin = segment(P, pos, kk, -1, false, t0, tn);
+          for (int i = threadIdx.x; i < tn * 16 * RS; i += nthr) {
+            const int t = t0 + i / (16 * RS), r = i % (16 * RS);
             buf(t, P)[r] = buf(t, fin)[r];
           }
+          for (int i = threadIdx.x; i < tn * 16; i += nthr) Ep[t0 * 16 + i] = Er[t0 * 16 + i];
           __syncthreads();
-          for (int i = threadIdx.x; i < T * 16; i += nthr) Ep[i] = Er[i];
-          __syncthreads();
+        };
+        if (pos < f) {
+          if (!seq) advance_prefix(f, 0, T);
+          else for (int t = 0; t < T; ++t) advance_prefix(f, t, 1);
+          pos = f;
         }
-        // the flipped row from position f to the end; the first step also
-        // leaves the unflipped extension of the prefix in U
-        const int fin = segment(P, f, L, j, true);
+        // the flipped row from position f to the end; with all terms at once
+        // the first step also leaves the unflipped prefix extension in U
+        if (!seq) {
+          record(segment(P, f, L, j, true, 0, T), 0, T);
+        } else {
+          for (int t = 0; t < T; ++t) record(segment(P, f, L, j, false, t, 1), t, 1);
+        }
         int accept = 0;
         if (live && stat == 0) {
           double lnew; int snew;
-          amp(fin, L, lnew, snew);
+          amp(lnew, snew);
           if (isnan(lnew)) {
             stat = -5;
           } else if (snew != 0) {
@@ -520,17 +562,19 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx) {
             }
           }
         }
-        // prefix through position f with the decided s_j: each lane copies
-        // the features it wrote in the first step
-        for (int t = 0; t < T; ++t)
+        // prefix through position f with the decided s_j
+        if (!seq) {  // each lane copies the features it wrote in the first step
+          for (int t = 0; t < T; ++t)
 #pragma unroll
-          for (int mt = 0; mt < MT; ++mt) {
-            const int off = m * RS + 16 * (wv * MT + mt) + 4 * g;
-            *reinterpret_cast<float4*>(buf(t, P) + off) =
-                *reinterpret_cast<const float4*>(buf(t, accept ? F : U) + off);
-          }
+            for (int mt = 0; mt < MT; ++mt) {
+              const int off = m * RS + 16 * (wv * MT + mt) + 4 * g;
+              *reinterpret_cast<float4*>(buf(t, P) + off) =
+                  *reinterpret_cast<const float4*>(buf(t, accept ? F : U) + off);
+            }
+        }
         if (wv == 0 && g == 0) {
-          for (int t = 0; t < T; ++t) Ep[t * 16 + m] = Ef[t * 16 + m];
+          if (!seq)
+            for (int t = 0; t < T; ++t) Ep[t * 16 + m] = Ef[t * 16 + m];
           if (accept) {
             sp[m * nw + (j >> 6)] ^= (1ull << (j & 63));
             const uint64_t* rmj = a.rmask + (size_t)j * LW;
@@ -538,6 +582,8 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx) {
           }
         }
         __syncthreads();
+        if (seq)  // one more step per term with the decided spin
+          for (int t = 0; t < T; ++t) advance_prefix(f + 1, t, 1);
         pos = f + 1;
       }
     }

@@ -88,46 +88,69 @@ int next_pow2(int x) {
 }
 
 struct Sched {
-  std::vector<int> fwd, bwd;  // int4 entries
-  std::vector<int> fslot, bslot;
-  int cut = 0, nslot = 16, nf = 1, nb = 1;
+  std::vector<int> fwd, bwd;     // int4 entries of every row group, concatenated
+  std::vector<int> fgs, bgs;     // int2 per group: (first entry, number of entries)
+  std::vector<int> fslot, bslot, grp;
+  int cut = 0, nslot = 16, ng = 1;
   long cost = 0;
 };
 
 // Forward steps over positions [0, c), backward steps over [c, L) from the
-// right; each spin gets a row spawned at its first position (forward) and a
-// column spawned at its last position (backward) on its side of the cut.
-Sched build_sched(const std::vector<int>& pi, int N, int L, int c) {
+// right.  Spins are dealt round-robin, in order of first position, into ng
+// row groups; one pass of group g carries the base vector and one vector
+// per spin of g, spawned at the spin's first position (forward) or last
+// position (backward) on its side of the cut.  At positions of spins of
+// other groups every vector uses the walker's slice (no odd row, w = -1).
+Sched build_sched(const std::vector<int>& pi, int N, int L, int c, int ng) {
   Sched s;
   s.cut = c;
+  s.ng = ng;
   s.fslot.assign(N, 0);
   s.bslot.assign(N, 0);
-  std::vector<int> fs(N, -1), bs(N, -1);
-  int nf = 1;
-  for (int k = 0; k < c; ++k) {
-    const int q = pi[k];
-    int oin, oout;
-    if (fs[q] < 0) { fs[q] = nf++; oin = 0; oout = fs[q]; }
-    else { oin = oout = fs[q]; }
-    s.fwd.insert(s.fwd.end(), {k, q, nf, oin | (oout << 16)});
-    s.cost += (nf + 15) / 16;
+  s.grp.assign(N, 0);
+  std::vector<int> first(N, -1);
+  for (int k = 0; k < L; ++k)
+    if (first[pi[k]] < 0) first[pi[k]] = k;
+  std::vector<int> order;
+  for (int k = 0; k < L; ++k)
+    if (first[pi[k]] == k) order.push_back(pi[k]);
+  for (int r = 0; r < (int)order.size(); ++r) s.grp[order[r]] = r % ng;
+  int nmax = 1;
+  for (int g = 0; g < ng; ++g) {
+    std::vector<int> fs(N, -1), bs(N, -1);
+    const int f0 = (int)s.fwd.size() / 4, b0 = (int)s.bwd.size() / 4;
+    int nf = 1;
+    for (int k = 0; k < c; ++k) {
+      const int q = pi[k];
+      int odd = -1;
+      if (s.grp[q] == g) {
+        if (fs[q] < 0) { fs[q] = nf++; odd = 0 | (fs[q] << 16); }
+        else odd = fs[q] | (fs[q] << 16);
+      }
+      s.fwd.insert(s.fwd.end(), {k, q, nf, odd});
+      s.cost += (nf + 15) / 16;
+    }
+    int nb = 1;
+    for (int k = L - 1; k >= c; --k) {
+      const int q = pi[k];
+      int odd = -1;
+      if (s.grp[q] == g) {
+        if (bs[q] < 0) { bs[q] = nb++; odd = 0 | (bs[q] << 16); }
+        else odd = bs[q] | (bs[q] << 16);
+      }
+      s.bwd.insert(s.bwd.end(), {k, q, nb, odd});
+      s.cost += (nb + 15) / 16;
+    }
+    s.fgs.insert(s.fgs.end(), {f0, c});
+    s.bgs.insert(s.bgs.end(), {b0, L - c});
+    for (int j = 0; j < N; ++j)
+      if (s.grp[j] == g) {
+        s.fslot[j] = fs[j] < 0 ? 0 : fs[j];
+        s.bslot[j] = bs[j] < 0 ? 0 : bs[j];
+      }
+    nmax = std::max(nmax, std::max(nf, nb));
   }
-  int nb = 1;
-  for (int k = L - 1; k >= c; --k) {
-    const int q = pi[k];
-    int oin, oout;
-    if (bs[q] < 0) { bs[q] = nb++; oin = 0; oout = bs[q]; }
-    else { oin = oout = bs[q]; }
-    s.bwd.insert(s.bwd.end(), {k, q, nb, oin | (oout << 16)});
-    s.cost += (nb + 15) / 16;
-  }
-  for (int j = 0; j < N; ++j) {
-    s.fslot[j] = fs[j] < 0 ? 0 : fs[j];
-    s.bslot[j] = bs[j] < 0 ? 0 : bs[j];
-  }
-  s.nf = nf;
-  s.nb = nb;
-  s.nslot = (std::max(nf, nb) + 15) / 16 * 16;
+  s.nslot = (nmax + 15) / 16 * 16;
   return s;
 }
 
@@ -166,6 +189,9 @@ struct rtt_s {
   int4* d_sb = nullptr;
   int* d_fslot = nullptr;
   int* d_bslot = nullptr;
+  int* d_grp = nullptr;
+  int2* d_fgs = nullptr;
+  int2* d_bgs = nullptr;
   int* d_pi = nullptr;
   int* d_order = nullptr;
   int* d_first = nullptr;
@@ -238,7 +264,7 @@ rtt_status upload(void** dst, const void* src, size_t bytes) {
 }
 
 void free_dev(rtt_s* h) {
-  void* ptrs[] = {h->d_fwd, h->d_bwd, h->d_cexp, h->d_cesum, h->d_rmask, h->d_sf, h->d_sb, h->d_fslot, h->d_bslot,
+  void* ptrs[] = {h->d_grp, h->d_fgs, h->d_bgs, h->d_fwd, h->d_bwd, h->d_cexp, h->d_cesum, h->d_rmask, h->d_sf, h->d_sb, h->d_fslot, h->d_bslot,
                   h->d_pi, h->d_order, h->d_first, h->d_coeffs, h->d_u, h->d_v, h->d_ue, h->d_ve};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -295,12 +321,15 @@ rtt_status finish_create(rtt_s* h) {
   h->rmask.assign((size_t)h->N * LW, 0ull);
   for (int k = 0; k < h->L; ++k) h->rmask[(size_t)h->pi[k] * LW + k / 64] |= 1ull << (k % 64);
   // schedules: choose the cut bond with the least matrix-core work that fits on chip
+  // the fewest row groups whose rows fit on chip, then the cheapest cut
   Sched best;
   bool have = false;
-  for (int c = 0; c <= h->L; ++c) {
-    Sched s = build_sched(h->pi, h->N, h->L, c);
-    if (pass_lds_bytes(h->chi, s.nslot, h->nw) > kLdsLimit) continue;
-    if (!have || s.cost < best.cost) { best = s; have = true; }
+  for (int ng = 1; ng <= 64 && !have; ++ng) {
+    for (int c = 0; c <= h->L; ++c) {
+      Sched s = build_sched(h->pi, h->N, h->L, c, ng);
+      if (pass_lds_bytes(h->chi, s.nslot, h->nw) > kLdsLimit) continue;
+      if (!have || s.cost < best.cost) { best = s; have = true; }
+    }
   }
   if (!have) return fail(RTT_E_UNSUPPORTED, "rtt_create: flip-ratio rows of one walker exceed on-chip memory");
   if (chain_lds_bytes(h->chi, h->T, h->L, h->nw) > kLdsLimit)
@@ -333,6 +362,9 @@ rtt_status finish_create(rtt_s* h) {
   if ((st = upload((void**)&h->d_sb, best.bwd.data(), best.bwd.size() * 4)) != RTT_OK) return st;
   if ((st = upload((void**)&h->d_fslot, best.fslot.data(), best.fslot.size() * 4)) != RTT_OK) return st;
   if ((st = upload((void**)&h->d_bslot, best.bslot.data(), best.bslot.size() * 4)) != RTT_OK) return st;
+  if ((st = upload((void**)&h->d_grp, best.grp.data(), best.grp.size() * 4)) != RTT_OK) return st;
+  if ((st = upload((void**)&h->d_fgs, best.fgs.data(), best.fgs.size() * 4)) != RTT_OK) return st;
+  if ((st = upload((void**)&h->d_bgs, best.bgs.data(), best.bgs.size() * 4)) != RTT_OK) return st;
   if ((st = upload((void**)&h->d_pi, h->pi.data(), h->pi.size() * 4)) != RTT_OK) return st;
   if ((st = upload((void**)&h->d_order, h->order.data(), h->order.size() * 4)) != RTT_OK) return st;
   if ((st = upload((void**)&h->d_first, h->first.data(), h->first.size() * 4)) != RTT_OK) return st;
@@ -348,7 +380,7 @@ rtt_status ensure_ws(rtt_s* h, int W) {
   h->d_u = h->d_v = nullptr;
   h->d_ue = h->d_ve = nullptr;
   h->ws_W = 0;
-  const size_t rows = (size_t)h->T * W * h->sched.nslot;
+  const size_t rows = (size_t)h->T * h->sched.ng * W * h->sched.nslot;
   HIPX(hipMalloc(&h->d_u, rows * h->chi * 4));
   HIPX(hipMalloc(&h->d_v, rows * h->chi * 4));
   HIPX(hipMalloc(&h->d_ue, rows * 4));
@@ -426,7 +458,7 @@ extern "C" {
 
 const char* rtt_last_error(void) { return g_err.c_str(); }
 
-int32_t rtt_abi_version(void) { return 1; }
+int32_t rtt_abi_version(void) { return 2; }
 
 rtt_status rtt_create(int32_t n_spins, int32_t n_cores, const int32_t* pi, const int32_t* bond,
                       const double* cores, int32_t dtype, rtt_t* out) {
@@ -536,6 +568,7 @@ rtt_status rtt_info(rtt_t h, int32_t* info) {
   if (!info) return fail(RTT_E_ARG, "rtt_info: info is null");
   info[0] = h->N; info[1] = h->L; info[2] = h->chi; info[3] = h->dtype;
   info[4] = h->T; info[5] = h->nw; info[6] = h->sched.cut; info[7] = h->sched.nslot;
+  info[8] = h->sched.ng;
   return RTT_OK;
 }
 
@@ -622,23 +655,25 @@ rtt_status rtt_evaluate(rtt_t h, rtt_ham_t ham, int32_t W, const uint64_t* spins
   pa.W = W;
   pa.spins = spins;
   // forward
+  pa.ng = h->sched.ng;
   pa.cores = h->d_fwd;
   pa.sched = h->d_sf;
-  pa.n_steps = (int)h->sched.fwd.size() / 4;
+  pa.gsteps = h->d_fgs;
   pa.out_vec = h->d_u;
   pa.out_exp = h->d_ue;
-  if ((st = dispatch<PassL>(h->dtype, h->chi, pa, h->T, s)) != RTT_OK) return st;
+  if ((st = dispatch<PassL>(h->dtype, h->chi, pa, h->T * h->sched.ng, s)) != RTT_OK) return st;
   // backward
   pa.cores = h->d_bwd;
   pa.sched = h->d_sb;
-  pa.n_steps = (int)h->sched.bwd.size() / 4;
+  pa.gsteps = h->d_bgs;
   pa.out_vec = h->d_v;
   pa.out_exp = h->d_ve;
-  if ((st = dispatch<PassL>(h->dtype, h->chi, pa, h->T, s)) != RTT_OK) return st;
+  if ((st = dispatch<PassL>(h->dtype, h->chi, pa, h->T * h->sched.ng, s)) != RTT_OK) return st;
   rttk::CombineArgs ca{};
   ca.u = h->d_u; ca.ue = h->d_ue; ca.v = h->d_v; ca.ve = h->d_ve;
   ca.nsf = h->sched.nslot; ca.nsb = h->sched.nslot; ca.chi = h->chi; ca.T = h->T; ca.W = W;
   ca.N = h->N; ca.nw = h->nw; ca.fslot = h->d_fslot; ca.bslot = h->d_bslot; ca.coeffs = h->d_coeffs;
+  ca.ng = h->sched.ng; ca.grp = h->d_grp;
   ca.spins = spins;
   ca.bonds = ham ? ham->d_bonds : nullptr;
   ca.nbonds = ham ? ham->nb : 0;
@@ -948,7 +983,7 @@ rtt_status rtt_batch_create(int32_t n, const rtt_t* rtts, const rtt_ham_t* hams,
   b->ws_i.assign(n, nullptr);
   for (int i = 0; i < n; ++i) {
     const rtt_s* h = b->rtts[i];
-    const size_t rows = (size_t)h->T * b->W[i] * h->sched.nslot;
+    const size_t rows = (size_t)h->T * h->sched.ng * b->W[i] * h->sched.nslot;
     if (hipMalloc(&b->ws_f[i], 2 * rows * h->chi * 4) != hipSuccess ||
         hipMalloc(&b->ws_i[i], 2 * rows * 4) != hipSuccess)
       return cleanup(fail(RTT_E_OOM, "rtt_batch_create: workspace for run %d", i));
@@ -956,10 +991,13 @@ rtt_status rtt_batch_create(int32_t n, const rtt_t* rtts, const rtt_ham_t* hams,
   auto ws_u = [&](int i) { return b->ws_f[i]; };
   auto ws_v = [&](int i) {
     const rtt_s* h = b->rtts[i];
-    return b->ws_f[i] + (size_t)h->T * b->W[i] * h->sched.nslot * h->chi;
+    return b->ws_f[i] + (size_t)h->T * h->sched.ng * b->W[i] * h->sched.nslot * h->chi;
   };
   auto ws_ue = [&](int i) { return b->ws_i[i]; };
-  auto ws_ve = [&](int i) { return b->ws_i[i] + (size_t)b->rtts[i]->T * b->W[i] * b->rtts[i]->sched.nslot; };
+  auto ws_ve = [&](int i) {
+    const rtt_s* h = b->rtts[i];
+    return b->ws_i[i] + (size_t)h->T * h->sched.ng * b->W[i] * h->sched.nslot;
+  };
   // group runs by (dtype, padded bond); order members by work, largest first
   for (int i = 0; i < n; ++i) {
     const rtt_s* h = b->rtts[i];
@@ -979,7 +1017,7 @@ rtt_status rtt_batch_create(int32_t n, const rtt_t* rtts, const rtt_ham_t* hams,
     std::vector<std::pair<double, int>> order;
     for (int i : c.members) {
       const rtt_s* h = b->rtts[i];
-      const double rows = (double)(h->sched.fwd.size() + h->sched.bwd.size()) / 4 * h->sched.nslot;
+      const double rows = (double)h->sched.cost * 16;
       order.push_back({rows * chi2 * h->T, i});
     }
     std::sort(order.begin(), order.end(), [](auto& x, auto& y) { return x.first > y.first; });
@@ -999,10 +1037,11 @@ rtt_status rtt_batch_create(int32_t n, const rtt_t* rtts, const rtt_ham_t* hams,
       rttk::PassArgs pa{};
       pa.core_exp = h->d_cexp; pa.nslot = h->sched.nslot; pa.L = h->L; pa.nw = h->nw; pa.W = W;
       pa.spins = b->spins[i];
-      pa.cores = h->d_fwd; pa.sched = h->d_sf; pa.n_steps = (int)h->sched.fwd.size() / 4;
+      pa.ng = h->sched.ng;
+      pa.cores = h->d_fwd; pa.sched = h->d_sf; pa.gsteps = h->d_fgs;
       pa.out_vec = ws_u(i); pa.out_exp = ws_ue(i);
       c.pass.push_back(pa);
-      pa.cores = h->d_bwd; pa.sched = h->d_sb; pa.n_steps = (int)h->sched.bwd.size() / 4;
+      pa.cores = h->d_bwd; pa.sched = h->d_sb; pa.gsteps = h->d_bgs;
       pa.out_vec = ws_v(i); pa.out_exp = ws_ve(i);
       c.pass.push_back(pa);
       c.pass_lds = std::max(c.pass_lds, pass_lds_bytes(c.chi, h->sched.nslot, h->nw));
@@ -1011,11 +1050,11 @@ rtt_status rtt_batch_create(int32_t n, const rtt_t* rtts, const rtt_ham_t* hams,
       for (int j = 0; j < h->N; ++j) if (h->first[j] >= 0) sweep_rows += h->L - h->first[j];
       c.chain_cost += sweep_rows * h->T * ((W + 15) / 16) * 16 * (double)c.chi * c.chi;
       const int wpb = 4 / rttk_wpw(c.chi);
-      c.pass_cost += (double)(h->sched.fwd.size() + h->sched.bwd.size()) / 4 * h->sched.nslot * h->T * W * (double)c.chi * c.chi;
+      c.pass_cost += (double)h->sched.cost * 16 * h->T * W * (double)c.chi * c.chi;
       for (int t = 0; t < (W + 15) / 16; ++t) c.chain_items.push_back(make_int4(mi, t, 0, 0));
       for (int dir = 0; dir < 2; ++dir)
-        for (int term = 0; term < h->T; ++term)
-          for (int bx = 0; bx < (W + wpb - 1) / wpb; ++bx) c.pass_items.push_back(make_int4(2 * mi + dir, bx, term, 0));
+        for (int ty = 0; ty < h->T * h->sched.ng; ++ty)
+          for (int bx = 0; bx < (W + wpb - 1) / wpb; ++bx) c.pass_items.push_back(make_int4(2 * mi + dir, bx, ty, 0));
     }
     rtt_status st;
     if ((st = upload((void**)&c.d_chain, c.chain.data(), c.chain.size() * sizeof(rttk::ChainArgs))) != RTT_OK) return cleanup(st);
@@ -1034,6 +1073,7 @@ rtt_status rtt_batch_create(int32_t n, const rtt_t* rtts, const rtt_ham_t* hams,
     ca.u = ws_u(i); ca.ue = ws_ue(i); ca.v = ws_v(i); ca.ve = ws_ve(i);
     ca.nsf = h->sched.nslot; ca.nsb = h->sched.nslot; ca.chi = h->chi; ca.T = h->T; ca.W = b->W[i];
     ca.N = h->N; ca.nw = h->nw; ca.fslot = h->d_fslot; ca.bslot = h->d_bslot; ca.coeffs = h->d_coeffs;
+    ca.ng = h->sched.ng; ca.grp = h->d_grp;
     ca.spins = b->spins[i]; ca.bonds = b->hams[i]->d_bonds; ca.nbonds = b->hams[i]->nb;
     ca.J = b->hams[i]->J; ca.h = b->hams[i]->h; ca.eloc = b->eloc[i];
     b->comb.push_back(ca);

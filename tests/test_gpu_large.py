@@ -1,0 +1,123 @@
+"""Shapes that do not fit on chip in one piece: row groups in the flip-ratio
+passes, and the term-sequential sweep of a large linear combination; and the
+16x16, chi = 256, 4-term FP8 workload on sampled spins."""
+import numpy as np
+import pytest
+import torch
+
+from helpers import case, check_ratios, device_cores
+from oracle import mcmc, rtt as orc, tt
+from paper_2604_22718_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def R():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2604_22718_amd import rtt
+    return rtt
+
+
+def test_row_groups_match_oracle(R):
+    N, Rr, chi, W = 100, 2, 256, 2
+    pi, bond, cores = case(N, Rr, chi, "perm", seed=60)
+    psi = R.RTT.create(N, pi, cores, "bf16")
+    assert psi.info["groups"] >= 2
+    qc = device_cores(psi, bond)
+    bits = wl.random_spins(W, N, 61)
+    out = psi.evaluate(R.spins_to_device(wl.pack_spins(bits)))
+    torch.cuda.synchronize()
+    out = {k: v.cpu().numpy() for k, v in out.items()}
+    r_ref = orc.flip_ratios(qc, pi, bits)
+    kap = orc.flip_condition_numbers(qc, pi, bits)
+    st = check_ratios(out["logratio"], out["rsign"], r_ref, kap, 2e-2)
+    print(psi.info, st)
+    assert st["n_bad"] == 0 and st["n_sign_bad"] == 0
+    la, sg = orc.log_sign(orc.amplitudes(qc, pi, bits))
+    assert np.all(out["sign"] == sg) and np.max(np.abs(out["logabs"] - la)) < 2e-2
+
+
+def test_row_groups_fp32_many_spins(R):
+    """FP32, chi = 128, N = 144: groups also in the FP32 path."""
+    N, Rr, chi, W = 144, 2, 128, 2
+    pi, bond, cores = case(N, Rr, chi, "perm", seed=62)
+    psi = R.RTT.create(N, pi, cores, "f32")
+    assert psi.info["groups"] >= 2
+    qc = device_cores(psi, bond)
+    bits = wl.random_spins(W, N, 63)
+    out = psi.evaluate(R.spins_to_device(wl.pack_spins(bits)))
+    torch.cuda.synchronize()
+    out = {k: v.cpu().numpy() for k, v in out.items()}
+    r_ref = orc.flip_ratios(qc, pi, bits)
+    kap = orc.flip_condition_numbers(qc, pi, bits)
+    st = check_ratios(out["logratio"], out["rsign"], r_ref, kap, 1e-5)
+    print(psi.info, st)
+    assert st["n_bad"] == 0 and st["n_sign_bad"] == 0
+
+
+def test_sequential_terms_sweep_matches_oracle(R):
+    """4 terms at chi = 256 exceed on-chip memory together, so the sweep runs
+    term by term; decisions equal the oracle's Metropolis on the direct-sum
+    train's amplitudes (the summed terms) away from near-ties."""
+    N, Rr, chi, T, W = 9, 2, 256, 4, 16
+    pi = wl.path_site_plus_perms(N, Rr, 64)
+    bond = wl.open_bonds(N * Rr, chi)
+    bond[1:-1] = 256
+    terms = [wl.gaussian_cores(bond, 65 + t) for t in range(T)]
+    c = np.array([1.0, -0.6, 0.8, 0.3])
+    hs = [R.RTT.create(N, pi, t, "bf16") for t in terms]
+    comb = R.RTT.lincomb(hs, c)
+    qts = device_cores(comb, bond, n_terms=T)
+    amp = lambda S: orc.lincomb_amplitudes(qts, c, pi, S)
+    bits = wl.random_spins(W, N, 66)
+    spins = R.spins_to_device(wl.pack_spins(bits))
+    la = torch.empty(W, dtype=torch.float64, device="cuda")
+    sg = torch.empty(W, dtype=torch.int8, device="cuda")
+    comb.sweep(spins, seed=17, rng_stream=2, sweep0=0, n_sweeps=2, logabs=la, sign=sg)
+    torch.cuda.synchronize()
+    ref, _, margins = mcmc.metropolis(None, pi, bits, seed=17, stream=2, sweep0=0, n_sweeps=2,
+                                      record=True, amp_fn=amp)
+    clean = np.min(np.abs(margins), axis=(0, 1)) > 1e-2   # BF16 ratios: 2e-2-level agreement
+    got = wl.unpack_spins(R.spins_to_host(spins), N)
+    assert clean.sum() >= W // 2
+    assert np.array_equal(got[clean], ref[clean])
+    lref, sref = orc.log_sign(amp(ref))
+    ok = clean
+    assert np.all(sg.cpu().numpy()[ok] == sref[ok])
+    assert np.max(np.abs(la.cpu().numpy()[ok] - lref[ok])) < 2e-2
+
+
+def test_16x16_chi256_four_term_fp8_sampled(R):
+    """The 16x16 periodic TFIM workload (N = 256, R = 2, L = 512, chi = 256,
+    4-term linear combination, FP8 cores): local energies of a few walkers;
+    the oracle recomputes 12 of the 256 flip ratios of walker 0."""
+    w = wl.HUGE_16x16
+    pi, bond = w.pi(), w.bond()
+    hs = [R.RTT.create(w.N, pi, w.cores(t), "fp8") for t in range(w.n_terms)]
+    comb = R.RTT.lincomb(hs, w.coeffs())
+    for h in hs:
+        h.close()
+    print(comb.info)
+    W = 8
+    bits = w.spins(W)
+    ham = R.TFIM(16, 16, w.J, w.h)
+    out = comb.evaluate(R.spins_to_device(wl.pack_spins(bits)), ham)
+    torch.cuda.synchronize()
+    out = {k: v.cpu().numpy() for k, v in out.items()}
+    assert np.all(out["status"] == 0) and np.all(np.isfinite(out["eloc"]))
+    qts = device_cores(comb, bond, n_terms=w.n_terms)
+    js = [0, 1, 17, 63, 64, 100, 128, 129, 200, 230, 254, 255]
+    r_ref = orc.lincomb_flip_ratios(qts, w.coeffs(), pi, bits[:1], which=js)
+    got = out["rsign"][:1, js] * np.exp(out["logratio"][:1, js])
+    rel = np.abs(np.log(np.abs(got)) - np.log(np.abs(r_ref)))
+    print("dlog", rel)
+    assert np.all(np.sign(got) == np.sign(r_ref))
+    assert np.median(rel) < 2e-2
+    # the sweep on the same workload (term-sequential at chi = 256, 4 terms)
+    spins = R.spins_to_device(wl.pack_spins(bits))
+    st = torch.zeros(W, dtype=torch.int32, device="cuda")
+    comb.sweep(spins, seed=w.chain_seed, n_sweeps=1, status=st)
+    torch.cuda.synchronize()
+    assert torch.all(st == 0)
