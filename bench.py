@@ -339,6 +339,8 @@ def main():
     ap.add_argument("--also", default="bf16", help="second precision reported alongside ('' for none)")
     ap.add_argument("--batched", type=int, default=0, help="also time the 256-RTT batch for this many steps")
     ap.add_argument("--learned", action="store_true", help="also compare learned-proposal ESS/s (10x10, chi=128)")
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="only copy this many MiB device-to-device 3 times (counter calibration) and exit")
     a = ap.parse_args()
     if a.gpus != 1:
         print(f"bench.py measures one GPU only: this build has no multi-GPU path (asked for {a.gpus}).",
@@ -347,6 +349,15 @@ def main():
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if a.copy_calibration:
+        n = a.copy_calibration * (1 << 20) // 4
+        src = torch.arange(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copied_bytes_per_launch": n * 4}))
+        return
     res = run(a.dtype, a.steps, a.warmup, not a.no_cpu)
     if a.also and a.also != a.dtype:
         other = run(a.also, a.steps, a.warmup, False)

@@ -9,7 +9,8 @@
 //                  every single-flip ratio, linear-combination sums and the
 //                  TFIM local energy, all in FP64.
 //  chain_kernel    16 walkers per block as the 16 matrix-core columns:
-//                  amplitudes, and Metropolis sweeps with Philox uniforms.
+//                  amplitudes (rows from the left and columns from the right
+//                  meeting half way), and Metropolis sweeps with Philox uniforms.
 //  reduce_kernel   compensated FP64 sums of local energies.
 #pragma once
 #include <float.h>
@@ -276,6 +277,7 @@ __global__ void __launch_bounds__(256) combine_kernel(CombineArgs a) { combine_b
 // ============================================================================
 struct ChainArgs {
   const void* cores;         // [T][L][2][CHI*CHI] forward fragment layout (prescaled)
+  const void* cores_bwd;     // [T][L][2][CHI*CHI] backward fragment layout (prescaled)
   const int32_t* cesum;      // [T][L+1] prefix sums of the per-position scale exponents
   const int32_t* pi;         // [L]
   const uint64_t* rmask;     // [N][LW] bit k set iff position k reads spin j
@@ -292,37 +294,57 @@ struct ChainArgs {
 
 constexpr int kRenormEvery = 4;  // steps between power-of-two renormalisations
 
-// Layout of the 16 walkers' state in LDS (offsets in bytes).  All terms of
-// a linear combination advance together (5 row buffers per term: prefix P,
-// first-step products U and F, ping-pong X and Y) when that fits; otherwise
-// ("sequential") each term keeps only its prefix and the terms share F, X, Y,
-// one term at a time, the prefix being advanced after the decision.
+// Layout of the 16 walkers' state in LDS (offsets in bytes).  Per term: the
+// prefix row P, the first-step products U and F, row ping-pong X/Y and
+// column ping-pong CX/CY (7 buffers), all terms advancing together when that
+// fits; otherwise ("sequential") each term keeps only its prefix and the
+// terms share F, X, Y, CX, CY, one term at a time, the prefix being advanced
+// after the decision.
 struct ChainLayout {
   int rows, exps, vals, pm, sp, total;
   bool seq;
   __host__ __device__ ChainLayout(int chi, int T, int LW, int nw) {
-    const int rs = chi + 4;
-    const int tail = 3 * T * 16 * 4 + T * 16 * 8 + 8 + 16 * LW * 8 + 16 * nw * 8;
-    seq = (T * 5 * 16 * rs * 4 + tail) > 160 * 1024;
-    rows = 0;                                          // float rows
-    exps = rows + (seq ? T + 3 : 5 * T) * 16 * rs * 4; // int [3][T][16]: prefix, first step, running
-    vals = exps + 3 * T * 16 * 4;                      // float [T][16] final values, int [T][16] exponents
-    pm = vals + T * 16 * 8;
+    const int bufb = 16 * (chi + 4) * 4;
+    const int tail = 4 * T * 16 * 4 + T * 16 * 12 + 8 + 16 * LW * 8 + 16 * nw * 8;
+    seq = (T * 7 * bufb + tail) > 160 * 1024;
+    rows = 0;                                      // float vectors
+    exps = rows + (seq ? T + 5 : 7 * T) * bufb;    // int [4][T][16]: prefix, first step, row, column
+    vals = exps + 4 * T * 16 * 4;                  // double [T][16] end values, int [T][16] exponents
+    pm = vals + T * 16 * 12;
     pm = (pm + 7) & ~7;
-    sp = pm + 16 * LW * 8;                             // uint64 [16][LW] position bits; [16][nw] spins
+    sp = pm + 16 * LW * 8;                         // uint64 [16][LW] position bits; [16][nw] spins
     total = sp + 16 * nw * 8;
   }
 };
 
+// Waves per side of the chain kernel: two sides of up to four waves, except
+// that wide bonds keep one wave per SIMD (their fragments need the whole
+// register file) with two waves per side.
+template <int CHI>
+struct ChainGeo {
+  static constexpr int SW = CHI >= 128 ? 2 : Geo<CHI>::WPW;  // waves per side
+  static constexpr int MT = CHI / (16 * SW);                   // output tiles per wave
+  static constexpr int NT = 2 * SW * 64;                       // threads per block
+};
+
+// Block of 2 * SW waves for 16 walkers (the 16 matrix-core columns).  Every
+// amplitude is contracted from both ends at once: the first SW waves carry
+// row vectors from the left (forward fragment layout), the other SW waves
+// column vectors from the right boundary (backward layout); the two meet
+// half way and are joined by an FP64 dot product.  The number of dependent
+// steps per amplitude is halved and each SIMD runs two independent chains.
 template <class D, int CHI>
-__device__ __forceinline__ void chain_body(const ChainArgs& a, int bx) {
+__device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t sweep0) {
   using E = typename D::elem;
   using G = Geo<CHI>;
-  constexpr int RS = G::RS, MT = G::MT, KPL = G::KPL;
+  constexpr int RS = G::RS, KPL = G::KPL;
+  constexpr int MT = ChainGeo<CHI>::MT, SW = ChainGeo<CHI>::SW;
   constexpr int BUF = 16 * RS;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int side = wave / SW;    // 0: rows from the left, 1: columns from the right
+  const int wv = wave % SW;      // wave within its side
   const int g = lane >> 4, m = lane & 15;
-  const int nthr = blockDim.x;
+  const int nthr = blockDim.x, nwave = nthr >> 6;
   const int T = a.T, L = a.L, LW = a.LW, nw = a.nw;
   extern __shared__ __align__(16) unsigned char lds_raw[];
   const ChainLayout lay(CHI, T, LW, nw);
@@ -330,22 +352,24 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx) {
   int* Ep = reinterpret_cast<int*>(lds_raw + lay.exps);   // [T][16] prefix
   int* Ef = Ep + T * 16;                                   // [T][16] after the first step
   int* Er = Ef + T * 16;                                   // [T][16] running row
-  float* fval = reinterpret_cast<float*>(lds_raw + lay.vals);   // [T][16] final feature 0
-  int* fexp = reinterpret_cast<int*>(fval + T * 16);           // [T][16] its exponent
+  int* Ec = Er + T * 16;                                   // [T][16] running column
+  double* fval = reinterpret_cast<double*>(lds_raw + lay.vals);  // [T][16] amplitude mantissas
+  int* fexp = reinterpret_cast<int*>(fval + T * 16);             // [T][16] their exponents
   uint64_t* pm = reinterpret_cast<uint64_t*>(lds_raw + lay.pm);
   uint64_t* sp = reinterpret_cast<uint64_t*>(lds_raw + lay.sp);
   const bool seq = lay.seq;
+  const int nbuf = seq ? T + 5 : 7 * T;
 
-  enum { P = 0, U = 1, F = 2, X = 3, Y = 4 };
+  enum { P = 0, U = 1, F = 2, X = 3, Y = 4, CX = 5, CY = 6 };
   auto buf = [&](int t, int b) {
-    if (!seq) return rows + (t * 5 + b) * BUF;
+    if (!seq) return rows + (t * 7 + b) * BUF;
     return b == P ? rows + t * BUF : rows + (T + b - F) * BUF;  // U is not used then
   };
 
   const int w0 = bx * 16;
   const bool live = (w0 + m) < a.W;
-  for (int i = threadIdx.x; i < T * 5 * BUF; i += nthr) rows[i] = 0.f;
-  for (int i = threadIdx.x; i < 3 * T * 16; i += nthr) Ep[i] = 0;
+  for (int i = threadIdx.x; i < nbuf * BUF; i += nthr) rows[i] = 0.f;
+  for (int i = threadIdx.x; i < 4 * T * 16; i += nthr) Ep[i] = 0;
   for (int i = threadIdx.x; i < 16 * nw; i += nthr) {
     const int n = i / nw, wd = i % nw;
     sp[i] = (w0 + n < a.W) ? a.spins[(size_t)(w0 + n) * nw + wd] : 0ull;
@@ -361,102 +385,142 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx) {
     pm[i] = word;
   }
 
-  const E* cores = static_cast<const E*>(a.cores);
+  const E* cores = static_cast<const E*>(side == 0 ? a.cores : a.cores_bwd);
   const size_t lane_off = (size_t)lane * KPL;
   struct Frags { E f0[KPL]; E f1[KPL]; };
   typename D::template BOp<KPL> bo;
 
-  // Advance the rows of every term from buffer `from` through positions
-  // [k0, k1) with spin jflip flipped (-1: none).  Work items are (position,
-  // term, output tile) in that order; the two core fragments of the next
-  // item are loaded while the current one computes.  With `split` the first
-  // step stores the walker's own slice product in F and the other slice's
-  // in U.  Rows are renormalised every kRenormEvery steps; the running
-  // exponent sum lives in Er.  Returns the buffer holding the result.
-  auto segment = [&](int from, int k0, int k1, int jflip, bool split, int t0, int tn) -> int {
-    if (k1 <= k0) return from;
-    int cur = from, out = split ? F : X;
-    int bit = 0;
-    uint64_t word = 0;
-    const uint64_t* rmj = jflip >= 0 ? a.rmask + (size_t)jflip * LW : nullptr;
-    const int tend = t0 + tn;
-    int k = k0, t = t0, mt = 0;
-    auto load = [&](Frags& Fr, int kk, int tt, int mm) {
-      const E* base = cores + (((size_t)tt * L + kk) * 2) * (CHI * CHI) +
-                      (size_t)(wv * MT + mm) * 64 * KPL + lane_off;
-      load_frag<KPL>(Fr.f0, base);
-      load_frag<KPL>(Fr.f1, base + CHI * CHI);
-    };
-    auto step = [&](const Frags& Fr) {
-      if (t == t0 && mt == 0 && (k == k0 || (k & 63) == 0)) {
-        word = pm[m * LW + (k >> 6)] ^ (rmj ? rmj[k >> 6] : 0ull);
-      }
-      if (t == t0 && mt == 0) bit = (int)((word >> (k & 63)) & 1ull);
-      if (mt == 0) {
-        float v[KPL];
-        lds_read<KPL>(v, buf(t, cur) + m * RS + g * KPL);
-        if ((k - k0) % kRenormEvery == 0) {
-          const int e = renorm_row<KPL>(v);
-          if (wv == 0 && g == 0) {
-            if (split && k == k0) {
-              const int ne = Ep[t * 16 + m] + e;
-              Ef[t * 16 + m] = ne;
-              Er[t * 16 + m] = ne;
-            } else {
-              Er[t * 16 + m] = (k == k0 ? Ep[t * 16 + m] : Er[t * 16 + m]) + e;
+  // Results of the last segment: rb holds the rows, cb the columns (-1: the
+  // right boundary vector itself).  Every wave knows both.
+  int rb = P, cb = -1;
+
+  // For terms [t0, t0+tn) with spin jflip flipped (-1: none): advance the
+  // row vectors from P through positions [k0, k1) and, at the same time,
+  // column vectors from the right boundary through positions L-1 down to kc.
+  // Work items of a wave are (step, term, output tile) in that order; the
+  // two core fragments of the next item are loaded while the current one
+  // computes.  Each joint step ends with one block barrier (the side with
+  // fewer steps still takes part).  With `split` the first row step stores
+  // the walker's own slice product in F and the other slice's in U.  Vectors
+  // are renormalised every kRenormEvery steps; the exponent sums live in Er
+  // and Ec.
+  auto segment = [&](int k0, int k1, int kc, int jflip, bool split, int t0, int tn) {
+    const int nr = k1 > k0 ? k1 - k0 : 0, nc = L - kc;
+    if (nr == 0) rb = P;
+    else if (split) rb = nr == 1 ? F : (((nr - 1) & 1) ? X : Y);
+    else rb = (nr & 1) ? X : Y;
+    cb = nc == 0 ? -1 : ((nc & 1) ? CX : CY);
+    const int S = nr > nc ? nr : nc;
+    const int n = side == 0 ? nr : nc;
+    if (n > 0) {
+      const uint64_t* rmj = jflip >= 0 ? a.rmask + (size_t)jflip * LW : nullptr;
+      int cur = side == 0 ? P : -1;
+      int out = side == 0 ? (split ? F : X) : CX;
+      const int tend = t0 + tn;
+      int i = 0, t = t0, mt = 0, bit = 0;
+      uint64_t word = 0;
+      auto pos_of = [&](int ii) { return side == 0 ? k0 + ii : L - 1 - ii; };
+      auto load = [&](Frags& Fr, int ii, int tt, int mm) {
+        const int kk = pos_of(ii < n ? ii : n - 1);
+        const E* base = cores + (((size_t)tt * L + kk) * 2) * (CHI * CHI) +
+                        (size_t)(wv * MT + mm) * 64 * KPL + lane_off;
+        load_frag<KPL>(Fr.f0, base);
+        load_frag<KPL>(Fr.f1, base + CHI * CHI);
+      };
+      auto step = [&](const Frags& Fr) {
+        const int k = pos_of(i);
+        if (t == t0 && mt == 0) {
+          if (i == 0 || (k & 63) == (side == 0 ? 0 : 63))
+            word = pm[m * LW + (k >> 6)] ^ (rmj ? rmj[k >> 6] : 0ull);
+          bit = (int)((word >> (k & 63)) & 1ull);
+        }
+        if (mt == 0) {
+          float v[KPL];
+          if (cur < 0) {  // the right boundary vector e_0
+#pragma unroll
+            for (int e = 0; e < KPL; ++e) v[e] = (g == 0 && e == 0) ? 1.f : 0.f;
+            if (wv == 0 && g == 0) Ec[t * 16 + m] = 0;
+          } else {
+            lds_read<KPL>(v, buf(t, cur) + m * RS + g * KPL);
+            if (i % kRenormEvery == 0) {
+              const int e = renorm_row<KPL>(v);
+              if (wv == 0 && g == 0) {
+                if (side == 1) {
+                  Ec[t * 16 + m] += e;
+                } else if (split && i == 0) {
+                  const int ne = Ep[t * 16 + m] + e;
+                  Ef[t * 16 + m] = ne;
+                  Er[t * 16 + m] = ne;
+                } else {
+                  Er[t * 16 + m] = (i == 0 ? Ep[t * 16 + m] : Er[t * 16 + m]) + e;
+                }
+              }
             }
           }
+          D::template prep<KPL>(v, bo);
         }
-        D::template prep<KPL>(v, bo);
+        f4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
+        D::template mma2<KPL>(Fr.f0, Fr.f1, bo, c0, c1);
+        const int tt = wv * MT + mt;
+        const f4 sel = bit ? c1 : c0;
+        *reinterpret_cast<float4*>(buf(t, out) + m * RS + 16 * tt + 4 * g) =
+            make_float4(sel[0], sel[1], sel[2], sel[3]);
+        if (split && side == 0 && i == 0) {
+          const f4 oth = bit ? c0 : c1;
+          *reinterpret_cast<float4*>(buf(t, U) + m * RS + 16 * tt + 4 * g) =
+              make_float4(oth[0], oth[1], oth[2], oth[3]);
+        }
+        if (mt == MT - 1 && t == tend - 1) {
+          lds_barrier();
+          cur = out;
+          out = side == 0 ? ((cur == X) ? Y : X) : ((cur == CX) ? CY : CX);
+        }
+        if (++mt == MT) { mt = 0; if (++t == tend) { t = t0; ++i; } }
+      };
+      auto next_of = [&](int& ii, int& tt, int& mm) {
+        if (++mm == MT) { mm = 0; if (++tt == tend) { tt = t0; ++ii; } }
+      };
+      // The prefetch is issued on every path (past the end it re-reads the
+      // last position) so the number of loads in flight is the same on all
+      // paths and the wait before the matrix ops only covers the current item.
+      Frags FA, FB;
+      load(FA, 0, t0, 0);
+      while (true) {
+        int ni = i, nt = t, nm = mt;
+        next_of(ni, nt, nm);
+        load(FB, ni, nt, nm);
+        step(FA);
+        if (i >= n) break;
+        ni = i; nt = t; nm = mt;
+        next_of(ni, nt, nm);
+        load(FA, ni, nt, nm);
+        step(FB);
+        if (i >= n) break;
       }
-      f4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
-      D::template mma2<KPL>(Fr.f0, Fr.f1, bo, c0, c1);
-      const int tt = wv * MT + mt;
-      const f4 sel = bit ? c1 : c0;
-      *reinterpret_cast<float4*>(buf(t, out) + m * RS + 16 * tt + 4 * g) =
-          make_float4(sel[0], sel[1], sel[2], sel[3]);
-      if (split && k == k0) {
-        const f4 oth = bit ? c0 : c1;
-        *reinterpret_cast<float4*>(buf(t, U) + m * RS + 16 * tt + 4 * g) =
-            make_float4(oth[0], oth[1], oth[2], oth[3]);
-      }
-      if (mt == MT - 1 && t == tend - 1) {
-        lds_barrier();
-        cur = out;
-        out = (cur == X) ? Y : X;
-      }
-      if (++mt == MT) { mt = 0; if (++t == tend) { t = t0; ++k; } }
-    };
-    auto next_of = [&](int& kk, int& tt, int& mm) {
-      if (++mm == MT) { mm = 0; if (++tt == tend) { tt = t0; ++kk; } }
-    };
-    // The prefetch is issued on every path (past the end it re-reads the
-    // last position) so the number of loads in flight is the same on all
-    // paths and the wait before the matrix ops only covers the current item.
-    Frags FA, FB;
-    load(FA, k, t, mt);
-    while (true) {
-      int nk = k, nt = t, nm = mt;
-      next_of(nk, nt, nm);
-      load(FB, nk < k1 ? nk : k1 - 1, nt, nm);
-      step(FA);
-      if (k >= k1) break;
-      nk = k; nt = t; nm = mt;
-      next_of(nk, nt, nm);
-      load(FA, nk < k1 ? nk : k1 - 1, nt, nm);
-      step(FB);
-      if (k >= k1) break;
     }
-    return cur;
+    for (int r = n; r < S; ++r) lds_barrier();
   };
 
-  // record feature 0 of buffer b (the end of the train) for terms [t0, t0+tn)
-  auto record = [&](int b, int t0, int tn) {
-    if (wv == 0 && g == 0)
-      for (int t = t0; t < t0 + tn; ++t) {
-        fval[t * 16 + m] = buf(t, b)[m * RS];
-        fexp[t * 16 + m] = Er[t * 16 + m] + a.cesum[(size_t)t * (L + 1) + L];
+  // Join rows rb and columns cb of terms [t0, t0+tn): FP64 dot product per
+  // walker (one wave per term, four lanes per walker) and its exponent.
+  auto record = [&](int t0, int tn) {
+    for (int t = t0 + wave; t < t0 + tn; t += nwave) {
+      const float* r = buf(t, rb) + m * RS + g * KPL;
+      double s = 0.0;
+      if (cb < 0) {
+        s = (g == 0) ? (double)r[0] : 0.0;
+      } else {
+        const float* c = buf(t, cb) + m * RS + g * KPL;
+        for (int e = 0; e < KPL; ++e) s = fma((double)r[e], (double)c[e], s);
       }
+      s += __shfl_xor(s, 16);
+      s += __shfl_xor(s, 32);
+      if (g == 0) {
+        fval[t * 16 + m] = s;
+        fexp[t * 16 + m] = Er[t * 16 + m] + (cb < 0 ? 0 : Ec[t * 16 + m]) +
+                           a.cesum[(size_t)t * (L + 1) + L];
+      }
+    }
     __syncthreads();
   };
   // combined amplitude of this lane's walker from the recorded values:
@@ -467,7 +531,7 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx) {
     int emax = INT_MIN;
     for (int t = 0; t < T; ++t) {
       int ed = 0;
-      const double md = frexp((double)fval[t * 16 + m], &ed);
+      const double md = frexp(fval[t * 16 + m], &ed);
       ms[t] = a.coeffs[t] * md;
       es[t] = fexp[t * 16 + m] + ed;
       if (ms[t] != 0.0 && es[t] > emax) emax = es[t];
@@ -490,6 +554,8 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx) {
     }
     for (int i = threadIdx.x; i < T * 16; i += nthr) Ep[i] = 0;
   };
+  // the meeting bond of a contraction that starts at position f
+  auto meet = [&](int f) { return f + (L - f + 1) / 2; };
 
   // amplitude of the current configuration (identical in every lane of a walker)
   reset_prefix();
@@ -498,10 +564,13 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx) {
   int sgn, stat;
   uint32_t nacc = 0;
   if (!seq) {
-    const int fin = segment(P, 0, L, -1, false, 0, T);
-    record(fin, 0, T);
+    segment(0, meet(0), meet(0), -1, false, 0, T);
+    record(0, T);
   } else {
-    for (int t = 0; t < T; ++t) record(segment(P, 0, L, -1, false, t, 1), t, 1);
+    for (int t = 0; t < T; ++t) {
+      segment(0, meet(0), meet(0), -1, false, t, 1);
+      record(t, 1);
+    }
   }
   amp(lab, sgn);
   stat = (sgn != 0 && isfinite(lab)) ? 0 : -5;
@@ -509,7 +578,7 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx) {
 
   if (a.mode == 1) {
     for (int ts = 0; ts < a.n_sweeps; ++ts) {
-      const uint64_t sweep = a.sweep0 + (uint64_t)ts;
+      const uint64_t sweep = sweep0 + (uint64_t)ts;
       reset_prefix();
       __syncthreads();
       int pos = 0;
@@ -519,17 +588,17 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx) {
         if (f < 0) {  // spin read by no position: ratio 1, always accepted
           if (live && stat == 0) {
             nacc += 1;
-            if (wv == 0 && g == 0) sp[m * nw + (j >> 6)] ^= (1ull << (j & 63));
+            if (wave == 0 && g == 0) sp[m * nw + (j >> 6)] ^= (1ull << (j & 63));
           }
           __syncthreads();
           continue;
         }
         // bring the prefix of terms [t0, t0+tn) from pos up to position kk
         auto advance_prefix = [&](int kk, int t0, int tn) {
-          const int fin = segment(P, pos, kk, -1, false, t0, tn);
+          segment(pos, kk, L, -1, false, t0, tn);
           for (int i = threadIdx.x; i < tn * 16 * RS; i += nthr) {
             const int t = t0 + i / (16 * RS), r = i % (16 * RS);
-            buf(t, P)[r] = buf(t, fin)[r];
+            buf(t, P)[r] = buf(t, rb)[r];
           }
           for (int i = threadIdx.x; i < tn * 16; i += nthr) Ep[t0 * 16 + i] = Er[t0 * 16 + i];
           __syncthreads();
@@ -539,12 +608,18 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx) {
           else for (int t = 0; t < T; ++t) advance_prefix(f, t, 1);
           pos = f;
         }
-        // the flipped row from position f to the end; with all terms at once
-        // the first step also leaves the unflipped prefix extension in U
+        // the flipped amplitude from position f, rows and columns meeting
+        // half way; with all terms at once the first row step also leaves
+        // the unflipped prefix extension in U
+        const int c = meet(f);
         if (!seq) {
-          record(segment(P, f, L, j, true, 0, T), 0, T);
+          segment(f, c, c, j, true, 0, T);
+          record(0, T);
         } else {
-          for (int t = 0; t < T; ++t) record(segment(P, f, L, j, false, t, 1), t, 1);
+          for (int t = 0; t < T; ++t) {
+            segment(f, c, c, j, false, t, 1);
+            record(t, 1);
+          }
         }
         int accept = 0;
         if (live && stat == 0) {
@@ -563,7 +638,7 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx) {
           }
         }
         // prefix through position f with the decided s_j
-        if (!seq) {  // each lane copies the features it wrote in the first step
+        if (!seq && side == 0) {  // each row lane copies the features it wrote in the first step
           for (int t = 0; t < T; ++t)
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt) {
@@ -572,7 +647,7 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx) {
                   *reinterpret_cast<const float4*>(buf(t, accept ? F : U) + off);
             }
         }
-        if (wv == 0 && g == 0) {
+        if (wave == 0 && g == 0) {
           if (!seq)
             for (int t = 0; t < T; ++t) Ep[t * 16 + m] = Ef[t * 16 + m];
           if (accept) {
@@ -590,7 +665,7 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx) {
   }
 
   // write back
-  if (wv == 0 && g == 0 && live) {
+  if (wave == 0 && g == 0 && live) {
     const int w = w0 + m;
     if (a.mode == 1)
       for (int wd = 0; wd < nw; ++wd) a.spins[(size_t)w * nw + wd] = sp[m * nw + wd];
@@ -603,8 +678,8 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx) {
 }
 
 template <class D, int CHI>
-__global__ void __launch_bounds__(64 * Geo<CHI>::WPW) chain_kernel(ChainArgs a) {
-  chain_body<D, CHI>(a, blockIdx.x);
+__global__ void __launch_bounds__(ChainGeo<CHI>::NT) chain_kernel(ChainArgs a) {
+  chain_body<D, CHI>(a, blockIdx.x, a.sweep0);
 }
 
 // ============================================================================
@@ -692,18 +767,17 @@ __global__ void __launch_bounds__(256) pass_persistent(const PassArgs* descs, co
 }
 
 template <class D, int CHI>
-__global__ void __launch_bounds__(64 * Geo<CHI>::WPW) chain_persistent(const ChainArgs* descs,
+__global__ void __launch_bounds__(ChainGeo<CHI>::NT) chain_persistent(const ChainArgs* descs,
                                                                         const int4* items, int n_items,
                                                                         int* counter,
                                                                         const uint64_t* sweep0) {
   __shared__ int s_item;
   for (;;) {
-    const int it = next_item(counter, &s_item);
+    // uniform item index: the descriptor's fields are then scalar loads
+    const int it = __builtin_amdgcn_readfirstlane(next_item(counter, &s_item));
     if (it >= n_items) break;
     const int4 w = items[it];
-    ChainArgs a = descs[w.x];
-    a.sweep0 = *sweep0;
-    chain_body<D, CHI>(a, w.y);
+    chain_body<D, CHI>(descs[w.x], w.y, *sweep0);
     __syncthreads();
   }
 }

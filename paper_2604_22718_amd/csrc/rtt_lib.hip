@@ -405,12 +405,11 @@ rtt_status launch_pass(const rttk::PassArgs& a, int T, hipStream_t s) {
 
 template <class D, int CHI>
 rtt_status launch_chain(const rttk::ChainArgs& a, hipStream_t s) {
-  constexpr int WPW = rttk::Geo<CHI>::WPW;
   const size_t lds = chain_lds_bytes(CHI, a.T, a.L, a.nw);
   auto kfn = rttk::chain_kernel<D, CHI>;
   HIPX(hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   dim3 grid((a.W + 15) / 16);
-  hipLaunchKernelGGL(kfn, grid, dim3(64 * WPW), lds, s, a);
+  hipLaunchKernelGGL(kfn, grid, dim3(rttk::ChainGeo<CHI>::NT), lds, s, a);
   HIPX(hipGetLastError());
   return RTT_OK;
 }
@@ -704,7 +703,7 @@ static rtt_status chain_common(rtt_t h, int32_t W, uint64_t* spins, double* loga
   if (!spins) return fail(RTT_E_ARG, "spins is null");
   if (n_sweeps < 0) return fail(RTT_E_ARG, "n_sweeps = %d < 0", n_sweeps);
   rttk::ChainArgs ca{};
-  ca.cores = h->d_fwd;
+  ca.cores = h->d_fwd; ca.cores_bwd = h->d_bwd;
   ca.cesum = h->d_cesum;
   ca.rmask = h->d_rmask;
   ca.pi = h->d_pi; ca.order = h->d_order; ca.first = h->d_first; ca.coeffs = h->d_coeffs;
@@ -808,7 +807,7 @@ struct BatchL {
     if (phase == 0) {
       if (c.chain_items.empty()) return RTT_OK;
       auto kfn = rttk::chain_persistent<D, CHI>;
-      hipLaunchKernelGGL(kfn, dim3(c.grid_chain), dim3(64 * rttk::Geo<CHI>::WPW), c.chain_lds, s, c.d_chain,
+      hipLaunchKernelGGL(kfn, dim3(c.grid_chain), dim3(rttk::ChainGeo<CHI>::NT), c.chain_lds, s, c.d_chain,
                          c.d_chain_items, (int)c.chain_items.size(), counters, sweep0);
     } else {
       if (c.pass_items.empty()) return RTT_OK;
@@ -1028,7 +1027,7 @@ rtt_status rtt_batch_create(int32_t n, const rtt_t* rtts, const rtt_ham_t* hams,
       rtt_s* h = b->rtts[i];
       const int W = b->W[i];
       rttk::ChainArgs ca{};
-      ca.cores = h->d_fwd; ca.cesum = h->d_cesum; ca.rmask = h->d_rmask; ca.pi = h->d_pi;
+      ca.cores = h->d_fwd; ca.cores_bwd = h->d_bwd; ca.cesum = h->d_cesum; ca.rmask = h->d_rmask; ca.pi = h->d_pi;
       ca.order = h->d_order; ca.first = h->d_first; ca.coeffs = h->d_coeffs;
       ca.T = h->T; ca.L = h->L; ca.N = h->N; ca.nw = h->nw; ca.LW = (h->L + 63) / 64; ca.W = W;
       ca.spins = b->spins[i]; ca.seed = seed; ca.rstream = (uint64_t)i; ca.mode = 1;
