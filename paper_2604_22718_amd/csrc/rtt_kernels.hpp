@@ -21,6 +21,7 @@
 namespace rttk {
 
 constexpr int kMaxTerms = 8;
+constexpr int kRenormEvery = 4;  // steps between power-of-two renormalisations
 
 template <int CHI>
 struct Geo {
@@ -105,11 +106,14 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int bx, int ty) {
     const int t = wv * MT + mt;
     const int cexp = cexp_p ? cexp_p[k] : 0;
     const int ntile = (nact + 15) >> 4;
+    // rows are renormalised every kRenormEvery steps: between two, a row
+    // grows by at most a factor chi per step (core entries below 1)
+    const bool rn = (s % kRenormEvery) == 0;
     for (int r = 0; r < ntile; ++r) {
       const int row = 16 * r + m;
       float v[KPL];
       lds_read<KPL>(v, cur + row * RS + g * KPL);
-      const int e = renorm_row<KPL>(v);
+      const int e = rn ? renorm_row<KPL>(v) : 0;
       if (mt == 0 && wv == 0 && g == 0) exn[row] = exc[row] + e + cexp;
       typename D::template BOp<KPL> bo;
       D::template prep<KPL>(v, bo);
@@ -122,7 +126,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int bx, int ty) {
       const int oin = odd & 0xffff, oout = odd >> 16;
       float v[KPL];
       lds_read<KPL>(v, cur + oin * RS + g * KPL);
-      const int e = renorm_row<KPL>(v);
+      const int e = rn ? renorm_row<KPL>(v) : 0;
       float p = 0.f;
 #pragma unroll
       for (int c = 0; c < KPL; ++c) p = fmaf(D::to_f32(F.o[c]), v[c], p);
@@ -292,8 +296,6 @@ struct ChainArgs {
   int mode;                  // 0: amplitudes only, 1: sweeps
 };
 
-constexpr int kRenormEvery = 4;  // steps between power-of-two renormalisations
-
 // Layout of the 16 walkers' state in LDS (offsets in bytes).  Per term: the
 // prefix row P, the first-step products U and F, row ping-pong X/Y and
 // column ping-pong CX/CY (7 buffers), all terms advancing together when that
@@ -325,6 +327,7 @@ struct ChainGeo {
   static constexpr int SW = CHI >= 128 ? 2 : Geo<CHI>::WPW;  // waves per side
   static constexpr int MT = CHI / (16 * SW);                   // output tiles per wave
   static constexpr int NT = 2 * SW * 64;                       // threads per block
+  static constexpr int PF = 2;                                 // fragment sets in flight + 1
 };
 
 // Block of 2 * SW waves for 16 walkers (the 16 matrix-core columns).  Every
@@ -338,7 +341,7 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
   using E = typename D::elem;
   using G = Geo<CHI>;
   constexpr int RS = G::RS, KPL = G::KPL;
-  constexpr int MT = ChainGeo<CHI>::MT, SW = ChainGeo<CHI>::SW;
+  constexpr int MT = ChainGeo<CHI>::MT, SW = ChainGeo<CHI>::SW, PF = ChainGeo<CHI>::PF;
   constexpr int BUF = 16 * RS;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int side = wave / SW;    // 0: rows from the left, 1: columns from the right
@@ -480,23 +483,27 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
       auto next_of = [&](int& ii, int& tt, int& mm) {
         if (++mm == MT) { mm = 0; if (++tt == tend) { tt = t0; ++ii; } }
       };
-      // The prefetch is issued on every path (past the end it re-reads the
-      // last position) so the number of loads in flight is the same on all
-      // paths and the wait before the matrix ops only covers the current item.
-      Frags FA, FB;
-      load(FA, 0, t0, 0);
-      while (true) {
-        int ni = i, nt = t, nm = mt;
-        next_of(ni, nt, nm);
-        load(FB, ni, nt, nm);
-        step(FA);
-        if (i >= n) break;
-        ni = i; nt = t; nm = mt;
-        next_of(ni, nt, nm);
-        load(FA, ni, nt, nm);
-        step(FB);
-        if (i >= n) break;
+      // A ring of PF fragment sets: the loads run PF - 1 items ahead of the
+      // matrix ops.  They are issued on every path (past the end they
+      // re-read the last position) so the number of loads in flight is the
+      // same on all paths and each wait covers only the item about to be used.
+      Frags FR[PF];
+      int li = 0, lt = t0, lm = 0;  // load cursor
+#pragma unroll
+      for (int q = 0; q < PF - 1; ++q) {
+        load(FR[q], li, lt, lm);
+        next_of(li, lt, lm);
       }
+      while (true) {
+#pragma unroll
+        for (int r = 0; r < PF; ++r) {
+          load(FR[(r + PF - 1) % PF], li, lt, lm);
+          next_of(li, lt, lm);
+          step(FR[r]);
+          if (i >= n) goto segment_done;
+        }
+      }
+    segment_done:;
     }
     for (int r = n; r < S; ++r) lds_barrier();
   };
