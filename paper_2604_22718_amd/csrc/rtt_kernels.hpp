@@ -185,8 +185,12 @@ struct CombineArgs {
   double* logabs; int8_t* sign; double* logratio; int8_t* rsign; double* eloc; int32_t* status;
 };
 
-// value = mant * 2^ex with |mant| in [0.5, 1) (mant = 0 for zero)
-__device__ inline void combined_value(const CombineArgs& a, int w, int gi, int fs, int bs,
+// value = mant * 2^ex with |mant| in [0.5, 1) (mant = 0 for zero) of the
+// combined amplitude whose forward row is slot fs and backward row slot bs
+// of row group gi.  Sixteen lanes (c16 = lane % 16) share one dot product:
+// each reads every 16th float4 of the two rows (coalesced 256-byte runs per
+// row), FP64 partial sums meet by butterfly; all sixteen lanes return it.
+__device__ inline void combined_value(const CombineArgs& a, int w, int gi, int fs, int bs, int c16,
                                       double& mant, int& ex) {
   double ms[kMaxTerms];
   int es[kMaxTerms];
@@ -196,7 +200,7 @@ __device__ inline void combined_value(const CombineArgs& a, int w, int gi, int f
     const float* pu = a.u + ((ty * a.W + w) * a.nsf + fs) * a.chi;
     const float* pv = a.v + ((ty * a.W + w) * a.nsb + bs) * a.chi;
     double d = 0.0;
-    for (int f = 0; f < a.chi; f += 4) {
+    for (int f = 4 * c16; f < a.chi; f += 64) {
       const float4 x = *reinterpret_cast<const float4*>(pu + f);
       const float4 y = *reinterpret_cast<const float4*>(pv + f);
       d = fma((double)x.x, (double)y.x, d);
@@ -204,6 +208,10 @@ __device__ inline void combined_value(const CombineArgs& a, int w, int gi, int f
       d = fma((double)x.z, (double)y.z, d);
       d = fma((double)x.w, (double)y.w, d);
     }
+    d += __shfl_xor(d, 8);
+    d += __shfl_xor(d, 4);
+    d += __shfl_xor(d, 2);
+    d += __shfl_xor(d, 1);
     int ed = 0;
     const double md = frexp(d, &ed);
     ms[t] = a.coeffs[t] * md;
@@ -224,13 +232,16 @@ __device__ inline double wave_sum(double x) {
   return x;
 }
 
+// One wave per walker; the wave's four 16-lane groups take four spins at a
+// time.  Writes log|psi|, sign, status, every log|r_j| and sign, and E_loc.
 __device__ __forceinline__ void combine_body(const CombineArgs& a, int bx) {
   const int lane = threadIdx.x & 63;
+  const int q = lane >> 4, c16 = lane & 15;
   const int w = bx * 4 + (threadIdx.x >> 6);
   if (w >= a.W) return;
   const double LN2 = 0.69314718055994530942;
   double m0; int e0;
-  combined_value(a, w, 0, 0, 0, m0, e0);
+  combined_value(a, w, 0, 0, 0, c16, m0, e0);
   const bool ok = (m0 != 0.0) && isfinite(m0);
   const double lab0 = ok ? log(fabs(m0)) + e0 * LN2 : NAN;
   if (lane == 0) {
@@ -239,7 +250,9 @@ __device__ __forceinline__ void combine_body(const CombineArgs& a, int bx) {
     if (a.status) a.status[w] = ok ? 0 : -5;
   }
   double rsum = 0.0;
-  for (int j = lane; j < a.N; j += 64) {
+  for (int j0 = 0; j0 < a.N; j0 += 4) {
+    const bool valid = j0 + q < a.N;
+    const int j = valid ? j0 + q : a.N - 1;  // every group takes part in its butterfly
     const int fs = a.fslot[j], bs = a.bslot[j];
     double lr = NAN, r = NAN;
     int8_t sg = 0;
@@ -248,7 +261,7 @@ __device__ __forceinline__ void combine_body(const CombineArgs& a, int bx) {
         lr = 0.0; sg = 1; r = 1.0;
       } else {
         double mj; int ej;
-        combined_value(a, w, a.grp[j], fs, bs, mj, ej);
+        combined_value(a, w, a.grp[j], fs, bs, c16, mj, ej);
         if (mj == 0.0) { lr = -INFINITY; sg = 1; r = 0.0; }
         else {
           lr = log(fabs(mj)) - log(fabs(m0)) + (double)(ej - e0) * LN2;
@@ -257,9 +270,11 @@ __device__ __forceinline__ void combine_body(const CombineArgs& a, int bx) {
         }
       }
     }
-    if (a.logratio) a.logratio[(size_t)w * a.N + j] = lr;
-    if (a.rsign) a.rsign[(size_t)w * a.N + j] = sg;
-    rsum += ok ? r : 0.0;
+    if (valid && c16 == 0) {
+      if (a.logratio) a.logratio[(size_t)w * a.N + j] = lr;
+      if (a.rsign) a.rsign[(size_t)w * a.N + j] = sg;
+      rsum += ok ? r : 0.0;
+    }
   }
   if (a.eloc) {
     const uint64_t* sw = a.spins + (size_t)w * a.nw;
