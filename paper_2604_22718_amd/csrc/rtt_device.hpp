@@ -195,6 +195,109 @@ __device__ __forceinline__ int renorm_row(float (&v)[KPL]) {
   return e;
 }
 
+// ---------------------------------------------------------------- activation rows
+// Act<D, CHI> keeps a row of CHI activations in LDS in the form the matrix
+// ops take, so that the wave producing a value converts it once instead of
+// every consuming wave converting it again: FP32 values for FP32 cores; for
+// BF16 cores the hi and lo BF16 parts, hi = RNE(x), lo = RNE(x - hi) (the
+// same pair the MFMA would be fed from x).  Either way a row is CHI dwords
+// (BF16: hi[0..CHI) then lo[0..CHI) as 16-bit words).
+template <class D, int CHI>
+struct Act;
+
+template <int CHI>
+struct Act<DF32, CHI> {
+  template <int KPL>
+  __device__ __forceinline__ static void load_b(const float* row, int g, DF32::BOp<KPL>& b) {
+    lds_read<KPL>(b.v, row + g * KPL);
+  }
+  // exponent e of the row's largest |x| (all four K-groups), max * 2^-e in [0.5, 1)
+  template <int KPL>
+  __device__ __forceinline__ static int row_exp(const DF32::BOp<KPL>& b) {
+    float mx = 0.f;
+#pragma unroll
+    for (int c = 0; c < KPL; ++c) mx = fmaxf(mx, fabsf(b.v[c]));
+    mx = group_max(mx);
+    return (mx > 0.f) ? __builtin_amdgcn_frexp_expf(mx) : 0;
+  }
+  template <int KPL>
+  __device__ __forceinline__ static void load_f32(const float* row, int g, float (&v)[KPL]) {
+    lds_read<KPL>(v, row + g * KPL);
+  }
+  __device__ __forceinline__ static void store4(float* row, int col, f4 v) {
+    *reinterpret_cast<float4*>(row + col) = make_float4(v[0], v[1], v[2], v[3]);
+  }
+  __device__ __forceinline__ static void store1(float* row, int col, float x) { row[col] = x; }
+  __device__ __forceinline__ static float get(const float* row, int i) { return row[i]; }
+  __device__ __forceinline__ static void set_unit(float* row) { row[0] = 1.f; }
+};
+
+template <int CHI>
+struct Act<DBF16, CHI> {
+  __device__ __forceinline__ static const uint16_t* hi(const float* row) {
+    return reinterpret_cast<const uint16_t*>(row);
+  }
+  __device__ __forceinline__ static uint16_t* hi(float* row) { return reinterpret_cast<uint16_t*>(row); }
+  template <int KPL>
+  __device__ __forceinline__ static void load_b(const float* row, int g, DBF16::BOp<KPL>& b) {
+    const uint16_t* h = hi(row) + g * KPL;
+#pragma unroll
+    for (int c = 0; c < KPL / 8; ++c) {
+      b.hi[c] = *reinterpret_cast<const bf16x8*>(h + 8 * c);
+      b.lo[c] = *reinterpret_cast<const bf16x8*>(h + CHI + 8 * c);
+    }
+  }
+  // the exponent is taken from the hi parts; any power of two is exact, and
+  // every wave derives the same one from the same bits
+  template <int KPL>
+  __device__ __forceinline__ static int row_exp(const DBF16::BOp<KPL>& b) {
+    uint32_t mx = 0;
+#pragma unroll
+    for (int c = 0; c < KPL / 8; ++c) {
+      const u16x8 u = __builtin_bit_cast(u16x8, b.hi[c]);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) mx = max(mx, (uint32_t)(u[i] & 0x7fffu));
+    }
+    const float f = group_max(__uint_as_float(mx << 16));
+    return (f > 0.f) ? __builtin_amdgcn_frexp_expf(f) : 0;
+  }
+  template <int KPL>
+  __device__ __forceinline__ static void load_f32(const float* row, int g, float (&v)[KPL]) {
+    const uint16_t* h = hi(row) + g * KPL;
+#pragma unroll
+    for (int c = 0; c < KPL / 8; ++c) {
+      const u16x8 a = *reinterpret_cast<const u16x8*>(h + 8 * c);
+      const u16x8 l = *reinterpret_cast<const u16x8*>(h + CHI + 8 * c);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) v[8 * c + i] = bf16_to_f32(a[i]) + bf16_to_f32(l[i]);
+    }
+  }
+  __device__ __forceinline__ static void split(float x, uint16_t& h, uint16_t& l) {
+    const __bf16 xh = (__bf16)x;  // round to nearest even
+    const __bf16 xl = (__bf16)(x - (float)xh);
+    h = __builtin_bit_cast(uint16_t, xh);
+    l = __builtin_bit_cast(uint16_t, xl);
+  }
+  __device__ __forceinline__ static void store4(float* row, int col, f4 v) {
+    uint16_t h[4], l[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) split(v[i], h[i], l[i]);
+    uint16_t* p = hi(row) + col;
+    *reinterpret_cast<uint2*>(p) = make_uint2(h[0] | ((uint32_t)h[1] << 16), h[2] | ((uint32_t)h[3] << 16));
+    *reinterpret_cast<uint2*>(p + CHI) = make_uint2(l[0] | ((uint32_t)l[1] << 16), l[2] | ((uint32_t)l[3] << 16));
+  }
+  __device__ __forceinline__ static void store1(float* row, int col, float x) {
+    uint16_t h, l;
+    split(x, h, l);
+    hi(row)[col] = h;
+    hi(row)[CHI + col] = l;
+  }
+  __device__ __forceinline__ static float get(const float* row, int i) {
+    return bf16_to_f32(hi(row)[i]) + bf16_to_f32(hi(row)[CHI + i]);
+  }
+  __device__ __forceinline__ static void set_unit(float* row) { hi(row)[0] = 0x3F80u; }
+};
+
 // ---------------------------------------------------------------- Philox4x64-10
 // Salmon et al., SC'11: 10 rounds of two 64x64->128 multiplies per block,
 // key bumped by the Weyl constants between rounds.

@@ -78,7 +78,8 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int bx, int ty) {
   for (int i = tid_w; i < 2 * nslot; i += NT_W) exc[i] = 0;
   for (int i = tid_w; i < a.nw; i += NT_W) spw[i] = a.spins[(size_t)w * a.nw + i];
   __syncthreads();
-  if (tid_w == 0) cur[0] = 1.f;  // boundary vector e_0 in the base slot
+  using A = Act<D, CHI>;
+  if (tid_w == 0) A::set_unit(cur);  // boundary vector e_0 in the base slot
   __syncthreads();
 
   const int term = ty / a.ng, grp = ty % a.ng;
@@ -87,55 +88,106 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int bx, int ty) {
   const int2 gs = a.gsteps[grp];
   const int4* sched = a.sched + gs.x;
 
-  // work items = (schedule step, output tile of this wave); the core
-  // fragments of item i+1 are loaded while item i computes
-  struct Frags { E m[KPL]; E o[KPL]; };
-  const int n_items = gs.y * MT;
+  // Work items = (schedule step, group of MTI output tiles of this wave).
+  // When the fragments of all MT tiles fit in registers (MTI = MT) a row
+  // tile's activations are read once per step and used for every tile;
+  // otherwise they are read again per tile.  The core fragments of item i+1
+  // are loaded while item i computes.  Rows are stored in the matrix-op
+  // form (Act), and renormalisation scales the products, not the inputs.
+  constexpr int FRAG_DW = MT * 2 * KPL * (int)sizeof(E) / 4;
+  constexpr int MTI = FRAG_DW <= 128 ? MT : 1;
+  constexpr int NIS = MT / MTI;  // items per step
+  constexpr bool ODD_MFMA = sizeof(E) == 2;
+  struct Frags { E m[MTI][KPL]; E o[MTI][KPL]; };
+  const int n_items = gs.y * NIS;
   auto load = [&](Frags& F, int item) {
-    const int s = item / MT, mt = item % MT;
+    const int s = item / NIS, ig = item % NIS;
     const int4 st = sched[s];
     const int bit = spin_bit(spw, st.y);
-    const size_t tile = ((size_t)(wv * MT + mt) * 64 + lane) * KPL;
-    load_frag<KPL>(F.m, cores + ((size_t)st.x * 2 + bit) * (CHI * CHI) + tile);
-    load_frag<KPL>(F.o, cores + ((size_t)st.x * 2 + (bit ^ 1)) * (CHI * CHI) + tile);
+#pragma unroll
+    for (int q = 0; q < MTI; ++q) {
+      const size_t tile = ((size_t)(wv * MT + ig * MTI + q) * 64 + lane) * KPL;
+      load_frag<KPL>(F.m[q], cores + ((size_t)st.x * 2 + bit) * (CHI * CHI) + tile);
+      load_frag<KPL>(F.o[q], cores + ((size_t)st.x * 2 + (bit ^ 1)) * (CHI * CHI) + tile);
+    }
   };
   auto compute = [&](const Frags& F, int item) {
-    const int s = item / MT, mt = item % MT;
+    const int s = item / NIS, ig = item % NIS;
     const int4 st = sched[s];
     const int k = st.x, nact = st.z, odd = st.w;
-    const int t = wv * MT + mt;
     const int cexp = cexp_p ? cexp_p[k] : 0;
     const int ntile = (nact + 15) >> 4;
     // rows are renormalised every kRenormEvery steps: between two, a row
     // grows by at most a factor chi per step (core entries below 1)
     const bool rn = (s % kRenormEvery) == 0;
+    // With BF16 cores the odd row rides on the matrix cores too: when the
+    // row tile holding its input comes by, the other slice is applied to the
+    // same B operand and the column of that row kept (stored after the loop,
+    // since the main loop may also write its output slot).  FP32 matrix ops
+    // are 8x slower, so there it stays a vector-ALU dot product.
+    const int oin = odd >= 0 ? (odd & 0xffff) : -1, oout = odd >> 16;
+    f4 oacc[MTI];
+    int oe = 0;
     for (int r = 0; r < ntile; ++r) {
       const int row = 16 * r + m;
-      float v[KPL];
-      lds_read<KPL>(v, cur + row * RS + g * KPL);
-      const int e = rn ? renorm_row<KPL>(v) : 0;
-      if (mt == 0 && wv == 0 && g == 0) exn[row] = exc[row] + e + cexp;
       typename D::template BOp<KPL> bo;
-      D::template prep<KPL>(v, bo);
-      f4 acc = {0.f, 0.f, 0.f, 0.f};
-      acc = D::template mma<KPL>(F.m, bo, acc);
-      *reinterpret_cast<float4*>(nxt + row * RS + 16 * t + 4 * g) =
-          make_float4(acc[0], acc[1], acc[2], acc[3]);
-    }
-    if (odd >= 0) {  // odd row on the vector ALUs: out[16t+m] = sum_k A[1-s][k][16t+m] in[k]
-      const int oin = odd & 0xffff, oout = odd >> 16;
-      float v[KPL];
-      lds_read<KPL>(v, cur + oin * RS + g * KPL);
-      const int e = rn ? renorm_row<KPL>(v) : 0;
-      float p = 0.f;
+      A::template load_b<KPL>(cur + row * RS, g, bo);
+      const int e = rn ? A::template row_exp<KPL>(bo) : 0;
+      if (ig == 0 && wv == 0 && g == 0) exn[row] = exc[row] + e + cexp;
 #pragma unroll
-      for (int c = 0; c < KPL; ++c) p = fmaf(D::to_f32(F.o[c]), v[c], p);
-      p += __shfl_xor(p, 16);
-      p += __shfl_xor(p, 32);
-      if (g == 0) nxt[oout * RS + 16 * t + m] = p;
-      if (mt == 0 && wv == 0 && lane == 0) exn[oout] = exc[oin] + e + cexp;
+      for (int q = 0; q < MTI; ++q) {
+        f4 acc = {0.f, 0.f, 0.f, 0.f};
+        acc = D::template mma<KPL>(F.m[q], bo, acc);
+        if (rn) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) acc[i] = __builtin_amdgcn_ldexpf(acc[i], -e);
+        }
+        A::store4(nxt + row * RS, 16 * (wv * MT + ig * MTI + q) + 4 * g, acc);
+      }
+      if (ODD_MFMA && r == (oin >> 4)) {
+        oe = e;
+#pragma unroll
+        for (int q = 0; q < MTI; ++q) {
+          f4 acc = {0.f, 0.f, 0.f, 0.f};
+          acc = D::template mma<KPL>(F.o[q], bo, acc);
+          if (rn) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) acc[i] = __builtin_amdgcn_ldexpf(acc[i], -e);
+          }
+          oacc[q] = acc;
+        }
+      }
     }
-    if (mt == MT - 1) {
+    if (ODD_MFMA && oin >= 0) {  // lanes of column oin % 16 hold 4 output features each
+      if (m == (oin & 15)) {
+#pragma unroll
+        for (int q = 0; q < MTI; ++q) A::store4(nxt + oout * RS, 16 * (wv * MT + ig * MTI + q) + 4 * g, oacc[q]);
+      }
+      if (ig == 0 && wv == 0 && lane == (oin & 15)) exn[oout] = exc[oin] + oe + cexp;
+    }
+    if (!ODD_MFMA && oin >= 0) {  // FP32: the odd row as a vector-ALU dot product per output
+      float v[KPL];
+      A::template load_f32<KPL>(cur + oin * RS, g, v);
+      int e = 0;
+      if (rn) {
+        float mx = 0.f;
+#pragma unroll
+        for (int c = 0; c < KPL; ++c) mx = fmaxf(mx, fabsf(v[c]));
+        mx = group_max(mx);
+        e = (mx > 0.f) ? __builtin_amdgcn_frexp_expf(mx) : 0;
+      }
+#pragma unroll
+      for (int q = 0; q < MTI; ++q) {
+        float p = 0.f;
+#pragma unroll
+        for (int c = 0; c < KPL; ++c) p = fmaf(D::to_f32(F.o[q][c]), v[c], p);
+        p += __shfl_xor(p, 16);
+        p += __shfl_xor(p, 32);
+        if (g == 0) A::store1(nxt + oout * RS, 16 * (wv * MT + ig * MTI + q) + m, __builtin_amdgcn_ldexpf(p, -e));
+      }
+      if (ig == 0 && wv == 0 && lane == 0) exn[oout] = exc[oin] + e + cexp;
+    }
+    if (ig == NIS - 1) {
       lds_barrier();
       float* tp = cur; cur = nxt; nxt = tp;
       int* te = exc; exc = exn; exn = te;
@@ -158,7 +210,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int bx, int ty) {
 
   if (w_raw < a.W) {
     float* ov = a.out_vec + (((size_t)ty * a.W + w) * nslot) * CHI;
-    for (int i = tid_w; i < nslot * CHI; i += NT_W) ov[i] = cur[(i / CHI) * RS + (i % CHI)];
+    for (int i = tid_w; i < nslot * CHI; i += NT_W) ov[i] = A::get(cur + (i / CHI) * RS, i % CHI);
     int32_t* oe = a.out_exp + ((size_t)ty * a.W + w) * nslot;
     for (int i = tid_w; i < nslot; i += NT_W) oe[i] = exc[i];
   }
