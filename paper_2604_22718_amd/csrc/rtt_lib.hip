@@ -38,6 +38,7 @@ rtt_status fail(rtt_status st, const char* fmt, ...) {
   } while (0)
 
 constexpr size_t kLdsLimit = 160 * 1024;
+constexpr int kPassOccupancy = 2;  // pass blocks per CU worth trading extra row groups for
 
 // ------------------------------------------------------------------ quantisation
 float to_f32(double x) { return (float)x; }
@@ -320,15 +321,25 @@ rtt_status finish_create(rtt_s* h) {
   const int LW = (h->L + 63) / 64;
   h->rmask.assign((size_t)h->N * LW, 0ull);
   for (int k = 0; k < h->L; ++k) h->rmask[(size_t)h->pi[k] * LW + k / 64] |= 1ull << (k % 64);
-  // schedules: choose the cut bond with the least matrix-core work that fits on chip
-  // the fewest row groups whose rows fit on chip, then the cheapest cut
+  // Schedules: over row-group counts and cut bonds whose rows fit on chip,
+  // minimise matrix-core tiles divided by the pass blocks resident per CU
+  // (counted up to kPassOccupancy: one block per CU leaves every latency
+  // of the step exposed; wide bonds run one wave per SIMD regardless).
   Sched best;
   bool have = false;
-  for (int ng = 1; ng <= 64 && !have; ++ng) {
+  double best_score = 0.0;
+  int first_ng = 0;
+  const int occ_cap = h->chi >= 256 ? 1 : kPassOccupancy;
+  for (int ng = 1; ng <= 64; ++ng) {
+    if (first_ng && ng > first_ng + 3) break;
     for (int c = 0; c <= h->L; ++c) {
       Sched s = build_sched(h->pi, h->N, h->L, c, ng);
-      if (pass_lds_bytes(h->chi, s.nslot, h->nw) > kLdsLimit) continue;
-      if (!have || s.cost < best.cost) { best = s; have = true; }
+      const size_t lds = pass_lds_bytes(h->chi, s.nslot, h->nw);
+      if (lds > kLdsLimit) continue;
+      if (!first_ng) first_ng = ng;
+      const int occ = std::min<int>(occ_cap, (int)(kLdsLimit / lds));
+      const double score = (double)s.cost / occ;
+      if (!have || score < best_score) { best = s; best_score = score; have = true; }
     }
   }
   if (!have) return fail(RTT_E_UNSUPPORTED, "rtt_create: flip-ratio rows of one walker exceed on-chip memory");
