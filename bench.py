@@ -72,6 +72,25 @@ def traffic_from_profile(kernel, workload):
     return d.get("bytes_per_launch")
 
 
+def eloc_error(workload, dtype, e_gpu):
+    """Relative error of GPU local energies of the seeded initial walkers
+    against FP64 values stored by tests/golden/make_eloc_refs.py (computed by
+    the oracle on the same quantised cores, and on the unquantised cores)."""
+    p = os.path.join(ROOT, "tests", "golden", "eloc_fp64_refs.json")
+    if not os.path.exists(p):
+        return None
+    for c in json.load(open(p))["cases"]:
+        if c["workload"] == workload and c["dtype"] == dtype:
+            idx = np.array(c["walkers"])
+            got = np.asarray(e_gpu)[idx]
+            q, u = np.array(c["eloc_quantised_cores"]), np.array(c["eloc_fp64_cores"])
+            return {"eloc_max_rel_vs_fp64_same_cores": float(np.max(np.abs(got - q) / np.abs(q))),
+                    "eloc_median_rel_vs_fp64_same_cores": float(np.median(np.abs(got - q) / np.abs(q))),
+                    "eloc_max_rel_vs_fp64_unquantised_cores": float(np.max(np.abs(got - u) / np.abs(u))),
+                    "sample_walkers": idx.tolist(), "reference": "tests/golden/eloc_fp64_refs.json"}
+    return None
+
+
 def cpu_baseline(w, n_walkers, n_steps):
     """The FP64 oracle on the host, single-threaded BLAS: the same step on a
     sample of the workload's walkers."""
@@ -100,7 +119,6 @@ def run(dtype, steps, warmup, with_cpu):
 
     from paper_2604_22718_amd import rtt as R
     from paper_2604_22718_amd import workloads as wl
-    from oracle import rtt as orc, stats, tfim
 
     w = wl.MEDIUM_8x8
     pi, bond, cores = w.pi(), w.bond(), w.cores()
@@ -111,18 +129,7 @@ def run(dtype, steps, warmup, with_cpu):
     W, N, L, chi = w.W, w.N, w.L, w.chi
 
     # energy error vs FP64 on the seeded configurations (sample of walkers)
-    idx = np.array([0, 1, 2, 3, 1000, 2000, 3000, 4095])
-    e_gpu = psi.local_energy(spins, ham).cpu().numpy()[idx]
-    from oracle import quant
-    qc = quant.quantise_cores(cores, dtype)
-    e_ref = orc.local_energy(qc, pi, bits[idx], tfim.bonds(w.Lx, w.Ly), w.J, w.h)
-    e_ref_unq = orc.local_energy(cores, pi, bits[idx], tfim.bonds(w.Lx, w.Ly), w.J, w.h)
-    err = {
-        "eloc_max_rel_vs_fp64_same_cores": float(np.max(np.abs(e_gpu - e_ref) / np.abs(e_ref))),
-        "eloc_median_rel_vs_fp64_same_cores": float(np.median(np.abs(e_gpu - e_ref) / np.abs(e_ref))),
-        "eloc_max_rel_vs_fp64_unquantised_cores": float(np.max(np.abs(e_gpu - e_ref_unq) / np.abs(e_ref_unq))),
-        "sample_walkers": idx.tolist(),
-    }
+    err = eloc_error(w.name, dtype, psi.local_energy(spins, ham).cpu().numpy())
 
     eloc = torch.empty(W, dtype=torch.float64, device="cuda")
     red = torch.empty(3, dtype=torch.float64, device="cuda")
@@ -256,13 +263,12 @@ def run_learned(n_meas=30, train_steps=150, learned_per_sweep=4):
     (network trained online on the chain, then frozen), same GPU."""
     import torch
 
-    from oracle import net as onet_init  # seeded initial weights only
     from paper_2604_22718_amd import rtt as R
     from paper_2604_22718_amd import workloads as wl
     w = wl.LARGE_10x10
     psi = R.RTT.create(w.N, w.pi(), w.cores(), "bf16")
     ham = R.TFIM(w.Lx, w.Ly, w.J, w.h)
-    net = R.Net(w.Lx, w.Ly, onet_init.init_params(4004))
+    net = R.Net(w.Lx, w.Ly, wl.net_init_params(4004))
     out = {"workload": w.name, "walkers": w.W}
     spins0 = R.spins_to_device(wl.pack_spins(w.spins()))
     # burn-in and online training
@@ -329,6 +335,63 @@ def stats_tau(x):
     return max(tau, 1.0)
 
 
+def run_wide(name, n_eval=3, with_sweep=True):
+    """Local energies (and one sweep) of a wide-bond workload: 10x10, R=3,
+    chi=128, 8192 walkers, BF16 (or 16x16, R=2, chi=256, 16384 walkers,
+    4-term FP8 combination).  Reports algorithmic TFLOP/s against the BF16
+    MFMA peak; with hi+lo BF16 activations the matrix cores execute twice
+    the algorithmic flops, which mfma_frac_hilo counts."""
+    import torch
+
+    from paper_2604_22718_amd import rtt as R
+    from paper_2604_22718_amd import workloads as wl
+    w = wl.WORKLOADS[name]
+    dtype = "bf16" if w.chi <= 128 else "fp8"
+    pi = w.pi()
+    if w.n_terms > 1:
+        terms = [R.RTT.create(w.N, pi, w.cores(t), dtype) for t in range(w.n_terms)]
+        psi = R.RTT.lincomb(terms, w.coeffs())
+        del terms
+    else:
+        psi = R.RTT.create(w.N, pi, w.cores(), dtype)
+    info = R.rtt_info(psi.handle)
+    ham = R.TFIM(w.Lx, w.Ly, w.J, w.h)
+    bits = w.spins()
+    spins = R.spins_to_device(wl.pack_spins(bits))
+    eloc = torch.empty(w.W, dtype=torch.float64, device="cuda")
+    R.rtt_evaluate(psi.handle, ham.handle, spins, eloc=eloc)
+    err = eloc_error(w.name, dtype, eloc.cpu().numpy())
+    torch.cuda.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    e[0].record()
+    for _ in range(n_eval):
+        R.rtt_evaluate(psi.handle, ham.handle, spins, eloc=eloc)
+    e[1].record()
+    if with_sweep:
+        psi.sweep(spins, seed=w.chain_seed, sweep0=0, n_sweeps=1)
+    e[2].record()
+    torch.cuda.synchronize()
+    le_ms = e[0].elapsed_time(e[1]) / n_eval
+    T = w.n_terms
+    fwd, bwd = schedule_rowsteps(pi, w.N, w.L, info["cut"])
+    le_flops = w.W * T * (fwd + bwd) * 2.0 * w.chi * w.chi
+    out = {"workload": w.name, "dtype": dtype, "walkers": w.W, "row_groups": info["groups"],
+           "le_evals_per_s": w.W / (le_ms * 1e-3), "le_ms": le_ms,
+           "le_algorithmic_tflops": le_flops / (le_ms * 1e-3) / 1e12,
+           "le_frac_bf16_peak": le_flops / (le_ms * 1e-3) / PEAK["bf16"],
+           "le_mfma_frac_hilo": 2 * le_flops / (le_ms * 1e-3) / PEAK["bf16"]}
+    if with_sweep:
+        sw_ms = e[1].elapsed_time(e[2])
+        sw_flops = w.W * T * sweep_rowsteps(pi, w.N, w.L) * 2.0 * w.chi * w.chi
+        out.update({"sweep_ms": sw_ms, "sweep_algorithmic_tflops": sw_flops / (sw_ms * 1e-3) / 1e12,
+                    "sweep_frac_bf16_peak": sw_flops / (sw_ms * 1e-3) / PEAK["bf16"]})
+    out["energy_error"] = err
+    psi.close()
+    ham.close()
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -339,6 +402,8 @@ def main():
     ap.add_argument("--also", default="bf16", help="second precision reported alongside ('' for none)")
     ap.add_argument("--batched", type=int, default=0, help="also time the 256-RTT batch for this many steps")
     ap.add_argument("--learned", action="store_true", help="also compare learned-proposal ESS/s (10x10, chi=128)")
+    ap.add_argument("--no-wide", action="store_true", help="skip the 10x10 chi=128 BF16 wide-bond line")
+    ap.add_argument("--huge", action="store_true", help="also time the 16x16 chi=256 4-term FP8 workload (slow)")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only copy this many MiB device-to-device 3 times (counter calibration) and exit")
     a = ap.parse_args()
@@ -363,6 +428,10 @@ def main():
         other = run(a.also, a.steps, a.warmup, False)
         res["also"] = {k: other[k] for k in ("dtype", "value", "ms_per_step", "effective_samples_per_s",
                                              "energy_error", "kernels", "roofline")}
+    if not a.no_wide:
+        res["wide_bond"] = [run_wide("tfim10x10_R3_chi128_W8192")]
+        if a.huge:
+            res["wide_bond"].append(run_wide("tfim16x16_R2_chi256_W16384_T4", n_eval=1))
     if a.batched:
         res["batched"] = run_batched(a.batched)
     if a.learned:

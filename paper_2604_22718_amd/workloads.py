@@ -111,6 +111,30 @@ def unpack_spins(words: np.ndarray, N: int) -> np.ndarray:
 
 
 # --------------------------------------------------------------------------
+# learned-proposal network: seeded initial weights
+# --------------------------------------------------------------------------
+# Parameter blocks in storage order: three 3x3 convolutions with 32 channels
+# (weights [out][in][3][3], then biases) and a 1x1 head with 9 outputs per
+# site.  Only the shapes are needed here, to draw the initial weights.
+NET_BLOCKS = [(32, 1, 3, 3), (32,), (32, 32, 3, 3), (32,), (32, 32, 3, 3), (32,), (9, 32), (9,)]
+
+
+def net_init_params(seed: int) -> np.ndarray:
+    """Flat initial network weights: uniform in +-sqrt(3 / fan_in) for the
+    weight blocks (fan_in = product of all but the first dimension), zero
+    biases, drawn from Philox(seed) block by block."""
+    g = generator(seed)
+    parts = []
+    for shp in NET_BLOCKS:
+        if len(shp) > 1:
+            lim = math.sqrt(3.0 / int(np.prod(shp[1:])))
+            parts.append(g.uniform(-lim, lim, size=shp).ravel())
+        else:
+            parts.append(np.zeros(shp))
+    return np.concatenate(parts)
+
+
+# --------------------------------------------------------------------------
 # workload configurations (synthetic stand-ins for the paper's 2D TFIM runs)
 # --------------------------------------------------------------------------
 @dataclass

@@ -104,3 +104,11 @@ def test_adam_closed_form_first_step():
     q, m, v = net.adam(p, np.zeros(2), np.zeros(2), g, 1, lr=0.1)
     # first bias-corrected step moves each coordinate by lr * sign(g)
     assert np.allclose(q, p - 0.1 * np.sign(g), atol=1e-7)
+
+
+def test_shared_initial_weights_match_the_oracle_draw():
+    """The benchmark draws its initial network weights from the shared input
+    module; they are the same numbers the oracle's initialiser draws."""
+    from paper_2604_22718_amd import workloads as wl
+    for seed in (3, 33, 4004):
+        assert np.array_equal(wl.net_init_params(seed), net.init_params(seed))
