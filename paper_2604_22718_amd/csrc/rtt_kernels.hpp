@@ -363,26 +363,27 @@ struct ChainArgs {
   int mode;                  // 0: amplitudes only, 1: sweeps
 };
 
-// Layout of the 16 walkers' state in LDS (offsets in bytes).  Per term: the
-// prefix row P, the first-step products U and F, row ping-pong X/Y and
-// column ping-pong CX/CY (7 buffers), all terms advancing together when that
-// fits; otherwise ("sequential") each term keeps only its prefix and the
-// terms share F, X, Y, CX, CY, one term at a time, the prefix being advanced
-// after the decision.
+// Layout of one block's walkers' state in LDS (offsets in bytes), for
+// nb = 16 * cg walkers.  Per term: the prefix row P, the first-step products
+// U and F, row ping-pong X/Y and column ping-pong CX/CY (7 buffers), all
+// terms advancing together when that fits; otherwise ("sequential") each
+// term keeps only its prefix and the terms share F, X, Y, CX, CY, one term
+// at a time, the prefix being advanced after the decision.
 struct ChainLayout {
-  int rows, exps, vals, pm, sp, total;
+  int nb, rows, exps, vals, pm, sp, total;
   bool seq;
-  __host__ __device__ ChainLayout(int chi, int T, int LW, int nw) {
-    const int bufb = 16 * (chi + 4) * 4;
-    const int tail = 4 * T * 16 * 4 + T * 16 * 12 + 8 + 16 * LW * 8 + 16 * nw * 8;
+  __host__ __device__ ChainLayout(int chi, int T, int LW, int nw, int cg) {
+    nb = 16 * cg;
+    const int bufb = nb * (chi + 4) * 4;
+    const int tail = 4 * T * nb * 4 + T * nb * 12 + 8 + nb * LW * 8 + nb * nw * 8;
     seq = (T * 7 * bufb + tail) > 160 * 1024;
     rows = 0;                                      // float vectors
-    exps = rows + (seq ? T + 5 : 7 * T) * bufb;    // int [4][T][16]: prefix, first step, row, column
-    vals = exps + 4 * T * 16 * 4;                  // double [T][16] end values, int [T][16] exponents
-    pm = vals + T * 16 * 12;
+    exps = rows + (seq ? T + 5 : 7 * T) * bufb;    // int [4][T][nb]: prefix, first step, row, column
+    vals = exps + 4 * T * nb * 4;                  // double [T][nb] end values, int [T][nb] exponents
+    pm = vals + T * nb * 12;
     pm = (pm + 7) & ~7;
-    sp = pm + 16 * LW * 8;                         // uint64 [16][LW] position bits; [16][nw] spins
-    total = sp + 16 * nw * 8;
+    sp = pm + nb * LW * 8;                         // uint64 [nb][LW] position bits; [nb][nw] spins
+    total = sp + nb * nw * 8;
   }
 };
 
@@ -397,19 +398,22 @@ struct ChainGeo {
   static constexpr int PF = 2;                                 // fragment sets in flight + 1
 };
 
-// Block of 2 * SW waves for 16 walkers (the 16 matrix-core columns).  Every
-// amplitude is contracted from both ends at once: the first SW waves carry
-// row vectors from the left (forward fragment layout), the other SW waves
-// column vectors from the right boundary (backward layout); the two meet
-// half way and are joined by an FP64 dot product.  The number of dependent
-// steps per amplitude is halved and each SIMD runs two independent chains.
-template <class D, int CHI>
+// Block of 2 * SW waves for 16 * CG walkers: CG groups of 16 matrix-core
+// columns that share every core fragment a wave loads (more walkers per
+// fragment when there are enough walkers to fill the GPU).  Every amplitude
+// is contracted from both ends at once: the first SW waves carry row vectors
+// from the left (forward fragment layout), the other SW waves column vectors
+// from the right boundary (backward layout); the two meet half way and are
+// joined by an FP64 dot product.  The number of dependent steps per
+// amplitude is halved and each SIMD runs two independent chains.
+template <class D, int CHI, int CG>
 __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t sweep0) {
   using E = typename D::elem;
   using G = Geo<CHI>;
   constexpr int RS = G::RS, KPL = G::KPL;
   constexpr int MT = ChainGeo<CHI>::MT, SW = ChainGeo<CHI>::SW, PF = ChainGeo<CHI>::PF;
-  constexpr int BUF = 16 * RS;
+  constexpr int NB = 16 * CG;
+  constexpr int BUF = NB * RS;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int side = wave / SW;    // 0: rows from the left, 1: columns from the right
   const int wv = wave % SW;      // wave within its side
@@ -417,14 +421,14 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
   const int nthr = blockDim.x, nwave = nthr >> 6;
   const int T = a.T, L = a.L, LW = a.LW, nw = a.nw;
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  const ChainLayout lay(CHI, T, LW, nw);
+  const ChainLayout lay(CHI, T, LW, nw, CG);
   float* rows = reinterpret_cast<float*>(lds_raw + lay.rows);
-  int* Ep = reinterpret_cast<int*>(lds_raw + lay.exps);   // [T][16] prefix
-  int* Ef = Ep + T * 16;                                   // [T][16] after the first step
-  int* Er = Ef + T * 16;                                   // [T][16] running row
-  int* Ec = Er + T * 16;                                   // [T][16] running column
-  double* fval = reinterpret_cast<double*>(lds_raw + lay.vals);  // [T][16] amplitude mantissas
-  int* fexp = reinterpret_cast<int*>(fval + T * 16);             // [T][16] their exponents
+  int* Ep = reinterpret_cast<int*>(lds_raw + lay.exps);   // [T][NB] prefix
+  int* Ef = Ep + T * NB;                                   // [T][NB] after the first step
+  int* Er = Ef + T * NB;                                   // [T][NB] running row
+  int* Ec = Er + T * NB;                                   // [T][NB] running column
+  double* fval = reinterpret_cast<double*>(lds_raw + lay.vals);  // [T][NB] amplitude mantissas
+  int* fexp = reinterpret_cast<int*>(fval + T * NB);             // [T][NB] their exponents
   uint64_t* pm = reinterpret_cast<uint64_t*>(lds_raw + lay.pm);
   uint64_t* sp = reinterpret_cast<uint64_t*>(lds_raw + lay.sp);
   const bool seq = lay.seq;
@@ -436,16 +440,18 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
     return b == P ? rows + t * BUF : rows + (T + b - F) * BUF;  // U is not used then
   };
 
-  const int w0 = bx * 16;
-  const bool live = (w0 + m) < a.W;
+  const int w0 = bx * NB;
+  bool live[CG];
+#pragma unroll
+  for (int cg = 0; cg < CG; ++cg) live[cg] = (w0 + 16 * cg + m) < a.W;
   for (int i = threadIdx.x; i < nbuf * BUF; i += nthr) rows[i] = 0.f;
-  for (int i = threadIdx.x; i < 4 * T * 16; i += nthr) Ep[i] = 0;
-  for (int i = threadIdx.x; i < 16 * nw; i += nthr) {
+  for (int i = threadIdx.x; i < 4 * T * NB; i += nthr) Ep[i] = 0;
+  for (int i = threadIdx.x; i < NB * nw; i += nthr) {
     const int n = i / nw, wd = i % nw;
     sp[i] = (w0 + n < a.W) ? a.spins[(size_t)(w0 + n) * nw + wd] : 0ull;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < 16 * LW; i += nthr) {
+  for (int i = threadIdx.x; i < NB * LW; i += nthr) {
     const int n = i / LW, wd = i % LW;
     uint64_t word = 0;
     for (int b = 0; b < 64 && 64 * wd + b < L; ++b) {
@@ -458,7 +464,7 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
   const E* cores = static_cast<const E*>(side == 0 ? a.cores : a.cores_bwd);
   const size_t lane_off = (size_t)lane * KPL;
   struct Frags { E f0[KPL]; E f1[KPL]; };
-  typename D::template BOp<KPL> bo;
+  typename D::template BOp<KPL> bo[CG];
 
   // Results of the last segment: rb holds the rows, cb the columns (-1: the
   // right boundary vector itself).  Every wave knows both.
@@ -469,11 +475,11 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
   // column vectors from the right boundary through positions L-1 down to kc.
   // Work items of a wave are (step, term, output tile) in that order; the
   // two core fragments of the next item are loaded while the current one
-  // computes.  Each joint step ends with one block barrier (the side with
-  // fewer steps still takes part).  With `split` the first row step stores
-  // the walker's own slice product in F and the other slice's in U.  Vectors
-  // are renormalised every kRenormEvery steps; the exponent sums live in Er
-  // and Ec.
+  // computes, and each serves all CG column groups.  Each joint step ends
+  // with one block barrier (the side with fewer steps still takes part).
+  // With `split` the first row step stores the walker's own slice product in
+  // F and the other slice's in U.  Vectors are renormalised every
+  // kRenormEvery steps; the exponent sums live in Er and Ec.
   auto segment = [&](int k0, int k1, int kc, int jflip, bool split, int t0, int tn) {
     const int nr = k1 > k0 ? k1 - k0 : 0, nc = L - kc;
     if (nr == 0) rb = P;
@@ -487,8 +493,11 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
       int cur = side == 0 ? P : -1;
       int out = side == 0 ? (split ? F : X) : CX;
       const int tend = t0 + tn;
-      int i = 0, t = t0, mt = 0, bit = 0;
-      uint64_t word = 0;
+      int i = 0, t = t0, mt = 0;
+      int bit[CG];
+      uint64_t word[CG];
+#pragma unroll
+      for (int cg = 0; cg < CG; ++cg) { bit[cg] = 0; word[cg] = 0; }
       auto pos_of = [&](int ii) { return side == 0 ? k0 + ii : L - 1 - ii; };
       auto load = [&](Frags& Fr, int ii, int tt, int mm) {
         const int kk = pos_of(ii < n ? ii : n - 1);
@@ -500,45 +509,61 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
       auto step = [&](const Frags& Fr) {
         const int k = pos_of(i);
         if (t == t0 && mt == 0) {
-          if (i == 0 || (k & 63) == (side == 0 ? 0 : 63))
-            word = pm[m * LW + (k >> 6)] ^ (rmj ? rmj[k >> 6] : 0ull);
-          bit = (int)((word >> (k & 63)) & 1ull);
+          const bool fresh = i == 0 || (k & 63) == (side == 0 ? 0 : 63);
+#pragma unroll
+          for (int cg = 0; cg < CG; ++cg) {
+            if (fresh) word[cg] = pm[(16 * cg + m) * LW + (k >> 6)] ^ (rmj ? rmj[k >> 6] : 0ull);
+            bit[cg] = (int)((word[cg] >> (k & 63)) & 1ull);
+          }
         }
         if (mt == 0) {
-          float v[KPL];
-          if (cur < 0) {  // the right boundary vector e_0
 #pragma unroll
-            for (int e = 0; e < KPL; ++e) v[e] = (g == 0 && e == 0) ? 1.f : 0.f;
-            if (wv == 0 && g == 0) Ec[t * 16 + m] = 0;
-          } else {
-            lds_read<KPL>(v, buf(t, cur) + m * RS + g * KPL);
-            if (i % kRenormEvery == 0) {
-              const int e = renorm_row<KPL>(v);
-              if (wv == 0 && g == 0) {
-                if (side == 1) {
-                  Ec[t * 16 + m] += e;
-                } else if (split && i == 0) {
-                  const int ne = Ep[t * 16 + m] + e;
-                  Ef[t * 16 + m] = ne;
-                  Er[t * 16 + m] = ne;
-                } else {
-                  Er[t * 16 + m] = (i == 0 ? Ep[t * 16 + m] : Er[t * 16 + m]) + e;
+          for (int cg = 0; cg < CG; ++cg) {
+            const int wn = 16 * cg + m;
+            float v[KPL];
+            if (cur < 0) {  // the right boundary vector e_0
+#pragma unroll
+              for (int e = 0; e < KPL; ++e) v[e] = (g == 0 && e == 0) ? 1.f : 0.f;
+              if (wv == 0 && g == 0) Ec[t * NB + wn] = 0;
+            } else {
+              lds_read<KPL>(v, buf(t, cur) + wn * RS + g * KPL);
+              if (i % kRenormEvery == 0) {
+                const int e = renorm_row<KPL>(v);
+                if (wv == 0 && g == 0) {
+                  if (side == 1) {
+                    Ec[t * NB + wn] += e;
+                  } else if (split && i == 0) {
+                    const int ne = Ep[t * NB + wn] + e;
+                    Ef[t * NB + wn] = ne;
+                    Er[t * NB + wn] = ne;
+                  } else {
+                    Er[t * NB + wn] = (i == 0 ? Ep[t * NB + wn] : Er[t * NB + wn]) + e;
+                  }
                 }
               }
             }
+            D::template prep<KPL>(v, bo[cg]);
           }
-          D::template prep<KPL>(v, bo);
         }
-        f4 c0 = {0.f, 0.f, 0.f, 0.f}, c1 = {0.f, 0.f, 0.f, 0.f};
-        D::template mma2<KPL>(Fr.f0, Fr.f1, bo, c0, c1);
         const int tt = wv * MT + mt;
-        const f4 sel = bit ? c1 : c0;
-        *reinterpret_cast<float4*>(buf(t, out) + m * RS + 16 * tt + 4 * g) =
-            make_float4(sel[0], sel[1], sel[2], sel[3]);
-        if (split && side == 0 && i == 0) {
-          const f4 oth = bit ? c0 : c1;
-          *reinterpret_cast<float4*>(buf(t, U) + m * RS + 16 * tt + 4 * g) =
-              make_float4(oth[0], oth[1], oth[2], oth[3]);
+        f4 c0[CG], c1[CG];
+#pragma unroll
+        for (int cg = 0; cg < CG; ++cg) {
+          c0[cg] = f4{0.f, 0.f, 0.f, 0.f};
+          c1[cg] = f4{0.f, 0.f, 0.f, 0.f};
+          D::template mma2<KPL>(Fr.f0, Fr.f1, bo[cg], c0[cg], c1[cg]);
+        }
+#pragma unroll
+        for (int cg = 0; cg < CG; ++cg) {
+          const int wn = 16 * cg + m;
+          const f4 sel = bit[cg] ? c1[cg] : c0[cg];
+          *reinterpret_cast<float4*>(buf(t, out) + wn * RS + 16 * tt + 4 * g) =
+              make_float4(sel[0], sel[1], sel[2], sel[3]);
+          if (split && side == 0 && i == 0) {
+            const f4 oth = bit[cg] ? c0[cg] : c1[cg];
+            *reinterpret_cast<float4*>(buf(t, U) + wn * RS + 16 * tt + 4 * g) =
+                make_float4(oth[0], oth[1], oth[2], oth[3]);
+          }
         }
         if (mt == MT - 1 && t == tend - 1) {
           lds_barrier();
@@ -579,35 +604,39 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
   // walker (one wave per term, four lanes per walker) and its exponent.
   auto record = [&](int t0, int tn) {
     for (int t = t0 + wave; t < t0 + tn; t += nwave) {
-      const float* r = buf(t, rb) + m * RS + g * KPL;
-      double s = 0.0;
-      if (cb < 0) {
-        s = (g == 0) ? (double)r[0] : 0.0;
-      } else {
-        const float* c = buf(t, cb) + m * RS + g * KPL;
-        for (int e = 0; e < KPL; ++e) s = fma((double)r[e], (double)c[e], s);
-      }
-      s += __shfl_xor(s, 16);
-      s += __shfl_xor(s, 32);
-      if (g == 0) {
-        fval[t * 16 + m] = s;
-        fexp[t * 16 + m] = Er[t * 16 + m] + (cb < 0 ? 0 : Ec[t * 16 + m]) +
-                           a.cesum[(size_t)t * (L + 1) + L];
+#pragma unroll
+      for (int cg = 0; cg < CG; ++cg) {
+        const int wn = 16 * cg + m;
+        const float* r = buf(t, rb) + wn * RS + g * KPL;
+        double s = 0.0;
+        if (cb < 0) {
+          s = (g == 0) ? (double)r[0] : 0.0;
+        } else {
+          const float* c = buf(t, cb) + wn * RS + g * KPL;
+          for (int e = 0; e < KPL; ++e) s = fma((double)r[e], (double)c[e], s);
+        }
+        s += __shfl_xor(s, 16);
+        s += __shfl_xor(s, 32);
+        if (g == 0) {
+          fval[t * NB + wn] = s;
+          fexp[t * NB + wn] = Er[t * NB + wn] + (cb < 0 ? 0 : Ec[t * NB + wn]) +
+                              a.cesum[(size_t)t * (L + 1) + L];
+        }
       }
     }
     __syncthreads();
   };
-  // combined amplitude of this lane's walker from the recorded values:
-  // log|psi| and sign (every lane of every wave computes it)
-  auto amp = [&](double& labs, int& sg) {
+  // combined amplitude of walker slot wn from the recorded values: log|psi|
+  // and sign (every lane of every wave computes it for its walkers)
+  auto amp = [&](int wn, double& labs, int& sg) {
     double ms[kMaxTerms];
     int es[kMaxTerms];
     int emax = INT_MIN;
     for (int t = 0; t < T; ++t) {
       int ed = 0;
-      const double md = frexp(fval[t * 16 + m], &ed);
+      const double md = frexp(fval[t * NB + wn], &ed);
       ms[t] = a.coeffs[t] * md;
-      es[t] = fexp[t * 16 + m] + ed;
+      es[t] = fexp[t * NB + wn] + ed;
       if (ms[t] != 0.0 && es[t] > emax) emax = es[t];
     }
     if (emax == INT_MIN) { labs = -INFINITY; sg = 0; return; }
@@ -622,11 +651,11 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
   };
 
   auto reset_prefix = [&]() {
-    for (int i = threadIdx.x; i < T * 16 * RS; i += nthr) {
-      const int t = i / (16 * RS), r = i % (16 * RS);
+    for (int i = threadIdx.x; i < T * NB * RS; i += nthr) {
+      const int t = i / (NB * RS), r = i % (NB * RS);
       buf(t, P)[r] = (r % RS == 0) ? 1.f : 0.f;
     }
-    for (int i = threadIdx.x; i < T * 16; i += nthr) Ep[i] = 0;
+    for (int i = threadIdx.x; i < T * NB; i += nthr) Ep[i] = 0;
   };
   // the meeting bond of a contraction that starts at position f
   auto meet = [&](int f) { return f + (L - f + 1) / 2; };
@@ -634,9 +663,9 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
   // amplitude of the current configuration (identical in every lane of a walker)
   reset_prefix();
   __syncthreads();
-  double lab;
-  int sgn, stat;
-  uint32_t nacc = 0;
+  double lab[CG];
+  int sgn[CG], stat[CG];
+  uint32_t nacc[CG];
   if (!seq) {
     segment(0, meet(0), meet(0), -1, false, 0, T);
     record(0, T);
@@ -646,8 +675,12 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
       record(t, 1);
     }
   }
-  amp(lab, sgn);
-  stat = (sgn != 0 && isfinite(lab)) ? 0 : -5;
+#pragma unroll
+  for (int cg = 0; cg < CG; ++cg) {
+    amp(16 * cg + m, lab[cg], sgn[cg]);
+    stat[cg] = (sgn[cg] != 0 && isfinite(lab[cg])) ? 0 : -5;
+    nacc[cg] = 0;
+  }
   __syncthreads();
 
   if (a.mode == 1) {
@@ -660,21 +693,23 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
         const int j = a.order[qi];
         const int f = a.first[j];
         if (f < 0) {  // spin read by no position: ratio 1, always accepted
-          if (live && stat == 0) {
-            nacc += 1;
-            if (wave == 0 && g == 0) sp[m * nw + (j >> 6)] ^= (1ull << (j & 63));
-          }
+#pragma unroll
+          for (int cg = 0; cg < CG; ++cg)
+            if (live[cg] && stat[cg] == 0) {
+              nacc[cg] += 1;
+              if (wave == 0 && g == 0) sp[(16 * cg + m) * nw + (j >> 6)] ^= (1ull << (j & 63));
+            }
           __syncthreads();
           continue;
         }
         // bring the prefix of terms [t0, t0+tn) from pos up to position kk
         auto advance_prefix = [&](int kk, int t0, int tn) {
           segment(pos, kk, L, -1, false, t0, tn);
-          for (int i = threadIdx.x; i < tn * 16 * RS; i += nthr) {
-            const int t = t0 + i / (16 * RS), r = i % (16 * RS);
+          for (int i = threadIdx.x; i < tn * NB * RS; i += nthr) {
+            const int t = t0 + i / (NB * RS), r = i % (NB * RS);
             buf(t, P)[r] = buf(t, rb)[r];
           }
-          for (int i = threadIdx.x; i < tn * 16; i += nthr) Ep[t0 * 16 + i] = Er[t0 * 16 + i];
+          for (int i = threadIdx.x; i < tn * NB; i += nthr) Ep[t0 * NB + i] = Er[t0 * NB + i];
           __syncthreads();
         };
         if (pos < f) {
@@ -695,19 +730,23 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
             record(t, 1);
           }
         }
-        int accept = 0;
-        if (live && stat == 0) {
-          double lnew; int snew;
-          amp(lnew, snew);
-          if (isnan(lnew)) {
-            stat = -5;
-          } else if (snew != 0) {
-            const double u = philox_uniform(a.seed, a.rstream, (uint64_t)(w0 + m), sweep, (uint64_t)j);
-            if (u < exp(2.0 * (lnew - lab))) {
-              accept = 1;
-              lab = lnew;
-              sgn = snew;
-              nacc += 1;
+        int accept[CG];
+#pragma unroll
+        for (int cg = 0; cg < CG; ++cg) {
+          accept[cg] = 0;
+          if (live[cg] && stat[cg] == 0) {
+            double lnew; int snew;
+            amp(16 * cg + m, lnew, snew);
+            if (isnan(lnew)) {
+              stat[cg] = -5;
+            } else if (snew != 0) {
+              const double u = philox_uniform(a.seed, a.rstream, (uint64_t)(w0 + 16 * cg + m), sweep, (uint64_t)j);
+              if (u < exp(2.0 * (lnew - lab[cg]))) {
+                accept[cg] = 1;
+                lab[cg] = lnew;
+                sgn[cg] = snew;
+                nacc[cg] += 1;
+              }
             }
           }
         }
@@ -715,19 +754,25 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
         if (!seq && side == 0) {  // each row lane copies the features it wrote in the first step
           for (int t = 0; t < T; ++t)
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt) {
-              const int off = m * RS + 16 * (wv * MT + mt) + 4 * g;
-              *reinterpret_cast<float4*>(buf(t, P) + off) =
-                  *reinterpret_cast<const float4*>(buf(t, accept ? F : U) + off);
-            }
+            for (int cg = 0; cg < CG; ++cg)
+#pragma unroll
+              for (int mt = 0; mt < MT; ++mt) {
+                const int off = (16 * cg + m) * RS + 16 * (wv * MT + mt) + 4 * g;
+                *reinterpret_cast<float4*>(buf(t, P) + off) =
+                    *reinterpret_cast<const float4*>(buf(t, accept[cg] ? F : U) + off);
+              }
         }
         if (wave == 0 && g == 0) {
-          if (!seq)
-            for (int t = 0; t < T; ++t) Ep[t * 16 + m] = Ef[t * 16 + m];
-          if (accept) {
-            sp[m * nw + (j >> 6)] ^= (1ull << (j & 63));
-            const uint64_t* rmj = a.rmask + (size_t)j * LW;
-            for (int wd = 0; wd < LW; ++wd) pm[m * LW + wd] ^= rmj[wd];
+#pragma unroll
+          for (int cg = 0; cg < CG; ++cg) {
+            const int wn = 16 * cg + m;
+            if (!seq)
+              for (int t = 0; t < T; ++t) Ep[t * NB + wn] = Ef[t * NB + wn];
+            if (accept[cg]) {
+              sp[wn * nw + (j >> 6)] ^= (1ull << (j & 63));
+              const uint64_t* rmj = a.rmask + (size_t)j * LW;
+              for (int wd = 0; wd < LW; ++wd) pm[wn * LW + wd] ^= rmj[wd];
+            }
           }
         }
         __syncthreads();
@@ -739,21 +784,26 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
   }
 
   // write back
-  if (wave == 0 && g == 0 && live) {
-    const int w = w0 + m;
-    if (a.mode == 1)
-      for (int wd = 0; wd < nw; ++wd) a.spins[(size_t)w * nw + wd] = sp[m * nw + wd];
-    const bool ok = stat == 0;
-    if (a.logabs) a.logabs[w] = ok ? lab : NAN;
-    if (a.sign) a.sign[w] = ok ? (int8_t)sgn : 0;
-    if (a.accepts && a.mode == 1) a.accepts[w] += nacc;
-    if (a.status) a.status[w] = stat;
+  if (wave == 0 && g == 0) {
+#pragma unroll
+    for (int cg = 0; cg < CG; ++cg) {
+      if (!live[cg]) continue;
+      const int wn = 16 * cg + m;
+      const int w = w0 + wn;
+      if (a.mode == 1)
+        for (int wd = 0; wd < nw; ++wd) a.spins[(size_t)w * nw + wd] = sp[wn * nw + wd];
+      const bool ok = stat[cg] == 0;
+      if (a.logabs) a.logabs[w] = ok ? lab[cg] : NAN;
+      if (a.sign) a.sign[w] = ok ? (int8_t)sgn[cg] : 0;
+      if (a.accepts && a.mode == 1) a.accepts[w] += nacc[cg];
+      if (a.status) a.status[w] = stat[cg];
+    }
   }
 }
 
-template <class D, int CHI>
+template <class D, int CHI, int CG>
 __global__ void __launch_bounds__(ChainGeo<CHI>::NT) chain_kernel(ChainArgs a) {
-  chain_body<D, CHI>(a, blockIdx.x, a.sweep0);
+  chain_body<D, CHI, CG>(a, blockIdx.x, a.sweep0);
 }
 
 // ============================================================================
@@ -851,7 +901,7 @@ __global__ void __launch_bounds__(ChainGeo<CHI>::NT) chain_persistent(const Chai
     const int it = __builtin_amdgcn_readfirstlane(next_item(counter, &s_item));
     if (it >= n_items) break;
     const int4 w = items[it];
-    chain_body<D, CHI>(descs[w.x], w.y, *sweep0);
+    chain_body<D, CHI, 1>(descs[w.x], w.y, *sweep0);
     __syncthreads();
   }
 }

@@ -164,8 +164,8 @@ size_t pass_lds_bytes(int chi, int nslot, int nw) {
   return (size_t)wpb * (2 * nslot * rs * 4 + 2 * nslot * 4 + nw * 8);
 }
 
-size_t chain_lds_bytes(int chi, int T, int L, int nw) {
-  return (size_t)rttk::ChainLayout(chi, T, (L + 63) / 64, nw).total;
+size_t chain_lds_bytes(int chi, int T, int L, int nw, int cg = 1) {
+  return (size_t)rttk::ChainLayout(chi, T, (L + 63) / 64, nw, cg).total;
 }
 
 }  // namespace
@@ -414,15 +414,37 @@ rtt_status launch_pass(const rttk::PassArgs& a, int T, hipStream_t s) {
   return RTT_OK;
 }
 
-template <class D, int CHI>
-rtt_status launch_chain(const rttk::ChainArgs& a, hipStream_t s) {
-  const size_t lds = chain_lds_bytes(CHI, a.T, a.L, a.nw);
-  auto kfn = rttk::chain_kernel<D, CHI>;
+int device_cus() {
+  int dev = 0, n = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) return 256;
+  return n;
+}
+
+template <class D, int CHI, int CG>
+rtt_status launch_chain_cg(const rttk::ChainArgs& a, hipStream_t s) {
+  const size_t lds = chain_lds_bytes(CHI, a.T, a.L, a.nw, CG);
+  auto kfn = rttk::chain_kernel<D, CHI, CG>;
   HIPX(hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  dim3 grid((a.W + 15) / 16);
+  dim3 grid((a.W + 16 * CG - 1) / (16 * CG));
   hipLaunchKernelGGL(kfn, grid, dim3(rttk::ChainGeo<CHI>::NT), lds, s, a);
   HIPX(hipGetLastError());
   return RTT_OK;
+}
+
+// Bond 128 with enough walkers to give every CU a block of 32 runs two
+// column groups per block (each core fragment serves 32 walkers), if the
+// state still fits on chip in the same layout.  (At 256 the registers of a
+// second group would spill; at 64 and below two waves share each SIMD.)
+template <class D, int CHI>
+rtt_status launch_chain(const rttk::ChainArgs& a, hipStream_t s) {
+  if constexpr (CHI == 128) {
+    const int LW = (a.L + 63) / 64;
+    const rttk::ChainLayout l1(CHI, a.T, LW, a.nw, 1), l2(CHI, a.T, LW, a.nw, 2);
+    if (a.W >= 32 * device_cus() && l2.seq == l1.seq && (size_t)l2.total <= kLdsLimit)
+      return launch_chain_cg<D, CHI, 2>(a, s);
+  }
+  return launch_chain_cg<D, CHI, 1>(a, s);
 }
 
 template <template <class, int> class F, class... Args>

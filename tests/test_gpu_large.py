@@ -1,6 +1,7 @@
 """Shapes that do not fit on chip in one piece: row groups in the flip-ratio
-passes, and the term-sequential sweep of a large linear combination; and the
-16x16, chi = 256, 4-term FP8 workload on sampled spins."""
+passes, and the term-sequential sweep of a large linear combination; the
+16x16, chi = 256, 4-term FP8 workload on sampled spins; and the sampler's
+two-column-group blocks (bond 128, at least 32 walkers per compute unit)."""
 import numpy as np
 import pytest
 import torch
@@ -121,3 +122,37 @@ def test_16x16_chi256_four_term_fp8_sampled(R):
     comb.sweep(spins, seed=w.chain_seed, n_sweeps=1, status=st)
     torch.cuda.synchronize()
     assert torch.all(st == 0)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_two_column_groups_many_walkers(R, dtype):
+    """Bond 128 with 32 * 256 + 24 walkers: the sampler runs 32 walkers per
+    block (two MFMA column groups sharing each core fragment), the last
+    block ragged.  Amplitudes of walkers in both groups, in the first and the
+    last block, match the oracle; one FP32 sweep makes the oracle's decisions
+    for the same walkers (Philox counters follow the walker index)."""
+    N, Rr, chi = 16, 2, 128
+    W = 32 * 256 + 24
+    pi, bond, cores = case(N, Rr, chi, "perm", seed=70)
+    psi = R.RTT.create(N, pi, cores, dtype)
+    qc = device_cores(psi, bond)
+    bits = wl.random_spins(W, N, 71)
+    spins = R.spins_to_device(wl.pack_spins(bits))
+    la, sg = psi.amplitudes(spins)
+    torch.cuda.synchronize()
+    idx = np.r_[0:40, W - 40:W]
+    la_ref, sg_ref = orc.log_sign(orc.amplitudes(qc, pi, bits[idx]))
+    k0 = orc.condition_numbers(qc, pi, bits[idx])
+    tol = {"f32": 1e-5, "bf16": 2e-2}[dtype]
+    assert np.all(sg.cpu().numpy()[idx] == sg_ref)
+    assert np.all(np.abs(la.cpu().numpy()[idx] - la_ref) <= tol * np.maximum(1.0, k0 / 10.0))
+    if dtype != "f32":
+        return
+    psi.sweep(spins, seed=77, rng_stream=2, sweep0=0, n_sweeps=1)
+    torch.cuda.synchronize()
+    got = wl.unpack_spins(R.spins_to_host(spins), N)[idx]
+    ref, _, margins = mcmc.metropolis(qc, pi, bits[idx], seed=77, stream=2, sweep0=0, n_sweeps=1,
+                                      walker_ids=idx, record=True)
+    clean = np.min(np.abs(margins), axis=(0, 1)) > 1e-4
+    assert clean.sum() >= len(idx) - 3
+    assert np.array_equal(got[clean], ref[clean])
