@@ -91,11 +91,11 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int bx, int ty) {
   // Work items = (schedule step, group of MTI output tiles of this wave).
   // When the fragments of all MT tiles fit in registers (MTI = MT) a row
   // tile's activations are read once per step and used for every tile;
-  // otherwise they are read again per tile.  The core fragments of item i+1
+  // otherwise (bond 256) once per half of the tiles.  The core fragments of item i+1
   // are loaded while item i computes.  Rows are stored in the matrix-op
   // form (Act), and renormalisation scales the products, not the inputs.
   constexpr int FRAG_DW = MT * 2 * KPL * (int)sizeof(E) / 4;
-  constexpr int MTI = FRAG_DW <= 128 ? MT : 1;
+  constexpr int MTI = FRAG_DW <= 128 ? MT : (MT % 2 == 0 && FRAG_DW <= 256 ? MT / 2 : 1);
   constexpr int NIS = MT / MTI;  // items per step
   constexpr bool ODD_MFMA = sizeof(E) == 2;
   struct Frags { E m[MTI][KPL]; E o[MTI][KPL]; };
