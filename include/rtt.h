@@ -161,6 +161,36 @@ rtt_status rtt_mcmc_sweep(rtt_t h, int32_t W, uint64_t* spins, double* logabs,
                           int32_t* status, void* stream);
 
 /*
+ * Dual Monte Carlo estimators (Sec. 3.3, "Dual Monte Carlo"): walkers s
+ * sampled from P^a = |psi^a|^2 / Z_a (e.g. by rtt_mcmc_sweep on psi^a),
+ * evaluated against each of M target states psi^b_m:
+ *   ratio[m][w] = psi^b_m(s_w) / psi^a(s_w)
+ *   mixed[m][w] = sum_t H_{s_w,t} psi^b_m(t) / psi^a(s_w)   (mixed local energy)
+ * Their averages over P^a are the row a of the un-symmetrised overlap and
+ * Hamiltonian matrices S~_ab, H~_ab of the physical-space optimisation
+ * (reduce each row with rtt_energy_reduce).  A target may be psi^a itself
+ * (ratio 1, mixed = E_loc) or any RTT / linear combination with the same
+ * spin count.
+ *   targets    host array of M handles, M >= 1
+ *   ham        TFIM on a lattice of N sites
+ *   spins      device uint64[W][ceil(N/64)]
+ *   logabs_a, sign_a  device double[W], int8[W]: log|psi^a| and sign of the
+ *              walkers (as rtt_mcmc_sweep or rtt_amplitudes leave them)
+ *   ratio, mixed  device double[M][W] (row m for target m)
+ *   status     device int32[W] or NULL: 0, or RTT_E_NONFINITE (-5) if the
+ *              sampled or any target amplitude is zero or non-finite (that
+ *              walker's outputs are NaN)
+ * Each target keeps a W-sized workspace, grown on demand (hipMalloc);
+ * calls on one target must not overlap.  Errors: RTT_E_ARG for null
+ * pointers, M < 1, W < 1, invalid handles or spin counts differing from the
+ * lattice; otherwise as rtt_evaluate.
+ */
+rtt_status rtt_mixed_estimators(int32_t M, const rtt_t* targets, rtt_ham_t ham, int32_t W,
+                                const uint64_t* spins, const double* logabs_a,
+                                const int8_t* sign_a, double* ratio, double* mixed,
+                                int32_t* status, void* stream);
+
+/*
  * Compensated (Neumaier) FP64 reduction of x[n] (device): out[0] = sum x,
  * out[1] = sum x^2, out[2] = number of finite entries summed (device
  * double[3]).  Non-finite entries are skipped and not counted.

@@ -924,6 +924,29 @@ __global__ void __launch_bounds__(256) reduce_many(const int* n, const double* c
   reduce_body(n[blockIdx.x], x[blockIdx.x], out + 3 * blockIdx.x);
 }
 
+// Dual Monte Carlo estimators for one target state b, walkers sampled from
+// P^a: ratio = psi^b / psi^a and the mixed local energy
+// sum_t H_st psi^b(t) / psi^a(s) = ratio * E_loc^b(s), from both states'
+// log|psi| and signs and b's local energy.  A walker whose sampled or target
+// amplitude is zero or non-finite gets NaN and status -5; `first` starts the
+// status, later targets fold into it.
+__global__ void __launch_bounds__(256) mixed_kernel(int W, const double* la, const int8_t* sa,
+                                                    const double* lb, const int8_t* sb, const double* eb,
+                                                    const int32_t* stb, double* ratio, double* mixed,
+                                                    int32_t* status, int first) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= W) return;
+  const bool ok = stb[w] == 0 && sa[w] != 0 && sb[w] != 0 && isfinite(la[w]) && isfinite(lb[w]) &&
+                  isfinite(eb[w]);
+  const double r = ok ? (double)(sa[w] * sb[w]) * exp(lb[w] - la[w]) : NAN;
+  ratio[w] = r;
+  mixed[w] = ok ? r * eb[w] : NAN;
+  if (status) {
+    const int32_t st = ok ? 0 : -5;
+    status[w] = first ? st : min(status[w], st);
+  }
+}
+
 // graph-safe clearing of work counters (a kernel, not a memset node)
 __global__ void fill_int(int* p, int n, int v) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;

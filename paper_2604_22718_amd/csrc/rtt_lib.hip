@@ -203,6 +203,12 @@ struct rtt_s {
   float* d_v = nullptr;
   int* d_ue = nullptr;
   int* d_ve = nullptr;
+  // this state's amplitudes and local energies as a dual Monte Carlo target
+  size_t mix_W = 0;
+  double* d_mla = nullptr;
+  int8_t* d_msg = nullptr;
+  double* d_mel = nullptr;
+  int32_t* d_mst = nullptr;
 };
 
 struct rtt_ham_s {
@@ -266,7 +272,8 @@ rtt_status upload(void** dst, const void* src, size_t bytes) {
 
 void free_dev(rtt_s* h) {
   void* ptrs[] = {h->d_grp, h->d_fgs, h->d_bgs, h->d_fwd, h->d_bwd, h->d_cexp, h->d_cesum, h->d_rmask, h->d_sf, h->d_sb, h->d_fslot, h->d_bslot,
-                  h->d_pi, h->d_order, h->d_first, h->d_coeffs, h->d_u, h->d_v, h->d_ue, h->d_ve};
+                  h->d_pi, h->d_order, h->d_first, h->d_coeffs, h->d_u, h->d_v, h->d_ue, h->d_ve,
+                  h->d_mla, h->d_msg, h->d_mel, h->d_mst};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -759,6 +766,48 @@ rtt_status rtt_mcmc_sweep(rtt_t h, int32_t W, uint64_t* spins, double* logabs, i
   g_err.clear();
   return chain_common(h, W, spins, logabs, sign, seed, rng_stream, sweep0, n_sweeps, accepts, status, 1,
                       stream);
+}
+
+rtt_status rtt_mixed_estimators(int32_t M, const rtt_t* targets, rtt_ham_t ham, int32_t W,
+                                const uint64_t* spins, const double* logabs_a, const int8_t* sign_a,
+                                double* ratio, double* mixed, int32_t* status, void* stream) {
+  g_err.clear();
+  if (M < 1 || !targets) return fail(RTT_E_ARG, "rtt_mixed_estimators: M = %d targets", M);
+  if (!ham) return fail(RTT_E_ARG, "rtt_mixed_estimators: Hamiltonian is null");
+  if (W < 1) return fail(RTT_E_ARG, "rtt_mixed_estimators: W = %d < 1", W);
+  if (!spins || !logabs_a || !sign_a || !ratio || !mixed)
+    return fail(RTT_E_ARG, "rtt_mixed_estimators: null device pointer");
+  for (int m = 0; m < M; ++m) {
+    if (check_handle(targets[m]) != RTT_OK) return RTT_E_ARG;
+    if (targets[m]->N != ham->Lx * ham->Ly)
+      return fail(RTT_E_ARG, "rtt_mixed_estimators: target %d has %d spins, lattice %d sites", m,
+                  targets[m]->N, ham->Lx * ham->Ly);
+    if (targets[m]->N != targets[0]->N)
+      return fail(RTT_E_ARG, "rtt_mixed_estimators: targets differ in spin count");
+  }
+  hipStream_t s = (hipStream_t)stream;
+  for (int m = 0; m < M; ++m) {
+    rtt_s* b = targets[m];
+    if ((size_t)W > b->mix_W) {
+      for (void* p : {(void*)b->d_mla, (void*)b->d_msg, (void*)b->d_mel, (void*)b->d_mst})
+        if (p) HIPX(hipFree(p));
+      b->d_mla = nullptr; b->d_msg = nullptr; b->d_mel = nullptr; b->d_mst = nullptr;
+      b->mix_W = 0;
+      HIPX(hipMalloc(&b->d_mla, (size_t)W * 8));
+      HIPX(hipMalloc(&b->d_msg, (size_t)W));
+      HIPX(hipMalloc(&b->d_mel, (size_t)W * 8));
+      HIPX(hipMalloc(&b->d_mst, (size_t)W * 4));
+      b->mix_W = W;
+    }
+    rtt_status st = rtt_evaluate(b, ham, W, spins, b->d_mla, b->d_msg, nullptr, nullptr, b->d_mel, b->d_mst,
+                                 stream);
+    if (st != RTT_OK) return st;
+    hipLaunchKernelGGL(rttk::mixed_kernel, dim3((W + 255) / 256), dim3(256), 0, s, W, logabs_a, sign_a,
+                       b->d_mla, b->d_msg, b->d_mel, b->d_mst, ratio + (size_t)m * W, mixed + (size_t)m * W,
+                       status, m == 0 ? 1 : 0);
+    HIPX(hipGetLastError());
+  }
+  return RTT_OK;
 }
 
 rtt_status rtt_energy_reduce(int32_t n, const double* x, double* out, void* stream) {

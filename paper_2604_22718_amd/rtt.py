@@ -102,6 +102,15 @@ def rtt_energy_reduce(x, out):
     check(lib().rtt_energy_reduce(x.numel(), _ptr(x), _ptr(out), _stream()))
 
 
+def rtt_mixed_estimators(targets, ham, spins, logabs_a, sign_a, ratio, mixed, status=None):
+    """targets: list of RTT handles; ratio, mixed: float64 [M][W] device tensors."""
+    M = len(targets)
+    arr = (C.c_void_p * M)(*[t.value for t in targets])
+    W = spins.shape[0]
+    check(lib().rtt_mixed_estimators(M, C.cast(arr, C.c_void_p), ham, W, _ptr(spins), _ptr(logabs_a),
+                                      _ptr(sign_a), _ptr(ratio), _ptr(mixed), _ptr(status), _stream()))
+
+
 def rtt_batch_create(rtts, hams, walkers, spins, eloc, seed):
     n = len(rtts)
     arr = lambda xs: (C.c_void_p * n)(*xs)
@@ -360,6 +369,18 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def mixed_estimators(targets, ham, spins, logabs_a, sign_a):
+    """Dual Monte Carlo estimators of walkers sampled from psi^a against the
+    RTT objects ``targets``: (ratio, mixed, status), ratio and mixed [M][W]."""
+    M, W = len(targets), spins.shape[0]
+    ratio = torch.empty((M, W), dtype=torch.float64, device=spins.device)
+    mixed = torch.empty((M, W), dtype=torch.float64, device=spins.device)
+    status = torch.empty(W, dtype=torch.int32, device=spins.device)
+    rtt_mixed_estimators([t.handle for t in targets], ham.handle, spins, logabs_a, sign_a, ratio, mixed,
+                         status)
+    return ratio, mixed, status
 
 
 def energy_reduce(x):

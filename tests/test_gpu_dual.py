@@ -1,0 +1,140 @@
+"""Dual Monte Carlo on the GPU (paper Sec. 3.3) through the C ABI against
+the FP64 oracle: per-walker overlap and mixed-energy estimators, the matrices
+H~ and S~ from GPU-sampled chains against exact enumeration, the lowest
+generalised eigenvalue, and stochastic Gram-Schmidt with a GPU overlap."""
+import numpy as np
+import pytest
+import scipy.linalg
+import torch
+
+from helpers import case, device_cores
+from oracle import dual, rtt as orc, stats, tfim
+from paper_2604_22718_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+J, HF = 1.0, 3.04
+
+
+@pytest.fixture(scope="module")
+def R():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2604_22718_amd import rtt
+    return rtt
+
+
+def states(R, N, Rr, chi, seed, dtype):
+    """Two RTTs on one path and their combination 0.8 a - 1.1 b."""
+    pi, bond, ca = case(N, Rr, chi, "perm", seed=seed)
+    cb = wl.gaussian_cores(bond, seed + 100)
+    a = R.RTT.create(N, pi, ca, dtype)
+    b = R.RTT.create(N, pi, cb, dtype)
+    coeffs = np.array([0.8, -1.1])
+    c = R.RTT.lincomb([a, b], coeffs)
+    qa, qb = device_cores(a, bond), device_cores(b, bond)
+    return pi, [a, b, c], [qa, qb, ([qa, qb], coeffs)]
+
+
+@pytest.mark.parametrize("dtype,tol", [("f32", 1e-5), ("bf16", 2e-2)])
+def test_mixed_estimators_match_oracle(R, dtype, tol):
+    Lx, Ly = 4, 4
+    N = Lx * Ly
+    pi, gpu, ref = states(R, N, 2, 16, 300, dtype)
+    ham = R.TFIM(Lx, Ly, J, HF)
+    bonds = tfim.bonds(Lx, Ly)
+    W = 37
+    bits = wl.random_spins(W, N, 301)
+    spins = R.spins_to_device(wl.pack_spins(bits))
+    for a in range(3):
+        la, sg = gpu[a].amplitudes(spins)
+        ratio, mixed, st = R.mixed_estimators(gpu, ham, spins, la, sg)
+        torch.cuda.synchronize()
+        ratio, mixed, st = ratio.cpu().numpy(), mixed.cpu().numpy(), st.cpu().numpy()
+        assert np.all(st == 0)
+        for b in range(3):
+            o_ref, e_ref = dual.mixed_estimators(ref[a], ref[b], pi, bits, bonds, J, HF)
+            # condition numbers of both states (combinations: those of their terms)
+            def kap(x):
+                if isinstance(x, tuple):
+                    return np.max([orc.flip_condition_numbers(t, pi, bits).max(axis=1) for t in x[0]], axis=0)
+                return orc.flip_condition_numbers(x, pi, bits).max(axis=1)
+            allow = tol * np.maximum(1.0, np.maximum(kap(ref[a]), kap(ref[b])) / 10.0)
+            dlog = np.abs(np.log(np.abs(ratio[b])) - np.log(np.abs(o_ref)))
+            assert np.all(dlog <= allow), (a, b, dlog.max())
+            assert np.all(np.sign(ratio[b]) == np.sign(o_ref))
+            # mixed = ratio * E_loc^b: error bounded by the size of its terms
+            pb_flips = np.abs(orc.flip_ratios(ref[b], pi, bits)) if not isinstance(ref[b], tuple) else \
+                np.abs(orc.lincomb_flip_ratios(ref[b][0], ref[b][1], pi, bits))
+            scale = np.abs(o_ref) * (J * len(bonds) + HF * pb_flips.sum(axis=1))
+            assert np.all(np.abs(mixed[b] - e_ref) <= 2 * allow * scale), (a, b)
+
+
+def test_dual_mc_matrices_within_3_sigma(R):
+    """3x3 lattice, three states (two RTTs and their combination), FP32:
+    every row of H~ and S~ from a GPU chain on P^a agrees with enumeration
+    within 3 sigma, and so does the lowest generalised eigenvalue."""
+    Lx, Ly = 3, 3
+    N = Lx * Ly
+    pi, gpu, ref = states(R, N, 2, 8, 310, "f32")
+    ham = R.TFIM(Lx, Ly, J, HF)
+    Ht_ex, St_ex, _ = dual.exact_matrices(ref, pi, Lx, Ly, J, HF)
+    W, burn, meas = 4096, 20, 40
+    Ht = np.zeros((3, 3)); St = np.zeros((3, 3)); sH = np.zeros((3, 3)); sS = np.zeros((3, 3))
+    for a in range(3):
+        spins = R.spins_to_device(wl.pack_spins(wl.random_spins(W, N, 311 + a)))
+        la = torch.empty(W, dtype=torch.float64, device="cuda")
+        sg = torch.empty(W, dtype=torch.int8, device="cuda")
+        gpu[a].sweep(spins, seed=312, rng_stream=a, sweep0=0, n_sweeps=burn, logabs=la, sign=sg)
+        rows_o, rows_e = [], []
+        for t in range(meas):
+            gpu[a].sweep(spins, seed=312, rng_stream=a, sweep0=burn + t, n_sweeps=1, logabs=la, sign=sg)
+            ratio, mixed, st = R.mixed_estimators(gpu, ham, spins, la, sg)
+            rows_o.append(ratio.mean(dim=1))
+            rows_e.append(mixed.mean(dim=1))
+        O = torch.stack(rows_o).cpu().numpy()      # (meas, 3)
+        E = torch.stack(rows_e).cpu().numpy()
+        for b in range(3):
+            for X, est, sig, ex in ((O, St, sS, St_ex), (E, Ht, sH, Ht_ex)):
+                m, s, tau, _ = stats.energy_estimate(X[:, b:b + 1])
+                est[a, b], sig[a, b] = m, s
+                # statistical error plus the FP32 evaluation tolerance (1e-5)
+                assert abs(m - ex[a, b]) < 3 * s + 1e-5 * (1.0 + abs(ex[a, b])), (a, b, m, ex[a, b], s)
+    lam = dual.lowest_generalised_eigenvalue(Ht, St)
+    lam_ex = dual.lowest_generalised_eigenvalue(Ht_ex, St_ex)
+    print(f"lambda0 GPU {lam:.5f} exact {lam_ex:.5f}")
+    e0, _ = tfim.ground_state(Lx, Ly, J, HF)
+    assert lam_ex >= e0 - 1e-9
+    assert abs(lam - lam_ex) < 0.02 * abs(lam_ex)
+
+
+def test_gram_schmidt_with_gpu_overlap(R):
+    """psi'^b = psi^b - S~_ab psi^a built on the GPU (rtt_lincomb) from the
+    GPU estimate of S~_ab has an overlap estimator averaging to 0 within
+    3 sigma under P^a, and exactly (enumeration) to the residual
+    S~_ab(exact) - S~_ab(estimate)."""
+    Lx, Ly = 3, 3
+    N = Lx * Ly
+    pi, gpu, ref = states(R, N, 2, 8, 320, "f32")
+    ham = R.TFIM(Lx, Ly, J, HF)
+    W, burn, meas = 4096, 20, 40
+
+    def overlap_series(a, targets, stream):
+        spins = R.spins_to_device(wl.pack_spins(wl.random_spins(W, N, 321 + stream)))
+        la = torch.empty(W, dtype=torch.float64, device="cuda")
+        sg = torch.empty(W, dtype=torch.int8, device="cuda")
+        gpu[a].sweep(spins, seed=322, rng_stream=stream, sweep0=0, n_sweeps=burn, logabs=la, sign=sg)
+        out = []
+        for t in range(meas):
+            gpu[a].sweep(spins, seed=322, rng_stream=stream, sweep0=burn + t, n_sweeps=1, logabs=la, sign=sg)
+            ratio, _, _ = R.mixed_estimators(targets, ham, spins, la, sg)
+            out.append(ratio.mean(dim=1))
+        return torch.stack(out).cpu().numpy()
+
+    s_ab = float(overlap_series(0, [gpu[1]], 0)[:, 0].mean())
+    b2 = R.RTT.lincomb([gpu[1], gpu[0]], np.array([1.0, -s_ab]))
+    X = overlap_series(0, [b2], 1)[:, 0]
+    m, s, _, _ = stats.energy_estimate(X[:, None])
+    _, St_ex, _ = dual.exact_matrices([ref[0], ref[1]], pi, Lx, Ly, J, HF)
+    resid = St_ex[0, 1] - s_ab
+    assert abs(m - resid) < 3 * s + 1e-5
+    assert abs(m) < 3 * s + abs(resid) + 1e-5
