@@ -392,6 +392,61 @@ def run_wide(name, n_eval=3, with_sweep=True):
     return out
 
 
+def run_dual(steps=5, warmup=1):
+    """Dual Monte Carlo step on the 8x8 workload (chi=64, FP32, 4096 walkers
+    per chain): three states (the workload's RTT, a second seeded RTT and
+    their combination 0.8 a - 1.1 b); for each state one sweep of its own
+    chain, then overlap and mixed-energy estimators of its walkers against
+    all three states (rows of H~ and S~)."""
+    import torch
+
+    from paper_2604_22718_amd import rtt as R
+    from paper_2604_22718_amd import workloads as wl
+    w = wl.MEDIUM_8x8
+    pi = w.pi()
+    a = R.RTT.create(w.N, pi, w.cores(), "f32")
+    b = R.RTT.create(w.N, pi, wl.gaussian_cores(w.bond(), w.core_seed + 5), "f32")
+    c = R.RTT.lincomb([a, b], np.array([0.8, -1.1]))
+    states = [a, b, c]
+    ham = R.TFIM(w.Lx, w.Ly, w.J, w.h)
+    W, M = w.W, len(states)
+    chains = []
+    for i in range(M):
+        spins = R.spins_to_device(wl.pack_spins(wl.random_spins(W, w.N, w.chain_seed + 10 + i)))
+        la = torch.empty(W, dtype=torch.float64, device="cuda")
+        sg = torch.empty(W, dtype=torch.int8, device="cuda")
+        chains.append((spins, la, sg))
+    sums = torch.zeros((M, 2, M), dtype=torch.float64, device="cuda")
+
+    def step(t):
+        for i, (spins, la, sg) in enumerate(chains):
+            states[i].sweep(spins, seed=w.chain_seed, rng_stream=100 + i, sweep0=t, n_sweeps=1, logabs=la, sign=sg)
+            ratio, mixed, _ = R.mixed_estimators(states, ham, spins, la, sg)
+            sums[i, 0] += ratio.mean(dim=1)
+            sums[i, 1] += mixed.mean(dim=1)
+
+    for t in range(warmup):
+        step(t)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for t in range(steps):
+        step(warmup + t)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    S = (sums[:, 0] / (steps + warmup)).cpu().numpy()
+    H = (sums[:, 1] / (steps + warmup)).cpu().numpy()
+    out = {"workload": w.name + "_dual3", "states": M, "walkers_per_chain": W, "ms_per_step": ms,
+           "mixed_estimator_evals_per_s": W * M * M / (ms * 1e-3),
+           "step": "per state: 1 sweep + overlap and mixed-energy estimators against all 3 states",
+           "S_tilde_diag": np.diag(S).tolist(), "H_tilde_diag_per_site": (np.diag(H) / w.N).tolist()}
+    for x in states[::-1]:
+        x.close()
+    ham.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -404,6 +459,7 @@ def main():
     ap.add_argument("--learned", action="store_true", help="also compare learned-proposal ESS/s (10x10, chi=128)")
     ap.add_argument("--no-wide", action="store_true", help="skip the 10x10 chi=128 BF16 wide-bond line")
     ap.add_argument("--huge", action="store_true", help="also time the 16x16 chi=256 4-term FP8 workload (slow)")
+    ap.add_argument("--no-dual", action="store_true", help="skip the dual Monte Carlo line")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only copy this many MiB device-to-device 3 times (counter calibration) and exit")
     a = ap.parse_args()
@@ -432,6 +488,8 @@ def main():
         res["wide_bond"] = [run_wide("tfim10x10_R3_chi128_W8192")]
         if a.huge:
             res["wide_bond"].append(run_wide("tfim16x16_R2_chi256_W16384_T4", n_eval=1))
+    if not a.no_dual:
+        res["dual_mc"] = run_dual()
     if a.batched:
         res["batched"] = run_batched(a.batched)
     if a.learned:
