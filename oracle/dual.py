@@ -84,3 +84,26 @@ def gram_schmidt_coefficients(St) -> np.ndarray:
         for a in range(m):
             C[m, a] = -St[a, m]
     return C
+
+
+def apply_z(cores, pi, i: int):
+    """The RTT of Z_i psi: Z on a spin acts on one of its replicas (Sec. 2.2.3
+    commutation rules), here the first position k of spin i, whose slice 1
+    changes sign, since Z|s> = (-1)^s |s>."""
+    k = int(np.flatnonzero(np.asarray(pi) == i)[0])
+    out = [np.array(c, copy=True) for c in cores]
+    out[k][1] = -out[k][1]
+    return out
+
+
+def z_only_matrices(ratio_rows, mixed_rows):
+    """Z-only shortcut: when every state is psi^a = d_a psi with d_a(s) = +-1
+    (diagonal operators made of Z's), all P^a equal P = |psi|^2/Z and one
+    chain on psi gives every element.  Inputs are per-walker arrays over
+    walkers sampled from P: ratio_rows[b] = psi^b/psi and mixed_rows[b] =
+    sum_t H_st psi^b(t)/psi(s).  Returns per-walker H~ and S~ estimators of
+    shape (M, M, W): S~_ab = psi^b/psi^a = r_b / r_a and
+    H~_ab = mixed_b / r_a (r_a = +-1)."""
+    r = np.asarray(ratio_rows)
+    e = np.asarray(mixed_rows)
+    return e[None, :, :] / r[:, None, :], r[None, :, :] / r[:, None, :]

@@ -138,3 +138,36 @@ def test_gram_schmidt_with_gpu_overlap(R):
     resid = St_ex[0, 1] - s_ab
     assert abs(m - resid) < 3 * s + 1e-5
     assert abs(m) < 3 * s + abs(resid) + 1e-5
+
+
+def test_z_only_shortcut_single_chain(R):
+    """States made by Z operators (Z_0 Z_1 psi, Z_4 psi) share |psi|^2, so one
+    GPU chain on psi with rtt_mixed_estimators against all three states gives
+    every element of H~ and S~ (paper Sec. 4, Z-only remark); all nine within
+    3 sigma of enumeration."""
+    Lx, Ly = 3, 3
+    N = Lx * Ly
+    pi, bond, c0 = case(N, 2, 8, "perm", seed=330)
+    cores = [c0, dual.apply_z(dual.apply_z(c0, pi, 0), pi, 1), dual.apply_z(c0, pi, 4)]
+    gpu = [R.RTT.create(N, pi, c, "f32") for c in cores]
+    ref = [device_cores(g, bond) for g in gpu]
+    Ht_ex, St_ex, _ = dual.exact_matrices(ref, pi, Lx, Ly, J, HF)
+    ham = R.TFIM(Lx, Ly, J, HF)
+    W, burn, meas = 4096, 20, 40
+    spins = R.spins_to_device(wl.pack_spins(wl.random_spins(W, N, 331)))
+    la = torch.empty(W, dtype=torch.float64, device="cuda")
+    sg = torch.empty(W, dtype=torch.int8, device="cuda")
+    gpu[0].sweep(spins, seed=332, sweep0=0, n_sweeps=burn, logabs=la, sign=sg)
+    Hs, Ss = [], []
+    for t in range(meas):
+        gpu[0].sweep(spins, seed=332, sweep0=burn + t, n_sweeps=1, logabs=la, sign=sg)
+        ratio, mixed, st = R.mixed_estimators(gpu, ham, spins, la, sg)
+        Hs.append((mixed[None, :, :] / ratio[:, None, :]).mean(dim=2))
+        Ss.append((ratio[None, :, :] / ratio[:, None, :]).mean(dim=2))
+    Hs = torch.stack(Hs).cpu().numpy()   # (meas, 3, 3)
+    Ss = torch.stack(Ss).cpu().numpy()
+    for X, ex in ((Hs, Ht_ex), (Ss, St_ex)):
+        for a in range(3):
+            for b in range(3):
+                m, s, _, _ = stats.energy_estimate(X[:, a, b:b + 1])
+                assert abs(m - ex[a, b]) < 3 * s + 1e-5 * (1.0 + abs(ex[a, b])), (a, b, m, ex[a, b], s)

@@ -120,3 +120,35 @@ def test_sampled_estimates_within_three_sigma():
     for series, exact in ((np.array(os_), St[a, b]), (np.array(es), Ht[a, b])):
         sig = series.std(ddof=1) / np.sqrt(len(series)) * 2.0   # generous tau
         assert abs(series.mean() - exact) < 3 * sig + 1e-12
+
+
+def test_z_operator_on_one_replica():
+    """Negating slice 1 of one replica core of spin i gives (-1)^{s_i} psi
+    (closed form over every configuration), whichever replica is used."""
+    N, R = 6, 2
+    pi = wl.path_site_plus_perms(N, R, 95)
+    cores = wl.gaussian_cores(wl.open_bonds(N * R, 3), 96)
+    S = rtt.all_configs(N)
+    psi = rtt.amplitudes(cores, pi, S)
+    for i in (0, 3, 5):
+        z = rtt.amplitudes(dual.apply_z(cores, pi, i), pi, S)
+        assert np.allclose(z, (1 - 2 * S[:, i].astype(np.int64)) * psi, rtol=1e-12, atol=0)
+
+
+def test_z_only_shortcut_equals_enumeration():
+    """States Z_i Z_j psi: every row of H~ and S~ is the average over
+    P = |psi|^2 / Z of the single chain's estimators, mapped by
+    z_only_matrices (exact enumeration on both sides)."""
+    Lx, Ly = 3, 2
+    N = Lx * Ly
+    pi = wl.path_site_plus_perms(N, 2, 97)
+    psi = wl.gaussian_cores(wl.open_bonds(2 * N, 3), 98)
+    states = [psi, dual.apply_z(dual.apply_z(psi, pi, 0), pi, 1), dual.apply_z(psi, pi, 4)]
+    Ht, St, _ = dual.exact_matrices(states, pi, Lx, Ly, J, H_FIELD)
+    S = rtt.all_configs(N)
+    p = rtt.amplitudes(psi, pi, S)
+    P = p * p / (p @ p)
+    rows = [dual.mixed_estimators(psi, st, pi, S, tfim.bonds(Lx, Ly), J, H_FIELD) for st in states]
+    h, s = dual.z_only_matrices([r[0] for r in rows], [r[1] for r in rows])
+    assert np.allclose(h @ P, Ht, rtol=1e-10, atol=1e-10)
+    assert np.allclose(s @ P, St, rtol=1e-10, atol=1e-12)
