@@ -31,6 +31,19 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float x) {
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) {
   return __uint_as_float((uint32_t)h << 16);
 }
+// two FP32 values to a packed BF16 pair (element 0 in the low half), RNE,
+// one hardware conversion
+__device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
+  typedef float f2 __attribute__((ext_vector_type(2)));
+  typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+  const b2 h = __builtin_convertvector(f2{a, b}, b2);
+  return __builtin_bit_cast(uint32_t, h);
+}
+// hi = RNE(x) and lo = RNE(x - hi) for a pair of values, packed
+__device__ __forceinline__ void split_bf16x2(float a, float b, uint32_t& hi, uint32_t& lo) {
+  hi = pack_bf16x2(a, b);
+  lo = pack_bf16x2(a - __uint_as_float(hi << 16), b - __uint_as_float(hi & 0xffff0000u));
+}
 
 // ---------------------------------------------------------------- dtype traits
 // Storage element of packed cores and the K-loop of one 16x16 output tile.
@@ -74,15 +87,13 @@ struct DBF16 {
   __device__ __forceinline__ static void prep(const float (&x)[KPL], BOp<KPL>& b) {
 #pragma unroll
     for (int c = 0; c < KPL / 8; ++c) {
-      bf16x8 hi, lo;
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const __bf16 h = (__bf16)x[8 * c + i];  // round to nearest even
-        hi[i] = h;
-        lo[i] = (__bf16)(x[8 * c + i] - (float)h);
-      }
-      b.hi[c] = hi;
-      b.lo[c] = lo;
+      uint4 h, l;
+      split_bf16x2(x[8 * c + 0], x[8 * c + 1], h.x, l.x);
+      split_bf16x2(x[8 * c + 2], x[8 * c + 3], h.y, l.y);
+      split_bf16x2(x[8 * c + 4], x[8 * c + 5], h.z, l.z);
+      split_bf16x2(x[8 * c + 6], x[8 * c + 7], h.w, l.w);
+      b.hi[c] = __builtin_bit_cast(bf16x8, h);
+      b.lo[c] = __builtin_bit_cast(bf16x8, l);
     }
   }
   template <int KPL>
@@ -279,12 +290,12 @@ struct Act<DBF16, CHI> {
     l = __builtin_bit_cast(uint16_t, xl);
   }
   __device__ __forceinline__ static void store4(float* row, int col, f4 v) {
-    uint16_t h[4], l[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) split(v[i], h[i], l[i]);
+    uint32_t h01, l01, h23, l23;
+    split_bf16x2(v[0], v[1], h01, l01);
+    split_bf16x2(v[2], v[3], h23, l23);
     uint16_t* p = hi(row) + col;
-    *reinterpret_cast<uint2*>(p) = make_uint2(h[0] | ((uint32_t)h[1] << 16), h[2] | ((uint32_t)h[3] << 16));
-    *reinterpret_cast<uint2*>(p + CHI) = make_uint2(l[0] | ((uint32_t)l[1] << 16), l[2] | ((uint32_t)l[3] << 16));
+    *reinterpret_cast<uint2*>(p) = make_uint2(h01, h23);
+    *reinterpret_cast<uint2*>(p + CHI) = make_uint2(l01, l23);
   }
   __device__ __forceinline__ static void store1(float* row, int col, float x) {
     uint16_t h, l;

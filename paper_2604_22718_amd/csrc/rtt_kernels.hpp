@@ -133,15 +133,14 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int bx, int ty) {
       typename D::template BOp<KPL> bo;
       A::template load_b<KPL>(cur + row * RS, g, bo);
       const int e = rn ? A::template row_exp<KPL>(bo) : 0;
+      const float sc = __builtin_amdgcn_ldexpf(1.f, -e);  // exact power of two
       if (ig == 0 && wv == 0 && g == 0) exn[row] = exc[row] + e + cexp;
 #pragma unroll
       for (int q = 0; q < MTI; ++q) {
         f4 acc = {0.f, 0.f, 0.f, 0.f};
         acc = D::template mma<KPL>(F.m[q], bo, acc);
-        if (rn) {
 #pragma unroll
-          for (int i = 0; i < 4; ++i) acc[i] = __builtin_amdgcn_ldexpf(acc[i], -e);
-        }
+        for (int i = 0; i < 4; ++i) acc[i] *= sc;
         A::store4(nxt + row * RS, 16 * (wv * MT + ig * MTI + q) + 4 * g, acc);
       }
       if (ODD_MFMA && r == (oin >> 4)) {
@@ -150,10 +149,8 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int bx, int ty) {
         for (int q = 0; q < MTI; ++q) {
           f4 acc = {0.f, 0.f, 0.f, 0.f};
           acc = D::template mma<KPL>(F.o[q], bo, acc);
-          if (rn) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) acc[i] = __builtin_amdgcn_ldexpf(acc[i], -e);
-          }
+          for (int i = 0; i < 4; ++i) acc[i] *= sc;
           oacc[q] = acc;
         }
       }
