@@ -342,3 +342,28 @@ def test_chain_energy_matches_exact_enumeration(R):
     mean, sigma, tau, var = stats.energy_estimate(E)
     print(f"GPU <E> {mean:.6f} +- {sigma:.6f} (tau {tau:.2f}) exact {exact:.6f}")
     assert abs(mean - exact) < 3 * sigma
+
+
+@pytest.mark.parametrize("dtype,chi", [("bf16", 32), ("fp8", 64), ("bf16", 128), ("bf16", 256)])
+def test_sweep_decisions_reduced_precision(R, dtype, chi):
+    """BF16 / FP8 cores (hi+lo BF16 activations): one GPU sweep makes the
+    oracle's decisions (same Philox words, oracle on the library's quantised
+    cores) for every walker whose margins |u - r^2| all exceed 1e-2, widened
+    by the condition number.  The stated tolerance (2e-2 on log-ratios)
+    would allow flips up to ~4e-2; the hi+lo path is far more accurate, and
+    this pins that its decisions follow the exact ones away from ties."""
+    N, Rr, W = 12, 2, 24
+    pi, bond, cores = case(N, Rr, chi, "perm", seed=340 + chi)
+    psi = R.RTT.create(N, pi, cores, dtype)
+    qc = device_cores(psi, bond)
+    bits = wl.random_spins(W, N, 341)
+    spins = R.spins_to_device(wl.pack_spins(bits))
+    psi.sweep(spins, seed=342, rng_stream=1, sweep0=0, n_sweeps=1)
+    torch.cuda.synchronize()
+    got = wl.unpack_spins(R.spins_to_host(spins), N)
+    ref, _, margins = mcmc.metropolis(qc, pi, bits, seed=342, stream=1, sweep0=0, n_sweeps=1, record=True)
+    kap = orc.condition_numbers(qc, pi, bits)
+    allow = 1e-2 * np.maximum(1.0, kap / 10.0)
+    clean = np.all(np.abs(margins[0]) > allow[None, :], axis=0)
+    assert clean.sum() >= W // 2, clean.sum()
+    assert np.array_equal(got[clean], ref[clean])
