@@ -191,6 +191,41 @@ rtt_status rtt_mixed_estimators(int32_t M, const rtt_t* targets, rtt_ham_t ham, 
                                 int32_t* status, void* stream);
 
 /*
+ * Tensor-train rounding on the host (FP64): right-to-left orthogonalisation
+ * by Householder QR, then left-to-right truncated SVDs keeping at most
+ * chi_max singular values per bond and none below rel_tol times the
+ * largest.  Compression step of the replica-space optimisation (Sec. 3.1).
+ *   bond, cores   host, rtt_create layout (bond[0] = bond[L] = 1)
+ *   bond_out      host int32[L+1]; cores_out host double[cap]
+ *   n_out         doubles written (or needed, with RTT_E_ARG when cap is short)
+ * Synchronous, no GPU work.  Errors: RTT_E_ARG for bad bonds, non-finite
+ * entries, chi_max < 1, rel_tol < 0 or too small an output.
+ */
+rtt_status rtt_tt_round(int32_t n_cores, const int32_t* bond, const double* cores,
+                        int32_t chi_max, double rel_tol, int32_t* bond_out,
+                        double* cores_out, int64_t cap, int64_t* n_out);
+
+/*
+ * One replica-space power step for the TFIM (Sec. 3.1, optimisation in the
+ * replica space, with the Sec. 2.2.3 commutation rules): for the train phi
+ * of path pi, returns round(phi - tau * H-bar phi) where
+ *   H-bar = J sum_<ij> Zbar_i Zbar_j - h sum_j Xbar_j,
+ * Xbar_j swaps the slices of every core reading spin j, Zbar_i changes the
+ * sign of slice 1 of the first core reading spin i, so that C phi' =
+ * (1 - tau H) C phi before compression.  The terms of H-bar phi are summed
+ * two by two with a rounding (chi_max, rel_tol) after each sum; the final
+ * difference is rounded once more.  Lattice Lx x Ly (= n_spins sites) with
+ * the bonds of rtt_tfim_create; every spin must be read by some position.
+ * Host FP64, synchronous; outputs and errors as rtt_tt_round.
+ */
+rtt_status rtt_tfim_power_step(int32_t n_spins, int32_t n_cores, const int32_t* pi,
+                               const int32_t* bond, const double* cores, int32_t Lx,
+                               int32_t Ly, int32_t periodic, double J, double h,
+                               double tau, int32_t chi_max, double rel_tol,
+                               int32_t* bond_out, double* cores_out, int64_t cap,
+                               int64_t* n_out);
+
+/*
  * Compensated (Neumaier) FP64 reduction of x[n] (device): out[0] = sum x,
  * out[1] = sum x^2, out[2] = number of finite entries summed (device
  * double[3]).  Non-finite entries are skipped and not counted.

@@ -33,6 +33,10 @@ SIGNATURES = {
                                  C.c_int32, P, P, P]),
     "rtt_energy_reduce": (C.c_int, [C.c_int32, P, P, P]),
     "rtt_mixed_estimators": (C.c_int, [C.c_int32, P, P, C.c_int32, P, P, P, P, P, P, P]),
+    "rtt_tt_round": (C.c_int, [C.c_int32, P, P, C.c_int32, C.c_double, P, P, C.c_int64, C.POINTER(C.c_int64)]),
+    "rtt_tfim_power_step": (C.c_int, [C.c_int32, C.c_int32, P, P, P, C.c_int32, C.c_int32, C.c_int32,
+                                      C.c_double, C.c_double, C.c_double, C.c_int32, C.c_double, P, P,
+                                      C.c_int64, C.POINTER(C.c_int64)]),
     "rtt_batch_create": (C.c_int, [C.c_int32, P, P, P, P, P, C.c_uint64, C.POINTER(P)]),
     "rtt_batch_step": (C.c_int, [P, C.c_int32, P, P]),
     "rtt_batch_autotune": (C.c_int, [P, C.c_int32, C.c_int32, C.c_char_p, P, P]),

@@ -14,6 +14,7 @@
 #include "../../include/rtt.h"
 #include "rtt_kernels.hpp"
 #include "rtt_net.hpp"
+#include "rtt_tt.hpp"
 
 namespace {
 
@@ -483,6 +484,54 @@ struct ChainL {
   static rtt_status run(const rttk::ChainArgs& a, hipStream_t s) { return launch_chain<D, CHI>(a, s); }
 };
 
+// nearest-neighbour bonds (i, i + x) and (i, i + y); wrap bonds on sides >= 3
+std::vector<int2> tfim_bond_list(int Lx, int Ly, int periodic) {
+  std::vector<int2> b;
+  for (int y = 0; y < Ly; ++y)
+    for (int x = 0; x < Lx; ++x) {
+      const int i = y * Lx + x;
+      if (x + 1 < Lx) b.push_back(make_int2(i, y * Lx + x + 1));
+      else if (periodic && Lx >= 3) b.push_back(make_int2(i, y * Lx));
+      if (y + 1 < Ly) b.push_back(make_int2(i, (y + 1) * Lx + x));
+      else if (periodic && Ly >= 3) b.push_back(make_int2(i, x));
+    }
+  return b;
+}
+
+// read a host train (rtt_create layout) with its bonds checked
+rtt_status read_train(const char* who, int32_t L, const int32_t* bond, const double* cores, rtt_tt::Train& t) {
+  if (L < 1 || !bond || !cores) return fail(RTT_E_ARG, "%s: empty train or null pointer", who);
+  if (bond[0] != 1 || bond[L] != 1) return fail(RTT_E_ARG, "%s: boundary bonds must be 1", who);
+  t.bond.assign(bond, bond + L + 1);
+  t.core.resize(L);
+  size_t off = 0;
+  for (int k = 0; k < L; ++k) {
+    if (bond[k] < 1 || bond[k] > 4096) return fail(RTT_E_ARG, "%s: bond[%d] = %d", who, k, bond[k]);
+    const size_t n = (size_t)2 * bond[k] * bond[k + 1];
+    t.core[k].assign(cores + off, cores + off + n);
+    for (double x : t.core[k])
+      if (!isfinite(x)) return fail(RTT_E_ARG, "%s: non-finite core entry at position %d", who, k);
+    off += n;
+  }
+  return RTT_OK;
+}
+
+rtt_status write_train(const char* who, const rtt_tt::Train& t, int32_t* bond_out, double* cores_out, int64_t cap,
+                       int64_t* n_out) {
+  int64_t need = 0;
+  for (int k = 0; k < t.L(); ++k) need += (int64_t)t.core[k].size();
+  if (n_out) *n_out = need;
+  if (!bond_out || !cores_out || cap < need)
+    return fail(RTT_E_ARG, "%s: output needs %lld doubles, capacity %lld", who, (long long)need, (long long)cap);
+  for (int k = 0; k <= t.L(); ++k) bond_out[k] = t.bond[k];
+  int64_t off = 0;
+  for (int k = 0; k < t.L(); ++k) {
+    std::copy(t.core[k].begin(), t.core[k].end(), cores_out + off);
+    off += (int64_t)t.core[k].size();
+  }
+  return RTT_OK;
+}
+
 rtt_status check_handle(const rtt_s* h) {
   if (!h) return fail(RTT_E_ARG, "null RTT handle");
   return RTT_OK;
@@ -647,15 +696,7 @@ rtt_status rtt_tfim_create(int32_t Lx, int32_t Ly, int32_t periodic, double J, d
   *out = nullptr;
   if (Lx < 1 || Ly < 1 || (long)Lx * Ly > 1024) return fail(RTT_E_ARG, "rtt_tfim_create: bad lattice %dx%d", Lx, Ly);
   if (!isfinite(J) || !isfinite(h)) return fail(RTT_E_ARG, "rtt_tfim_create: J and h must be finite");
-  std::vector<int2> b;
-  for (int y = 0; y < Ly; ++y)
-    for (int x = 0; x < Lx; ++x) {
-      const int i = y * Lx + x;
-      if (x + 1 < Lx) b.push_back(make_int2(i, y * Lx + x + 1));
-      else if (periodic && Lx >= 3) b.push_back(make_int2(i, y * Lx));
-      if (y + 1 < Ly) b.push_back(make_int2(i, (y + 1) * Lx + x));
-      else if (periodic && Ly >= 3) b.push_back(make_int2(i, x));
-    }
+  const std::vector<int2> b = tfim_bond_list(Lx, Ly, periodic);
   rtt_ham_s* H = new rtt_ham_s;
   H->Lx = Lx; H->Ly = Ly; H->periodic = periodic; H->J = J; H->h = h; H->nb = (int)b.size();
   rtt_status st = upload((void**)&H->d_bonds, b.data(), b.size() * sizeof(int2));
@@ -808,6 +849,44 @@ rtt_status rtt_mixed_estimators(int32_t M, const rtt_t* targets, rtt_ham_t ham, 
     HIPX(hipGetLastError());
   }
   return RTT_OK;
+}
+
+rtt_status rtt_tt_round(int32_t n_cores, const int32_t* bond, const double* cores, int32_t chi_max,
+                        double rel_tol, int32_t* bond_out, double* cores_out, int64_t cap, int64_t* n_out) {
+  g_err.clear();
+  if (chi_max < 1 || !(rel_tol >= 0.0)) return fail(RTT_E_ARG, "rtt_tt_round: chi_max %d, rel_tol %g", chi_max, rel_tol);
+  rtt_tt::Train t;
+  rtt_status st = read_train("rtt_tt_round", n_cores, bond, cores, t);
+  if (st != RTT_OK) return st;
+  rtt_tt::round_train(t, chi_max, rel_tol);
+  return write_train("rtt_tt_round", t, bond_out, cores_out, cap, n_out);
+}
+
+rtt_status rtt_tfim_power_step(int32_t n_spins, int32_t n_cores, const int32_t* pi, const int32_t* bond,
+                               const double* cores, int32_t Lx, int32_t Ly, int32_t periodic, double J, double h,
+                               double tau, int32_t chi_max, double rel_tol, int32_t* bond_out, double* cores_out,
+                               int64_t cap, int64_t* n_out) {
+  g_err.clear();
+  if (Lx < 1 || Ly < 1 || Lx * Ly != n_spins)
+    return fail(RTT_E_ARG, "rtt_tfim_power_step: lattice %dx%d for %d spins", Lx, Ly, n_spins);
+  if (!isfinite(J) || !isfinite(h) || !isfinite(tau)) return fail(RTT_E_ARG, "rtt_tfim_power_step: non-finite J, h or tau");
+  if (chi_max < 1 || !(rel_tol >= 0.0)) return fail(RTT_E_ARG, "rtt_tfim_power_step: chi_max %d, rel_tol %g", chi_max, rel_tol);
+  if (!pi) return fail(RTT_E_ARG, "rtt_tfim_power_step: pi is null");
+  std::vector<int> p(pi, pi + std::max(n_cores, 0));
+  std::vector<int> seen(std::max(n_spins, 0), 0);
+  for (int k = 0; k < n_cores; ++k) {
+    if (p[k] < 0 || p[k] >= n_spins) return fail(RTT_E_ARG, "rtt_tfim_power_step: pi[%d] = %d", k, p[k]);
+    seen[p[k]] = 1;
+  }
+  for (int j = 0; j < n_spins; ++j)
+    if (!seen[j]) return fail(RTT_E_ARG, "rtt_tfim_power_step: spin %d is read by no position", j);
+  rtt_tt::Train t;
+  rtt_status st = read_train("rtt_tfim_power_step", n_cores, bond, cores, t);
+  if (st != RTT_OK) return st;
+  std::vector<std::pair<int, int>> bonds;
+  for (const int2& b : tfim_bond_list(Lx, Ly, periodic)) bonds.push_back({b.x, b.y});
+  const rtt_tt::Train out = rtt_tt::tfim_power_step(t, p, n_spins, bonds, J, h, tau, chi_max, rel_tol);
+  return write_train("rtt_tfim_power_step", out, bond_out, cores_out, cap, n_out);
 }
 
 rtt_status rtt_energy_reduce(int32_t n, const double* x, double* out, void* stream) {

@@ -1,0 +1,304 @@
+// Host tensor-train algebra for the replica-space power method (FP64).
+//
+// A train of L cores; core k is [2][a_k][a_{k+1}] row-major (a_0 = a_L = 1).
+//   * Pauli strings in replica space act as rank-1 operators: X swaps the two
+//     slices of a core, Z changes the sign of slice 1 (Sec. 2.2.3: X on a
+//     spin acts on every replica, Z on one replica of the spin's choice).
+//   * The sum of two trains has block-diagonal interior cores.
+//   * Rounding (compression): right-to-left orthogonalisation by Householder
+//     QR, then left-to-right truncated SVDs (one-sided Jacobi), keeping at
+//     most chi_max singular values and none below rel_tol times the largest.
+//   * A power step of the TFIM (Sec. 3.1): phi - tau H-bar phi, the terms of
+//     H-bar phi summed two by two with a rounding after each sum.
+#pragma once
+#include <math.h>
+
+#include <algorithm>
+#include <vector>
+
+namespace rtt_tt {
+
+struct Train {
+  std::vector<int> bond;                 // L + 1
+  std::vector<std::vector<double>> core;  // L cores, [2][a][b]
+  int L() const { return (int)core.size(); }
+  double& at(int k, int s, int i, int j) { return core[k][((size_t)s * bond[k] + i) * bond[k + 1] + j]; }
+  double at(int k, int s, int i, int j) const { return core[k][((size_t)s * bond[k] + i) * bond[k + 1] + j]; }
+};
+
+// column-major dense matrix
+struct Mat {
+  int m = 0, n = 0;
+  std::vector<double> v;
+  Mat() = default;
+  Mat(int m_, int n_) : m(m_), n(n_), v((size_t)m_ * n_, 0.0) {}
+  double& operator()(int i, int j) { return v[(size_t)j * m + i]; }
+  double operator()(int i, int j) const { return v[(size_t)j * m + i]; }
+};
+
+// Householder QR of A (m x n): Q (m x r) with orthonormal columns, R (r x n),
+// r = min(m, n), A = Q R.
+inline void qr(const Mat& A, Mat& Q, Mat& R) {
+  const int m = A.m, n = A.n, r = std::min(m, n);
+  Mat W = A;
+  std::vector<std::vector<double>> vs;
+  std::vector<double> betas;
+  for (int k = 0; k < r; ++k) {
+    double nrm = 0.0;
+    for (int i = k; i < m; ++i) nrm += W(i, k) * W(i, k);
+    nrm = sqrt(nrm);
+    std::vector<double> v(m - k, 0.0);
+    double beta = 0.0;
+    if (nrm > 0.0) {
+      const double alpha = W(k, k) >= 0.0 ? -nrm : nrm;
+      for (int i = k; i < m; ++i) v[i - k] = W(i, k);
+      v[0] -= alpha;
+      double vv = 0.0;
+      for (double x : v) vv += x * x;
+      beta = vv > 0.0 ? 2.0 / vv : 0.0;
+      for (int j = k; j < n; ++j) {
+        double d = 0.0;
+        for (int i = k; i < m; ++i) d += v[i - k] * W(i, j);
+        d *= beta;
+        for (int i = k; i < m; ++i) W(i, j) -= d * v[i - k];
+      }
+    }
+    vs.push_back(v);
+    betas.push_back(beta);
+  }
+  R = Mat(r, n);
+  for (int i = 0; i < r; ++i)
+    for (int j = i; j < n; ++j) R(i, j) = W(i, j);
+  Q = Mat(m, r);
+  for (int j = 0; j < r; ++j) Q(j, j) = 1.0;
+  for (int k = r - 1; k >= 0; --k) {  // Q = H_0 ... H_{r-1} applied to the first r unit columns
+    const std::vector<double>& v = vs[k];
+    for (int j = 0; j < r; ++j) {
+      double d = 0.0;
+      for (int i = k; i < m; ++i) d += v[i - k] * Q(i, j);
+      d *= betas[k];
+      for (int i = k; i < m; ++i) Q(i, j) -= d * v[i - k];
+    }
+  }
+}
+
+// Thin SVD A = U diag(S) V^T by one-sided Jacobi rotations (Hestenes), for
+// m >= n; singular values in decreasing order.
+inline void svd_tall(const Mat& A, Mat& U, std::vector<double>& S, Mat& V) {
+  const int m = A.m, n = A.n;
+  Mat W = A;
+  V = Mat(n, n);
+  for (int i = 0; i < n; ++i) V(i, i) = 1.0;
+  for (int sweep = 0; sweep < 80; ++sweep) {
+    double off = 0.0;
+    for (int p = 0; p < n - 1; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        double a = 0.0, b = 0.0, g = 0.0;
+        for (int i = 0; i < m; ++i) {
+          a += W(i, p) * W(i, p);
+          b += W(i, q) * W(i, q);
+          g += W(i, p) * W(i, q);
+        }
+        if (g == 0.0) continue;
+        const double rel = fabs(g) / sqrt(a * b);
+        off = std::max(off, rel);
+        if (rel < 1e-15) continue;
+        const double zeta = (b - a) / (2.0 * g);
+        const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+        for (int i = 0; i < m; ++i) {
+          const double wp = W(i, p), wq = W(i, q);
+          W(i, p) = c * wp - s * wq;
+          W(i, q) = s * wp + c * wq;
+        }
+        for (int i = 0; i < n; ++i) {
+          const double vp = V(i, p), vq = V(i, q);
+          V(i, p) = c * vp - s * vq;
+          V(i, q) = s * vp + c * vq;
+        }
+      }
+    if (off < 1e-15) break;
+  }
+  std::vector<double> nrm(n);
+  for (int j = 0; j < n; ++j) {
+    double d = 0.0;
+    for (int i = 0; i < m; ++i) d += W(i, j) * W(i, j);
+    nrm[j] = sqrt(d);
+  }
+  std::vector<int> ord(n);
+  for (int j = 0; j < n; ++j) ord[j] = j;
+  std::sort(ord.begin(), ord.end(), [&](int x, int y) { return nrm[x] > nrm[y]; });
+  U = Mat(m, n);
+  S.assign(n, 0.0);
+  Mat Vs(n, n);
+  for (int jj = 0; jj < n; ++jj) {
+    const int j = ord[jj];
+    S[jj] = nrm[j];
+    for (int i = 0; i < m; ++i) U(i, jj) = nrm[j] > 0.0 ? W(i, j) / nrm[j] : 0.0;
+    for (int i = 0; i < n; ++i) Vs(i, jj) = V(i, j);
+  }
+  V = Vs;
+}
+
+// thin SVD of any shape
+inline void svd(const Mat& A, Mat& U, std::vector<double>& S, Mat& V) {
+  if (A.m >= A.n) { svd_tall(A, U, S, V); return; }
+  Mat At(A.n, A.m);
+  for (int i = 0; i < A.m; ++i)
+    for (int j = 0; j < A.n; ++j) At(j, i) = A(i, j);
+  svd_tall(At, V, S, U);  // A^T = V S U^T
+}
+
+inline void round_train(Train& t, int chi_max, double rel_tol) {
+  const int L = t.L();
+  // right-to-left: core k becomes right-orthonormal, R moves left
+  for (int k = L - 1; k > 0; --k) {
+    const int a = t.bond[k], b = t.bond[k + 1];
+    Mat Mt(2 * b, a);  // M^T, M[a][(s, b)]
+    for (int s = 0; s < 2; ++s)
+      for (int i = 0; i < a; ++i)
+        for (int j = 0; j < b; ++j) Mt(s * b + j, i) = t.at(k, s, i, j);
+    Mat Q, R;
+    qr(Mt, Q, R);  // M = R^T Q^T
+    const int r = Q.n;
+    std::vector<double> nc((size_t)2 * r * b);
+    for (int s = 0; s < 2; ++s)
+      for (int i = 0; i < r; ++i)
+        for (int j = 0; j < b; ++j) nc[((size_t)s * r + i) * b + j] = Q(s * b + j, i);
+    const int x = t.bond[k - 1];
+    std::vector<double> pc((size_t)2 * x * r, 0.0);  // A_{k-1}[s] R^T
+    for (int s = 0; s < 2; ++s)
+      for (int i = 0; i < x; ++i)
+        for (int j = 0; j < r; ++j) {
+          double d = 0.0;
+          for (int l = 0; l < a; ++l) d += t.at(k - 1, s, i, l) * R(j, l);
+          pc[((size_t)s * x + i) * r + j] = d;
+        }
+    t.core[k] = nc;
+    t.core[k - 1] = pc;
+    t.bond[k] = r;
+  }
+  // left-to-right: truncated SVD, S V^T moves right
+  for (int k = 0; k < L - 1; ++k) {
+    const int a = t.bond[k], b = t.bond[k + 1];
+    Mat M(2 * a, b);  // M[(a, s)][b]
+    for (int s = 0; s < 2; ++s)
+      for (int i = 0; i < a; ++i)
+        for (int j = 0; j < b; ++j) M(i * 2 + s, j) = t.at(k, s, i, j);
+    Mat U, V;
+    std::vector<double> S;
+    svd(M, U, S, V);
+    int keep = 1;
+    if (S[0] > 0.0) {
+      keep = 0;
+      for (double x : S)
+        if (x > rel_tol * S[0]) ++keep;
+      keep = std::max(1, std::min(chi_max, keep));
+    }
+    std::vector<double> nc((size_t)2 * a * keep);
+    for (int s = 0; s < 2; ++s)
+      for (int i = 0; i < a; ++i)
+        for (int j = 0; j < keep; ++j) nc[((size_t)s * a + i) * keep + j] = U(i * 2 + s, j);
+    const int y = t.bond[k + 2];
+    std::vector<double> next((size_t)2 * keep * y, 0.0);  // (S V^T) A_{k+1}[s]
+    for (int s = 0; s < 2; ++s)
+      for (int i = 0; i < keep; ++i)
+        for (int j = 0; j < y; ++j) {
+          double d = 0.0;
+          for (int l = 0; l < b; ++l) d += S[i] * V(l, i) * t.at(k + 1, s, l, j);
+          next[((size_t)s * keep + i) * y + j] = d;
+        }
+    t.core[k] = nc;
+    t.core[k + 1] = next;
+    t.bond[k + 1] = keep;
+  }
+}
+
+inline Train add(const Train& A, const Train& B) {
+  const int L = A.L();
+  Train C;
+  C.bond.assign(L + 1, 0);
+  C.core.resize(L);
+  C.bond[0] = 1;
+  C.bond[L] = 1;
+  for (int k = 1; k < L; ++k) C.bond[k] = A.bond[k] + B.bond[k];
+  if (L == 1) {
+    C.core[0] = A.core[0];
+    for (size_t i = 0; i < C.core[0].size(); ++i) C.core[0][i] += B.core[0][i];
+    return C;
+  }
+  for (int k = 0; k < L; ++k) {
+    const int a = C.bond[k], b = C.bond[k + 1];
+    C.core[k].assign((size_t)2 * a * b, 0.0);
+    const int ra = (k == 0) ? 0 : A.bond[k], cb = (k == L - 1) ? 0 : A.bond[k + 1];
+    for (int s = 0; s < 2; ++s) {
+      for (int i = 0; i < A.bond[k]; ++i)
+        for (int j = 0; j < A.bond[k + 1]; ++j) C.core[k][((size_t)s * a + i) * b + j] = A.at(k, s, i, j);
+      for (int i = 0; i < B.bond[k]; ++i)
+        for (int j = 0; j < B.bond[k + 1]; ++j)
+          C.core[k][((size_t)s * a + (ra + i)) * b + (cb + j)] = B.at(k, s, i, j);
+    }
+  }
+  return C;
+}
+
+inline void scale(Train& t, double c) {
+  for (double& x : t.core[0]) x *= c;
+}
+
+inline void apply_x(Train& t, const std::vector<int>& pi, int j) {
+  for (int k = 0; k < t.L(); ++k)
+    if (pi[k] == j) {
+      const size_t h = t.core[k].size() / 2;
+      std::swap_ranges(t.core[k].begin(), t.core[k].begin() + h, t.core[k].begin() + h);
+    }
+}
+
+inline void apply_z(Train& t, const std::vector<int>& pi, int i) {
+  for (int k = 0; k < t.L(); ++k)
+    if (pi[k] == i) {
+      const size_t h = t.core[k].size() / 2;
+      for (size_t e = h; e < t.core[k].size(); ++e) t.core[k][e] = -t.core[k][e];
+      return;
+    }
+}
+
+// phi - tau H-bar phi for H-bar = J sum_bonds Zbar_i Zbar_j - h sum_j Xbar_j
+inline Train tfim_power_step(const Train& phi, const std::vector<int>& pi, int N,
+                             const std::vector<std::pair<int, int>>& bonds, double J, double h, double tau,
+                             int chi_max, double rel_tol) {
+  std::vector<Train> terms;
+  for (const auto& b : bonds) {
+    Train t = phi;
+    apply_z(t, pi, b.first);
+    apply_z(t, pi, b.second);
+    scale(t, J);
+    terms.push_back(std::move(t));
+  }
+  for (int j = 0; j < N; ++j) {
+    Train t = phi;
+    apply_x(t, pi, j);
+    scale(t, -h);
+    terms.push_back(std::move(t));
+  }
+  while (terms.size() > 1) {
+    std::vector<Train> nxt;
+    for (size_t t = 0; t < terms.size(); t += 2) {
+      if (t + 1 < terms.size()) {
+        Train s = add(terms[t], terms[t + 1]);
+        round_train(s, chi_max, rel_tol);
+        nxt.push_back(std::move(s));
+      } else {
+        nxt.push_back(std::move(terms[t]));
+      }
+    }
+    terms.swap(nxt);
+  }
+  Train hp = terms[0];
+  scale(hp, -tau);
+  Train out = add(phi, hp);
+  round_train(out, chi_max, rel_tol);
+  return out;
+}
+
+}  // namespace rtt_tt

@@ -102,6 +102,49 @@ def rtt_energy_reduce(x, out):
     check(lib().rtt_energy_reduce(x.numel(), _ptr(x), _ptr(out), _stream()))
 
 
+def _flat_cores(cores):
+    bond = np.asarray([cores[0].shape[1]] + [c.shape[2] for c in cores], dtype=np.int32)
+    flat = np.concatenate([np.ascontiguousarray(c, dtype=np.float64).ravel() for c in cores])
+    return bond, flat
+
+
+def _split_flat(bond, flat):
+    out, off = [], 0
+    for k in range(len(bond) - 1):
+        a, b = int(bond[k]), int(bond[k + 1])
+        out.append(flat[off:off + 2 * a * b].reshape(2, a, b).copy())
+        off += 2 * a * b
+    return out
+
+
+def rtt_tt_round(cores, chi_max, rel_tol=1e-14):
+    """Host FP64 tensor-train rounding; cores: list of (2, a, b) arrays."""
+    bond, flat = _flat_cores(cores)
+    L = len(cores)
+    bout = np.zeros(L + 1, dtype=np.int32)
+    cap = 2 * sum(int(min(bond[k], chi_max)) * int(min(bond[k + 1], chi_max)) for k in range(L)) + 2 * L
+    out = np.zeros(cap)
+    n = C.c_int64()
+    check(lib().rtt_tt_round(L, bond.ctypes.data, flat.ctypes.data, chi_max, rel_tol, bout.ctypes.data,
+                             out.ctypes.data, cap, C.byref(n)))
+    return _split_flat(bout, out[:n.value])
+
+
+def rtt_tfim_power_step(n_spins, pi, cores, Lx, Ly, J, h, tau, chi_max, rel_tol=1e-14, periodic=1):
+    """One replica-space TFIM power step on the host; returns the new cores."""
+    bond, flat = _flat_cores(cores)
+    pi = np.ascontiguousarray(pi, dtype=np.int32)
+    L = len(cores)
+    bout = np.zeros(L + 1, dtype=np.int32)
+    cap = 2 * L * chi_max * chi_max
+    out = np.zeros(cap)
+    n = C.c_int64()
+    check(lib().rtt_tfim_power_step(n_spins, L, pi.ctypes.data, bond.ctypes.data, flat.ctypes.data, Lx, Ly,
+                                    periodic, J, h, tau, chi_max, rel_tol, bout.ctypes.data, out.ctypes.data,
+                                    cap, C.byref(n)))
+    return _split_flat(bout, out[:n.value])
+
+
 def rtt_mixed_estimators(targets, ham, spins, logabs_a, sign_a, ratio, mixed, status=None):
     """targets: list of RTT handles; ratio, mixed: float64 [M][W] device tensors."""
     M = len(targets)
