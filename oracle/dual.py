@@ -46,14 +46,14 @@ def mixed_estimators(state_a, state_b, pi, spins, bonds, J: float, h: float):
     return pb / pa, hpsi_b / pa
 
 
-def exact_matrices(states, pi, Lx: int, Ly: int, J: float, h: float):
+def exact_matrices(states, pi, Lx: int, Ly: int, J: float, h: float, periodic=True):
     """H~ and S~ of a list of states by enumeration of all 2^N configurations
     with the sparse Hamiltonian (another route than mixed_estimators), plus
     the norms Z_a."""
     N = Lx * Ly
     S = all_configs(N)
     psi = [state_amplitudes(st, pi, S) for st in states]
-    H = sparse_hamiltonian(Lx, Ly, J, h)
+    H = sparse_hamiltonian(Lx, Ly, J, h, periodic)
     M = len(states)
     Z = np.array([p @ p for p in psi])
     Ht = np.empty((M, M))
