@@ -226,6 +226,48 @@ rtt_status rtt_tfim_power_step(int32_t n_spins, int32_t n_cores, const int32_t* 
                                int64_t* n_out);
 
 /*
+ * A sum of Pauli strings applied to a train (Sec. 2.2.3 replica-space
+ * operators, Sec. 3.1 power method, Sec. 4.1.3 operators routed to one part
+ * of the path): returns round(alpha phi + beta sum_t coeffs[t] O_t phi).
+ *   ops     host uint8[n_terms][n_cores]: the string O_t per train position,
+ *           0 = identity, 1 = X (slices swapped), 2 = Z (slice 1 negated),
+ *           3 = X Z (slice 1 negated, then slices swapped)
+ *   coeffs  host double[n_terms]
+ * The terms are summed two by two in index order with a rounding (chi_sum,
+ * rel_tol) after each sum; the result is scaled by beta, alpha phi is added
+ * when alpha != 0, and the whole is rounded to (chi_max, rel_tol).  Rounding
+ * the partial sums to the final rank discards most of a power step; a
+ * chi_sum of a few times chi_max keeps it.  alpha = 1,
+ * beta = -tau with the strings of a replica Hamiltonian is one power step
+ * phi - tau H-bar phi; alpha = 0, beta = 1 applies an operator.
+ * Host FP64, synchronous; outputs as rtt_tt_round.  Errors: RTT_E_ARG for
+ * n_terms < 1, chi_sum < 1, an op above 3, non-finite coefficients, alpha
+ * or beta, and
+ * the train errors of rtt_tt_round.
+ */
+rtt_status rtt_pauli_apply(int32_t n_cores, const int32_t* bond, const double* cores,
+                           int32_t n_terms, const double* coeffs, const uint8_t* ops,
+                           double alpha, double beta, int32_t chi_max, int32_t chi_sum,
+                           double rel_tol, int32_t* bond_out, double* cores_out, int64_t cap,
+                           int64_t* n_out);
+
+/*
+ * A linear combination of trains on one path, compressed (the final
+ * compression of the physical-space combination sum_a c_a psi^a, Sec. 4.3,
+ * and of stochastic Gram-Schmidt, Sec. 3.3): round(sum_m coeffs[m] phi_m).
+ *   bonds   host int32[n_trains][n_cores+1], each with bond[0] = bond[L] = 1
+ *   cores   host array of n_trains pointers, each to a train in rtt_create layout
+ * The trains are summed two by two in index order with a rounding (chi_max,
+ * rel_tol) after each sum, then rounded once more.  Host FP64, synchronous;
+ * outputs as rtt_tt_round.  Errors: RTT_E_ARG for n_trains < 1, non-finite
+ * coefficients and the train errors of rtt_tt_round.
+ */
+rtt_status rtt_tt_combine(int32_t n_trains, int32_t n_cores, const int32_t* bonds,
+                          const double* const* cores, const double* coeffs, int32_t chi_max,
+                          double rel_tol, int32_t* bond_out, double* cores_out, int64_t cap,
+                          int64_t* n_out);
+
+/*
  * Compensated (Neumaier) FP64 reduction of x[n] (device): out[0] = sum x,
  * out[1] = sum x^2, out[2] = number of finite entries summed (device
  * double[3]).  Non-finite entries are skipped and not counted.

@@ -34,6 +34,10 @@ SIGNATURES = {
     "rtt_energy_reduce": (C.c_int, [C.c_int32, P, P, P]),
     "rtt_mixed_estimators": (C.c_int, [C.c_int32, P, P, C.c_int32, P, P, P, P, P, P, P]),
     "rtt_tt_round": (C.c_int, [C.c_int32, P, P, C.c_int32, C.c_double, P, P, C.c_int64, C.POINTER(C.c_int64)]),
+    "rtt_pauli_apply": (C.c_int, [C.c_int32, P, P, C.c_int32, P, P, C.c_double, C.c_double, C.c_int32,
+                                  C.c_int32, C.c_double, P, P, C.c_int64, C.POINTER(C.c_int64)]),
+    "rtt_tt_combine": (C.c_int, [C.c_int32, C.c_int32, P, P, P, C.c_int32, C.c_double, P, P, C.c_int64,
+                                 C.POINTER(C.c_int64)]),
     "rtt_tfim_power_step": (C.c_int, [C.c_int32, C.c_int32, P, P, P, C.c_int32, C.c_int32, C.c_int32,
                                       C.c_double, C.c_double, C.c_double, C.c_int32, C.c_double, P, P,
                                       C.c_int64, C.POINTER(C.c_int64)]),

@@ -14,7 +14,7 @@ FLAGS = [
     # packed FP32 instructions stay off: the compiler must not form them
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"),
-    "-Wno-unused-result",
+    "-Wno-unused-result", "-pthread",
 ]
 
 

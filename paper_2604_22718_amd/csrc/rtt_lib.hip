@@ -889,6 +889,43 @@ rtt_status rtt_tfim_power_step(int32_t n_spins, int32_t n_cores, const int32_t* 
   return write_train("rtt_tfim_power_step", out, bond_out, cores_out, cap, n_out);
 }
 
+rtt_status rtt_pauli_apply(int32_t n_cores, const int32_t* bond, const double* cores, int32_t n_terms,
+                           const double* coeffs, const uint8_t* ops, double alpha, double beta, int32_t chi_max,
+                           int32_t chi_sum, double rel_tol, int32_t* bond_out, double* cores_out, int64_t cap, int64_t* n_out) {
+  g_err.clear();
+  if (n_terms < 1 || !coeffs || !ops) return fail(RTT_E_ARG, "rtt_pauli_apply: no terms or null pointer");
+  if (!isfinite(alpha) || !isfinite(beta)) return fail(RTT_E_ARG, "rtt_pauli_apply: non-finite alpha or beta");
+  if (chi_max < 1 || chi_sum < 1 || !(rel_tol >= 0.0))
+    return fail(RTT_E_ARG, "rtt_pauli_apply: chi_max %d, chi_sum %d, rel_tol %g", chi_max, chi_sum, rel_tol);
+  for (int t = 0; t < n_terms; ++t)
+    if (!isfinite(coeffs[t])) return fail(RTT_E_ARG, "rtt_pauli_apply: coeffs[%d] is not finite", t);
+  rtt_tt::Train t;
+  rtt_status st = read_train("rtt_pauli_apply", n_cores, bond, cores, t);
+  if (st != RTT_OK) return st;
+  for (int64_t e = 0; e < (int64_t)n_terms * n_cores; ++e)
+    if (ops[e] > 3)
+      return fail(RTT_E_ARG, "rtt_pauli_apply: ops[%lld][%lld] = %d (0..3)", (long long)(e / n_cores),
+                  (long long)(e % n_cores), ops[e]);
+  const rtt_tt::Train out = rtt_tt::pauli_apply(t, n_terms, coeffs, ops, alpha, beta, chi_max, chi_sum, rel_tol);
+  return write_train("rtt_pauli_apply", out, bond_out, cores_out, cap, n_out);
+}
+
+rtt_status rtt_tt_combine(int32_t n_trains, int32_t n_cores, const int32_t* bonds, const double* const* cores,
+                          const double* coeffs, int32_t chi_max, double rel_tol, int32_t* bond_out,
+                          double* cores_out, int64_t cap, int64_t* n_out) {
+  g_err.clear();
+  if (n_trains < 1 || !bonds || !cores || !coeffs) return fail(RTT_E_ARG, "rtt_tt_combine: no trains or null pointer");
+  if (chi_max < 1 || !(rel_tol >= 0.0)) return fail(RTT_E_ARG, "rtt_tt_combine: chi_max %d, rel_tol %g", chi_max, rel_tol);
+  std::vector<rtt_tt::Train> trains(n_trains);
+  for (int m = 0; m < n_trains; ++m) {
+    if (!isfinite(coeffs[m])) return fail(RTT_E_ARG, "rtt_tt_combine: coeffs[%d] is not finite", m);
+    rtt_status st = read_train("rtt_tt_combine", n_cores, bonds + (size_t)m * (n_cores + 1), cores[m], trains[m]);
+    if (st != RTT_OK) return st;
+  }
+  const rtt_tt::Train out = rtt_tt::combine(std::move(trains), coeffs, chi_max, rel_tol);
+  return write_train("rtt_tt_combine", out, bond_out, cores_out, cap, n_out);
+}
+
 rtt_status rtt_energy_reduce(int32_t n, const double* x, double* out, void* stream) {
   g_err.clear();
   if (n < 0 || (n > 0 && !x) || !out) return fail(RTT_E_ARG, "rtt_energy_reduce: bad argument");

@@ -12,8 +12,10 @@
 //     H-bar phi summed two by two with a rounding after each sum.
 #pragma once
 #include <math.h>
+#include <stdint.h>
 
 #include <algorithm>
+#include <thread>
 #include <vector>
 
 namespace rtt_tt {
@@ -264,6 +266,80 @@ inline void apply_z(Train& t, const std::vector<int>& pi, int i) {
 }
 
 // phi - tau H-bar phi for H-bar = J sum_bonds Zbar_i Zbar_j - h sum_j Xbar_j
+// One Pauli string on the train: per position 0 = identity, 1 = X (slices
+// swapped), 2 = Z (slice 1 negated), 3 = X Z (slice 1 negated, then swapped).
+inline void apply_ops(Train& t, const uint8_t* ops) {
+  for (int k = 0; k < t.L(); ++k) {
+    if (ops[k] == 0) continue;
+    const size_t n = t.core[k].size() / 2;
+    double* c = t.core[k].data();
+    if (ops[k] & 2)
+      for (size_t e = 0; e < n; ++e) c[n + e] = -c[n + e];
+    if (ops[k] & 1)
+      for (size_t e = 0; e < n; ++e) std::swap(c[e], c[n + e]);
+  }
+}
+
+// Sum of trains, two by two in order, each partial sum rounded.
+// The sums of one level are independent: they run on up to 16 host threads.
+inline Train pairwise_sum(std::vector<Train> terms, int chi_max, double rel_tol) {
+  const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  while (terms.size() > 1) {
+    const size_t pairs = terms.size() / 2;
+    std::vector<Train> nxt((terms.size() + 1) / 2);
+    auto work = [&](size_t p0, size_t p1) {
+      for (size_t p = p0; p < p1; ++p) {
+        nxt[p] = add(terms[2 * p], terms[2 * p + 1]);
+        round_train(nxt[p], chi_max, rel_tol);
+      }
+    };
+    const size_t nt = std::min<size_t>(hw, pairs);
+    if (nt <= 1) {
+      work(0, pairs);
+    } else {
+      std::vector<std::thread> th;
+      for (size_t w = 0; w < nt; ++w) th.emplace_back(work, pairs * w / nt, pairs * (w + 1) / nt);
+      for (auto& t : th) t.join();
+    }
+    if (terms.size() % 2) nxt.back() = std::move(terms.back());
+    terms.swap(nxt);
+  }
+  return std::move(terms[0]);
+}
+
+// alpha phi + beta sum_t c_t O_t phi: partial sums of the terms rounded to
+// chi_sum, the result to chi_max.  With alpha = 1, beta = -tau and the
+// strings of a replica-space Hamiltonian this is one power step; with
+// alpha = 0, beta = 1 it applies an operator (a sum of strings) to phi.
+inline Train pauli_apply(const Train& phi, int n_terms, const double* coeff, const uint8_t* ops, double alpha,
+                         double beta, int chi_max, int chi_sum, double rel_tol) {
+  std::vector<Train> terms;
+  terms.reserve(n_terms);
+  for (int t = 0; t < n_terms; ++t) {
+    Train x = phi;
+    apply_ops(x, ops + (size_t)t * phi.L());
+    scale(x, coeff[t]);
+    terms.push_back(std::move(x));
+  }
+  Train s = pairwise_sum(std::move(terms), chi_sum, rel_tol);
+  scale(s, beta);
+  if (alpha != 0.0) {
+    Train a = phi;
+    scale(a, alpha);
+    s = add(a, s);
+  }
+  round_train(s, chi_max, rel_tol);
+  return s;
+}
+
+// sum_m c_m phi_m: partial sums rounded to chi_max, the result once more.
+inline Train combine(std::vector<Train> trains, const double* coeff, int chi_max, double rel_tol) {
+  for (size_t m = 0; m < trains.size(); ++m) scale(trains[m], coeff[m]);
+  Train s = pairwise_sum(std::move(trains), chi_max, rel_tol);
+  round_train(s, chi_max, rel_tol);
+  return s;
+}
+
 inline Train tfim_power_step(const Train& phi, const std::vector<int>& pi, int N,
                              const std::vector<std::pair<int, int>>& bonds, double J, double h, double tau,
                              int chi_max, double rel_tol) {
@@ -281,20 +357,7 @@ inline Train tfim_power_step(const Train& phi, const std::vector<int>& pi, int N
     scale(t, -h);
     terms.push_back(std::move(t));
   }
-  while (terms.size() > 1) {
-    std::vector<Train> nxt;
-    for (size_t t = 0; t < terms.size(); t += 2) {
-      if (t + 1 < terms.size()) {
-        Train s = add(terms[t], terms[t + 1]);
-        round_train(s, chi_max, rel_tol);
-        nxt.push_back(std::move(s));
-      } else {
-        nxt.push_back(std::move(terms[t]));
-      }
-    }
-    terms.swap(nxt);
-  }
-  Train hp = terms[0];
+  Train hp = pairwise_sum(std::move(terms), chi_max, rel_tol);
   scale(hp, -tau);
   Train out = add(phi, hp);
   round_train(out, chi_max, rel_tol);

@@ -1,0 +1,155 @@
+"""The paper's two optimisation routes on the four-part path, driven through
+the library: the replica-space power method (Sec. 3.1 with the replica
+Hamiltonians of Sec. 4.2) run by rtt_pauli_apply on the host, energies by
+GPU Markov chains (Sec. 3.3), and one physical-space step (Sec. 3.3 dual
+Monte Carlo with the operators of Sec. 4.3): states O-bar_a phi compressed,
+re-orthogonalised against the first, the matrices H~ and S~ from one GPU
+chain per state, the lowest generalised eigenpair, and the combination
+compressed back into one train.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import lattice
+from . import rtt as R
+from . import workloads as wl
+
+
+def normalise(cores):
+    """Scale a train so that its last core has unit Frobenius norm (after a
+    left-to-right rounding the norm of the whole train sits there)."""
+    out = [np.array(c, copy=True) for c in cores]
+    out[-1] /= np.linalg.norm(out[-1])
+    return out
+
+
+def constant_train(L):
+    """phi^(0) = 1: every replica index has amplitude one (bond 1)."""
+    return [np.ones((2, 1, 1)) for _ in range(L)]
+
+
+def power_method(Lx, Ly, kind, h, tau, steps, chi, chi_sum=None, alpha=0.0, J=1.0, periodic=False, phi=None,
+                 callback=None):
+    """phi^(P) = (1 - tau H-bar)^P phi^(0) with a compression after every
+    step; H-bar is H-bar_H, H-bar_HV or H-bar_HVDD' on the H+V+D+D' path.
+    Returns (pi, cores)."""
+    pi = lattice.path(Lx, Ly)
+    coeffs, ops = lattice.replica_hamiltonian(Lx, Ly, kind, h, alpha=alpha, J=J, periodic=periodic)
+    phi = constant_train(len(pi)) if phi is None else phi
+    for p in range(steps):
+        phi = normalise(R.rtt_pauli_apply(phi, coeffs, ops, 1.0, -tau, chi, chi_sum))
+        if callback is not None:
+            callback(p, phi)
+    return pi, phi
+
+
+def _walkers(W, N, seed):
+    return R.spins_to_device(wl.pack_spins(wl.random_spins(W, N, seed)))
+
+
+def _blocked_sigma(series, blocks=20):
+    """Error bar of the mean of a correlated series by block averages."""
+    x = np.asarray(series, dtype=np.float64)
+    nb = min(blocks, len(x))
+    if nb < 2:
+        return float("nan")
+    m = np.array([b.mean() for b in np.array_split(x, nb)])
+    return float(m.std(ddof=1) / np.sqrt(nb))
+
+
+def vmc_energy(psi, ham, walkers, burn, sweeps, seed, rng_stream=0):
+    """<H> under |psi|^2 from one GPU chain of ``walkers`` walkers: burn-in,
+    then E_loc after every sweep.  Returns mean, sigma (block averages over
+    sweeps), variance of E_loc and the V-score N var / E^2."""
+    N = psi.N
+    spins = _walkers(walkers, N, seed)
+    psi.sweep(spins, seed=seed, rng_stream=rng_stream, sweep0=0, n_sweeps=burn)
+    means = torch.empty(sweeps, dtype=torch.float64, device=spins.device)
+    squares = torch.empty(sweeps, dtype=torch.float64, device=spins.device)
+    for t in range(sweeps):
+        psi.sweep(spins, seed=seed, rng_stream=rng_stream, sweep0=burn + t, n_sweeps=1)
+        e = psi.local_energy(spins, ham)
+        means[t] = e.mean()
+        squares[t] = (e * e).mean()
+    means, squares = means.cpu().numpy(), squares.cpu().numpy()
+    mean = float(means.mean())
+    var = float(squares.mean() - mean * mean)
+    return {"mean": mean, "sigma": _blocked_sigma(means), "var": var, "v_score": N * var / (mean * mean)}
+
+
+def dual_matrices(states, ham, walkers, burn, sweeps, seed):
+    """H~_ab and S~_ab (Sec. 3.3): for each a, one GPU chain on |psi^a|^2 and
+    the overlap and mixed-energy estimators against every state after each
+    sweep.  Returns H~, S~ and their block-average error bars."""
+    M, N = len(states), states[0].N
+    Ht, St = np.zeros((M, M)), np.zeros((M, M))
+    sH, sS = np.zeros((M, M)), np.zeros((M, M))
+    for a in range(M):
+        spins = _walkers(walkers, N, seed + a)
+        la = torch.empty(walkers, dtype=torch.float64, device=spins.device)
+        sg = torch.empty(walkers, dtype=torch.int8, device=spins.device)
+        states[a].sweep(spins, seed=seed, rng_stream=a, sweep0=0, n_sweeps=burn, logabs=la, sign=sg)
+        o_rows, e_rows = [], []
+        for t in range(sweeps):
+            states[a].sweep(spins, seed=seed, rng_stream=a, sweep0=burn + t, n_sweeps=1, logabs=la, sign=sg)
+            ratio, mixed, st = R.mixed_estimators(states, ham, spins, la, sg)
+            o_rows.append(ratio.mean(dim=1))
+            e_rows.append(mixed.mean(dim=1))
+        O = torch.stack(o_rows).cpu().numpy()
+        E = torch.stack(e_rows).cpu().numpy()
+        St[a], Ht[a] = O.mean(axis=0), E.mean(axis=0)
+        sS[a] = [_blocked_sigma(O[:, b]) for b in range(M)]
+        sH[a] = [_blocked_sigma(E[:, b]) for b in range(M)]
+    return Ht, St, sH, sS
+
+
+def lowest_eigenpair(Ht, St):
+    """Lowest real eigenvalue of H~ c = lambda S~ c and its vector, scaled so
+    that c^T S~ c = 1 (with c[0] >= 0)."""
+    w, v = np.linalg.eig(np.linalg.solve(St, Ht))
+    ok = np.isfinite(w) & (np.abs(w.imag) <= 1e-9 * np.maximum(1.0, np.abs(w.real)))
+    if not ok.any():
+        raise RuntimeError("no real eigenvalue in the generalised problem")
+    i = np.flatnonzero(ok)[np.argmin(w.real[ok])]
+    c = v[:, i].real
+    n = c @ St @ c
+    c = c / np.sqrt(abs(n)) if n != 0 else c
+    return float(w.real[i]), (c if c[0] >= 0 else -c)
+
+
+def physical_space_step(pi, phi, Lx, Ly, operators, chi, ham, walkers, burn, sweeps, seed, chi_sum=None,
+                        periodic=False, orthogonalise=True, dtype="f32"):
+    """One physical-space optimisation step (Sec. 3.3, Sec. 4.3): states
+    psi^a = C O-bar_a phi for the named operators (each compressed to chi),
+    re-orthogonalised against psi^1 with a GPU overlap estimate, dual Monte
+    Carlo H~ and S~, the lowest generalised eigenpair, and the combination
+    sum_a c_a psi^a compressed to chi.  Returns (new cores, info)."""
+    N = Lx * Ly
+    trains = []
+    for name in operators:
+        if name == "I":
+            trains.append(normalise(phi))
+            continue
+        c, o = lattice.operator(Lx, Ly, name, periodic)
+        trains.append(normalise(R.rtt_pauli_apply(phi, c, o, 0.0, 1.0, chi, chi_sum)))
+    gs = np.zeros(len(trains))
+    if orthogonalise and len(trains) > 1:
+        first = R.RTT.create(N, pi, trains[0], dtype)
+        others = [R.RTT.create(N, pi, t, dtype) for t in trains[1:]]
+        _, St, _, _ = dual_matrices([first] + others, ham, walkers, burn, sweeps, seed + 1000)
+        for m in range(1, len(trains)):
+            gs[m] = St[0, m]
+            trains[m] = normalise(R.rtt_tt_combine([trains[m], trains[0]], [1.0, -gs[m]], chi))
+        for x in [first] + others:
+            x.close()
+    states = [R.RTT.create(N, pi, t, dtype) for t in trains]
+    Ht, St, sH, sS = dual_matrices(states, ham, walkers, burn, sweeps, seed)
+    lam, c = lowest_eigenpair(Ht, St)
+    new = normalise(R.rtt_tt_combine(trains, c, chi))
+    for x in states:
+        x.close()
+    return new, {"lambda": lam, "coeffs": c.tolist(), "H_tilde": Ht.tolist(), "S_tilde": St.tolist(),
+                 "sigma_H": sH.tolist(), "sigma_S": sS.tolist(), "gram_schmidt": gs.tolist(),
+                 "trains": trains}

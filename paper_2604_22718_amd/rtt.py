@@ -117,6 +117,14 @@ def _split_flat(bond, flat):
     return out
 
 
+def _out_cap(bond, chi_max, mult):
+    """Doubles that bound the output train: bond k is at most chi_max, at most
+    mult times the input bond, and at most 2^min(k, L-k)."""
+    L = len(bond) - 1
+    b = [min(int(chi_max), int(mult) * int(bond[k]), 1 << min(k, L - k, 40)) for k in range(L + 1)]
+    return 2 * sum(b[k] * b[k + 1] for k in range(L))
+
+
 def rtt_tt_round(cores, chi_max, rel_tol=1e-14):
     """Host FP64 tensor-train rounding; cores: list of (2, a, b) arrays."""
     bond, flat = _flat_cores(cores)
@@ -136,12 +144,52 @@ def rtt_tfim_power_step(n_spins, pi, cores, Lx, Ly, J, h, tau, chi_max, rel_tol=
     pi = np.ascontiguousarray(pi, dtype=np.int32)
     L = len(cores)
     bout = np.zeros(L + 1, dtype=np.int32)
-    cap = 2 * L * chi_max * chi_max
+    cap = _out_cap(bond, chi_max, Lx * Ly * 3 + 1)
     out = np.zeros(cap)
     n = C.c_int64()
     check(lib().rtt_tfim_power_step(n_spins, L, pi.ctypes.data, bond.ctypes.data, flat.ctypes.data, Lx, Ly,
                                     periodic, J, h, tau, chi_max, rel_tol, bout.ctypes.data, out.ctypes.data,
                                     cap, C.byref(n)))
+    return _split_flat(bout, out[:n.value])
+
+
+def rtt_pauli_apply(cores, coeffs, ops, alpha, beta, chi_max, chi_sum=None, rel_tol=1e-14):
+    """round(alpha phi + beta sum_t coeffs[t] O_t phi) on the host; ops is a
+    (n_terms, L) uint8 table (0 I, 1 X, 2 Z, 3 XZ); partial sums rounded to
+    chi_sum (default chi_max).  Returns the new cores."""
+    chi_sum = chi_max if chi_sum is None else chi_sum
+    bond, flat = _flat_cores(cores)
+    L = len(cores)
+    coeffs = np.ascontiguousarray(coeffs, dtype=np.float64)
+    ops = np.ascontiguousarray(ops, dtype=np.uint8)
+    if ops.ndim != 2 or ops.shape != (len(coeffs), L):
+        raise ValueError(f"ops must be ({len(coeffs)}, {L}), got {ops.shape}")
+    bout = np.zeros(L + 1, dtype=np.int32)
+    cap = _out_cap(bond, chi_max, len(coeffs) + 1)
+    out = np.zeros(cap)
+    n = C.c_int64()
+    check(lib().rtt_pauli_apply(L, bond.ctypes.data, flat.ctypes.data, len(coeffs), coeffs.ctypes.data,
+                                ops.ctypes.data, alpha, beta, chi_max, chi_sum, rel_tol, bout.ctypes.data,
+                                out.ctypes.data, cap, C.byref(n)))
+    return _split_flat(bout, out[:n.value])
+
+
+def rtt_tt_combine(trains, coeffs, chi_max, rel_tol=1e-14):
+    """round(sum_m coeffs[m] phi_m) on the host for trains on one path."""
+    coeffs = np.ascontiguousarray(coeffs, dtype=np.float64)
+    L = len(trains[0])
+    if len(coeffs) != len(trains) or any(len(t) != L for t in trains):
+        raise ValueError("one coefficient per train, all trains of the same length")
+    flats = [_flat_cores(t) for t in trains]
+    bonds = np.ascontiguousarray(np.stack([b for b, _ in flats]), dtype=np.int32)
+    ptrs = (C.c_void_p * len(trains))(*[f.ctypes.data for _, f in flats])
+    bmax = bonds.max(axis=0)
+    bout = np.zeros(L + 1, dtype=np.int32)
+    cap = _out_cap(bmax, chi_max, len(trains))
+    out = np.zeros(cap)
+    n = C.c_int64()
+    check(lib().rtt_tt_combine(len(trains), L, bonds.ctypes.data, C.cast(ptrs, C.c_void_p), coeffs.ctypes.data,
+                               chi_max, rel_tol, bout.ctypes.data, out.ctypes.data, cap, C.byref(n)))
     return _split_flat(bout, out[:n.value])
 
 
