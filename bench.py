@@ -447,6 +447,46 @@ def run_dual(steps=5, warmup=1):
     return out
 
 
+def run_paper_pipeline(L=10, steps=120, phys_steps=2):
+    """The paper's chi = 2 pipeline on an L x L open lattice, h = 3 (the
+    setting of its physical-space table): H+V+D+D' path, replica-space power
+    method with H-bar_HV (tau = 0.1, host rounding, partial sums at rank 8)
+    from the constant train, then physical-space steps with I, O_X,
+    O_ZZ,HV, O_ZZ,DD'.  Energies from GPU chains (FP32, 4096 walkers)."""
+    import time
+
+    import torch
+
+    from paper_2604_22718_amd import pipeline
+    from paper_2604_22718_amd import rtt as R
+    N, hx = L * L, 3.0
+    ham = R.TFIM(L, L, 1.0, hx, periodic=False)
+    t0 = time.perf_counter()
+    pi, phi = pipeline.power_method(L, L, "HV", hx, 0.1, steps, chi=2, chi_sum=8, periodic=False)
+    host_ms = (time.perf_counter() - t0) * 1e3 / steps
+
+    def energy(cores, seed):
+        psi = R.RTT.create(N, pi, cores, "f32")
+        r = pipeline.vmc_energy(psi, ham, 4096, 50, 200, seed=seed)
+        psi.close()
+        return {"E_per_site": r["mean"] / N, "sigma_per_site": r["sigma"] / N, "v_score": r["v_score"]}
+
+    out = {"workload": f"tfim{L}x{L}_open_h3_path_HVDDp_chi2", "power_steps": steps,
+           "power_step_host_ms": host_ms, "replica_HV": energy(phi, 1200), "physical": []}
+    for it in range(phys_steps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        phi, info = pipeline.physical_space_step(pi, phi, L, L, ["I", "X", "ZZ_HV", "ZZ_DD'"], 2, ham, 4096, 300,
+                                                 200, seed=1300 + 10 * it, chi_sum=8, periodic=False)
+        torch.cuda.synchronize()
+        out["physical"].append({"lambda_per_site": info["lambda"] / N, "coeffs": info["coeffs"],
+                                "step_s": time.perf_counter() - t, **energy(phi, 1400 + it)})
+    out["paper_table_context"] = {"replica_HV_only": {"E_per_site": -3.163, "v_score": 0.005},
+                                  "with_ZZ_DDp": {"E_per_site": -3.1682, "v_score": 0.0013}}
+    ham.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -460,6 +500,8 @@ def main():
     ap.add_argument("--no-wide", action="store_true", help="skip the 10x10 chi=128 BF16 wide-bond line")
     ap.add_argument("--huge", action="store_true", help="also time the 16x16 chi=256 4-term FP8 workload (slow)")
     ap.add_argument("--no-dual", action="store_true", help="skip the dual Monte Carlo line")
+    ap.add_argument("--paper-pipeline", type=int, default=0, metavar="STEPS",
+                    help="also run the chi=2 10x10 power method for STEPS steps plus two physical-space steps")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only copy this many MiB device-to-device 3 times (counter calibration) and exit")
     a = ap.parse_args()
@@ -490,6 +532,8 @@ def main():
             res["wide_bond"].append(run_wide("tfim16x16_R2_chi256_W16384_T4", n_eval=1))
     if not a.no_dual:
         res["dual_mc"] = run_dual()
+    if a.paper_pipeline:
+        res["paper_pipeline"] = run_paper_pipeline(steps=a.paper_pipeline)
     if a.batched:
         res["batched"] = run_batched(a.batched)
     if a.learned:
