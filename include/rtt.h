@@ -75,6 +75,11 @@ int32_t rtt_abi_version(void);
  *   dtype    rtt_dtype
  * The library quantises the cores, packs them into matrix-core operand
  * layouts padded to a power-of-two bond, and builds its contraction schedule.
+ * When every bond is at most 4 (the paper's chi = 2 states), evaluation and
+ * sampling take vector-ALU kernels on C x C slices instead (C = 2 or 4, FP32
+ * arithmetic on the same quantised values); the environment variable
+ * RTT_NARROW=0 at creation keeps such a train on the matrix-core kernels.
+ * The batched entry points always use the matrix-core kernels.
  * RTT_E_UNSUPPORTED if the working set of one walker exceeds on-chip memory.
  */
 rtt_status rtt_create(int32_t n_spins, int32_t n_cores, const int32_t* pi,
@@ -92,9 +97,10 @@ rtt_status rtt_lincomb(int32_t n_terms, const rtt_t* terms, const double* coeffs
 
 rtt_status rtt_destroy(rtt_t h);
 
-/* info (host int32[9]): N, L, padded bond, dtype, n_terms, words per walker,
+/* info (host int32[10]): N, L, padded bond, dtype, n_terms, words per walker,
    cut bond of the flip-ratio schedule, rows per walker and row group, row
-   groups. */
+   groups, and the width C of the narrow-bond path (0 when the matrix-core
+   kernels run; see rtt_create). */
 rtt_status rtt_info(rtt_t h, int32_t* info);
 
 /*

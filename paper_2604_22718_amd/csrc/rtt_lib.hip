@@ -5,6 +5,7 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -13,6 +14,7 @@
 
 #include "../../include/rtt.h"
 #include "rtt_kernels.hpp"
+#include "rtt_narrow.hpp"
 #include "rtt_net.hpp"
 #include "rtt_tt.hpp"
 
@@ -198,6 +200,9 @@ struct rtt_s {
   int* d_order = nullptr;
   int* d_first = nullptr;
   double* d_coeffs = nullptr;
+  // narrow-bond path (every bond <= 4): C x C slices, prescaled, zero padded
+  int narrow = 0;             // C = 2 or 4, 0 when the matrix-core path runs
+  float* d_ncores = nullptr;  // [T][L][2][C][C]
   // workspace
   size_t ws_W = 0;
   float* d_u = nullptr;
@@ -274,7 +279,7 @@ rtt_status upload(void** dst, const void* src, size_t bytes) {
 void free_dev(rtt_s* h) {
   void* ptrs[] = {h->d_grp, h->d_fgs, h->d_bgs, h->d_fwd, h->d_bwd, h->d_cexp, h->d_cesum, h->d_rmask, h->d_sf, h->d_sb, h->d_fslot, h->d_bslot,
                   h->d_pi, h->d_order, h->d_first, h->d_coeffs, h->d_u, h->d_v, h->d_ue, h->d_ve,
-                  h->d_mla, h->d_msg, h->d_mel, h->d_mst};
+                  h->d_mla, h->d_msg, h->d_mel, h->d_mst, h->d_ncores};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
 }
@@ -322,6 +327,39 @@ void prescale(rtt_s* h) {
       off += n;
     }
   }
+}
+
+size_t narrow_chain_lds(const rtt_s* h) { return (size_t)((h->L + 63) / 64 + h->nw) * 64 * 8; }
+
+// Trains with every bond <= 4 also get C x C slices (C = 2 or 4) for the
+// vector-ALU kernels, the same prescaled values as the packed fragments.
+rtt_status setup_narrow(rtt_s* h) {
+  int bmax = 1;
+  for (int b : h->bond) bmax = std::max(bmax, b);
+  h->narrow = 0;
+  if (bmax > rttn::kNarrowMax || h->T > rttn::kMaxTermsN || narrow_chain_lds(h) > kLdsLimit) return RTT_OK;
+  const char* off = getenv("RTT_NARROW");
+  if (off && off[0] == '0') return RTT_OK;
+  const int C = bmax <= 2 ? 2 : 4;
+  std::vector<float> nc((size_t)h->T * h->L * 2 * C * C, 0.f);
+  for (int t = 0; t < h->T; ++t) {
+    const std::vector<double>& q = h->qcores[t];
+    size_t off = 0;
+    for (int k = 0; k < h->L; ++k) {
+      const int ra = h->bond[k], rb = h->bond[k + 1];
+      const int e = h->core_exp[(size_t)t * h->L + k];
+      float* dst = nc.data() + ((size_t)t * h->L + k) * 2 * C * C;
+      for (int sl = 0; sl < 2; ++sl)
+        for (int r = 0; r < ra; ++r)
+          for (int c = 0; c < rb; ++c)
+            dst[sl * C * C + r * C + c] = (float)ldexp(q[off + ((size_t)sl * ra + r) * rb + c], -e);
+      off += (size_t)2 * ra * rb;
+    }
+  }
+  rtt_status st = upload((void**)&h->d_ncores, nc.data(), nc.size() * 4);
+  if (st != RTT_OK) return st;
+  h->narrow = C;
+  return RTT_OK;
 }
 
 rtt_status finish_create(rtt_s* h) {
@@ -388,6 +426,7 @@ rtt_status finish_create(rtt_s* h) {
   if ((st = upload((void**)&h->d_order, h->order.data(), h->order.size() * 4)) != RTT_OK) return st;
   if ((st = upload((void**)&h->d_first, h->first.data(), h->first.size() * 4)) != RTT_OK) return st;
   if ((st = upload((void**)&h->d_coeffs, h->coeffs.data(), h->coeffs.size() * 8)) != RTT_OK) return st;
+  if ((st = setup_narrow(h)) != RTT_OK) return st;
   HIPX(hipDeviceSynchronize());
   return RTT_OK;
 }
@@ -537,6 +576,31 @@ rtt_status check_handle(const rtt_s* h) {
   return RTT_OK;
 }
 
+rttn::NarrowArgs narrow_args(const rtt_s* h, int W) {
+  rttn::NarrowArgs a{};
+  a.cores = h->d_ncores; a.cesum = h->d_cesum; a.rmask = h->d_rmask; a.pi = h->d_pi;
+  a.order = h->d_order; a.first = h->d_first; a.coeffs = h->d_coeffs;
+  a.T = h->T; a.L = h->L; a.N = h->N; a.nw = h->nw; a.LW = (h->L + 63) / 64; a.W = W;
+  return a;
+}
+
+template <int C>
+rtt_status launch_narrow_eval(const rttn::NarrowArgs& a, hipStream_t s) {
+  const int threads = std::min(1024, (a.N + 1 + 63) / 64 * 64);
+  hipLaunchKernelGGL(rttn::narrow_eval_kernel<C>, dim3(a.W), dim3(threads), (size_t)a.LW * 8, s, a);
+  HIPX(hipGetLastError());
+  return RTT_OK;
+}
+
+template <int C>
+rtt_status launch_narrow_chain(const rttn::NarrowArgs& a, size_t lds, hipStream_t s) {
+  auto kfn = rttn::narrow_chain_kernel<C>;
+  HIPX(hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(kfn, dim3((a.W + 63) / 64), dim3(64), lds, s, a);
+  HIPX(hipGetLastError());
+  return RTT_OK;
+}
+
 }  // namespace
 
 // ============================================================================
@@ -546,7 +610,7 @@ extern "C" {
 
 const char* rtt_last_error(void) { return g_err.c_str(); }
 
-int32_t rtt_abi_version(void) { return 2; }
+int32_t rtt_abi_version(void) { return 3; }
 
 rtt_status rtt_create(int32_t n_spins, int32_t n_cores, const int32_t* pi, const int32_t* bond,
                       const double* cores, int32_t dtype, rtt_t* out) {
@@ -656,7 +720,7 @@ rtt_status rtt_info(rtt_t h, int32_t* info) {
   if (!info) return fail(RTT_E_ARG, "rtt_info: info is null");
   info[0] = h->N; info[1] = h->L; info[2] = h->chi; info[3] = h->dtype;
   info[4] = h->T; info[5] = h->nw; info[6] = h->sched.cut; info[7] = h->sched.nslot;
-  info[8] = h->sched.ng;
+  info[8] = h->sched.ng; info[9] = h->narrow;
   return RTT_OK;
 }
 
@@ -723,6 +787,17 @@ rtt_status rtt_evaluate(rtt_t h, rtt_ham_t ham, int32_t W, const uint64_t* spins
   if (eloc && !ham) return fail(RTT_E_ARG, "rtt_evaluate: eloc requested without a Hamiltonian");
   if (ham && ham->Lx * ham->Ly != h->N) return fail(RTT_E_ARG, "rtt_evaluate: lattice has %d sites, RTT has %d spins", ham->Lx * ham->Ly, h->N);
   hipStream_t s = (hipStream_t)stream;
+  if (h->narrow) {
+    rttn::NarrowArgs na = narrow_args(h, W);
+    na.spins = const_cast<uint64_t*>(spins);
+    na.bonds = ham ? ham->d_bonds : nullptr;
+    na.nbonds = ham ? ham->nb : 0;
+    na.J = ham ? ham->J : 0.0;
+    na.h = ham ? ham->h : 0.0;
+    na.logabs = logabs; na.sign = sign; na.logratio = logratio; na.rsign = rsign; na.eloc = eloc;
+    na.status = status;
+    return h->narrow == 2 ? launch_narrow_eval<2>(na, s) : launch_narrow_eval<4>(na, s);
+  }
   rtt_status st = ensure_ws(h, W);
   if (st != RTT_OK) return st;
   const size_t tslice = (size_t)h->L * 2 * h->chi * h->chi * elem_bytes(h->dtype);
@@ -783,6 +858,14 @@ static rtt_status chain_common(rtt_t h, int32_t W, uint64_t* spins, double* loga
   if (W < 1) return fail(RTT_E_ARG, "W = %d < 1", W);
   if (!spins) return fail(RTT_E_ARG, "spins is null");
   if (n_sweeps < 0) return fail(RTT_E_ARG, "n_sweeps = %d < 0", n_sweeps);
+  if (h->narrow) {
+    rttn::NarrowArgs na = narrow_args(h, W);
+    na.spins = spins; na.logabs = logabs; na.sign = sign; na.accepts = accepts; na.status = status;
+    na.seed = seed; na.rstream = rstream; na.sweep0 = sweep0; na.n_sweeps = n_sweeps; na.mode = mode;
+    const size_t lds = narrow_chain_lds(h);
+    return h->narrow == 2 ? launch_narrow_chain<2>(na, lds, (hipStream_t)stream)
+                          : launch_narrow_chain<4>(na, lds, (hipStream_t)stream);
+  }
   rttk::ChainArgs ca{};
   ca.cores = h->d_fwd; ca.cores_bwd = h->d_bwd;
   ca.cesum = h->d_cesum;

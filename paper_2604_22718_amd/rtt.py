@@ -52,9 +52,9 @@ def rtt_destroy(h):
 
 
 def rtt_info(h):
-    info = np.zeros(9, dtype=np.int32)
+    info = np.zeros(10, dtype=np.int32)
     check(lib().rtt_info(h, info.ctypes.data))
-    return dict(zip(["N", "L", "chi", "dtype", "terms", "nw", "cut", "nslot", "groups"], info.tolist()))
+    return dict(zip(["N", "L", "chi", "dtype", "terms", "nw", "cut", "nslot", "groups", "narrow"], info.tolist()))
 
 
 def rtt_get_cores(h, term, size):

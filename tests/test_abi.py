@@ -32,7 +32,7 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_abi_version(lib):
-    assert lib.rtt_abi_version() == 2
+    assert lib.rtt_abi_version() == 3
 
 
 def _create(lib, N, pi, bond, cores, dtype=1):

@@ -1,0 +1,239 @@
+"""Narrow-bond kernels (every bond <= 4, as in the paper's chi = 2 states)
+through the C ABI against the FP64 oracle on the library's quantised cores:
+amplitudes, flip ratios and local energies for row widths C = 2 and C = 4,
+unread spins, linear combinations, 1024 spins (two items per thread),
+Metropolis sweeps with the oracle's Philox decisions, and agreement with the
+matrix-core kernels on the same train (RTT_NARROW=0)."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from helpers import check_ratios, device_cores
+from oracle import mcmc, rtt as orc, tfim
+from paper_2604_22718_amd import lattice
+from paper_2604_22718_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+TOL = {"f32": 1e-5, "bf16": 2e-2, "fp8": 2e-2}
+
+
+@pytest.fixture(scope="module")
+def R():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2604_22718_amd import rtt
+    return rtt
+
+
+def matrix_core(R, N, pi, cores, dtype):
+    os.environ["RTT_NARROW"] = "0"
+    try:
+        return R.RTT.create(N, pi, cores, dtype)
+    finally:
+        del os.environ["RTT_NARROW"]
+
+
+def check_eval(out, qc, pi, bits, tol, ham_args=None):
+    assert np.all(out["status"] == 0)
+    la_ref, sg_ref = orc.log_sign(orc.amplitudes(qc, pi, bits))
+    k0 = orc.condition_numbers(qc, pi, bits)
+    assert np.all(out["sign"] == sg_ref)
+    assert np.all(np.abs(out["logabs"] - la_ref) <= tol * np.maximum(1.0, k0 / 10.0))
+    kap = orc.flip_condition_numbers(qc, pi, bits)
+    st = check_ratios(out["logratio"], out["rsign"], orc.flip_ratios(qc, pi, bits), kap, tol)
+    print(st, flush=True)
+    assert st["n_bad"] == 0 and st["n_sign_bad"] == 0 and st["max_well"] <= tol
+    if ham_args is not None:
+        el = orc.local_energy(qc, pi, bits, *ham_args)
+        kmax = kap.max(axis=1)
+        assert np.all(np.abs(out["eloc"] - el) <= tol * np.maximum(1.0, np.abs(el)) * np.maximum(1.0, kmax / 10.0))
+
+
+def unread_path():
+    pi = np.array([3, 0, 0, 5, 1, 7, 3, 2, 9, 1, 4, 3, 6, 0, 8, 2, 5, 9, 11, 11], dtype=np.int32)  # 10 unread
+    bond = np.array([1, 2, 3, 4, 4, 3, 2, 4, 3, 1, 2, 4, 4, 3, 4, 2, 3, 4, 2, 2, 1])
+    return pi, bond
+
+
+CASES = [
+    # name, narrow width, dtype
+    ("hvddp_4x4_chi2", 2, "f32"),
+    ("unread_chi4", 4, "f32"),
+    ("perm_n30_chi4_bf16", 4, "bf16"),
+    ("perm_n30_chi3_fp8", 4, "fp8"),
+]
+
+
+def build_case(name):
+    if name == "hvddp_4x4_chi2":
+        Lx = Ly = 4
+        pi = lattice.path(Lx, Ly)
+        bond = wl.open_bonds(len(pi), 2)
+        return 16, pi, bond, wl.gaussian_cores(bond, 601), (Lx, Ly)
+    if name == "unread_chi4":
+        pi, bond = unread_path()
+        return 12, pi, bond, wl.gaussian_cores(bond, 602, std=0.6), (4, 3)
+    chi = 4 if "chi4" in name else 3
+    pi = wl.path_site_plus_perms(30, 2, 603)
+    bond = wl.open_bonds(60, chi)
+    cores = wl.gaussian_cores(bond, 604)
+    if "fp8" in name:
+        cores = [c * 40.0 for c in cores]
+    return 30, pi, bond, cores, (6, 5)
+
+
+@pytest.mark.parametrize("name,C,dtype", CASES, ids=[c[0] for c in CASES])
+def test_narrow_evaluate_matches_oracle(R, name, C, dtype):
+    print(f"[case] {name}", flush=True)
+    N, pi, bond, cores, (Lx, Ly) = build_case(name)
+    psi = R.RTT.create(N, pi, cores, dtype)
+    assert psi.info["narrow"] == C
+    qc = device_cores(psi, bond)
+    bits = wl.random_spins(37, N, 610)
+    ham = R.TFIM(Lx, Ly, 1.0, 3.0)
+    out = psi.evaluate(R.spins_to_device(wl.pack_spins(bits)), ham)
+    torch.cuda.synchronize()
+    out = {k: v.cpu().numpy() for k, v in out.items()}
+    check_eval(out, qc, pi, bits, TOL[dtype], (tfim.bonds(Lx, Ly), 1.0, 3.0))
+    if name == "unread_chi4":
+        assert np.all(out["logratio"][:, 10] == 0.0) and np.all(out["rsign"][:, 10] == 1)
+
+
+def test_narrow_1024_spins(R):
+    """N = 1024 needs N + 1 items per walker: the block of 1024 threads takes
+    the configuration itself in a second round."""
+    N = 1024
+    pi = np.arange(N, dtype=np.int32)
+    bond = wl.open_bonds(N, 2)
+    cores = wl.gaussian_cores(bond, 620, std=0.9)
+    psi = R.RTT.create(N, pi, cores, "f32")
+    assert psi.info["narrow"] == 2
+    qc = device_cores(psi, bond)
+    bits = wl.random_spins(3, N, 621)
+    out = psi.evaluate(R.spins_to_device(wl.pack_spins(bits)), R.TFIM(32, 32, 1.0, 3.0))
+    torch.cuda.synchronize()
+    out = {k: v.cpu().numpy() for k, v in out.items()}
+    check_eval(out, qc, pi, bits, 1e-5, (tfim.bonds(32, 32), 1.0, 3.0))
+
+
+def test_narrow_lincomb(R):
+    Lx = Ly = 3
+    N = 9
+    pi = lattice.path(Lx, Ly)
+    bond = wl.open_bonds(len(pi), 2)
+    terms = [R.RTT.create(N, pi, wl.gaussian_cores(bond, 630 + t), "f32") for t in range(3)]
+    coeffs = np.array([0.7, -1.2, 0.4])
+    psi = R.RTT.lincomb(terms, coeffs)
+    assert psi.info["narrow"] == 2
+    qcs = device_cores(psi, bond, n_terms=3)
+    bits = wl.random_spins(29, N, 631)
+    out = psi.evaluate(R.spins_to_device(wl.pack_spins(bits)), R.TFIM(Lx, Ly, 1.0, 3.0))
+    torch.cuda.synchronize()
+    out = {k: v.cpu().numpy() for k, v in out.items()}
+    la_ref, sg_ref = orc.log_sign(orc.lincomb_amplitudes(qcs, coeffs, pi, bits))
+    assert np.all(out["sign"] == sg_ref)
+    # conditioning of the sum: the direct-sum train is one RTT with the same
+    # psi, and cancellation between terms shows in its condition numbers
+    from oracle import tt
+    ds = tt.direct_sum(qcs, coeffs)
+    k0 = orc.condition_numbers(ds, pi, bits)
+    assert np.all(np.abs(out["logabs"] - la_ref) <= 1e-5 * np.maximum(1.0, k0 / 10.0))
+    kap = orc.flip_condition_numbers(ds, pi, bits)
+    st = check_ratios(out["logratio"], out["rsign"], orc.lincomb_flip_ratios(qcs, coeffs, pi, bits), kap, 1e-5)
+    print(st)
+    assert st["n_bad"] == 0 and st["n_sign_bad"] == 0
+
+
+def test_narrow_sweep_trajectory_parity(R):
+    """Same Philox words: the narrow chain makes the oracle's decisions for
+    every walker up to its first near-tie |u - r^2| < 1e-4, and counts the
+    same acceptances."""
+    Lx = Ly = 3
+    N = 9
+    pi = lattice.path(Lx, Ly)
+    bond = wl.open_bonds(len(pi), 2)
+    psi = R.RTT.create(N, pi, wl.gaussian_cores(bond, 640), "f32")
+    qc = device_cores(psi, bond)
+    W = 96
+    bits = wl.random_spins(W, N, 641)
+    spins = R.spins_to_device(wl.pack_spins(bits))
+    acc = torch.zeros(W, dtype=torch.int32, device="cuda")
+    s, tie_free, nacc = bits.copy(), np.ones(W, dtype=bool), np.zeros(W, dtype=np.int64)
+    for t in range(6):
+        psi.sweep(spins, seed=77, rng_stream=3, sweep0=t, n_sweeps=1, accepts=acc)
+        torch.cuda.synchronize()
+        s, a, margins = mcmc.metropolis(qc, pi, s, seed=77, stream=3, sweep0=t, n_sweeps=1, record=True)
+        nacc += a
+        tie_free &= np.min(np.abs(margins), axis=(0, 1)) > 1e-4
+        got = wl.unpack_spins(R.spins_to_host(spins), N)
+        assert np.array_equal(got[tie_free], s[tie_free]), f"sweep {t}"
+    assert tie_free.sum() >= W - 3
+    assert np.array_equal(acc.cpu().numpy()[tie_free], nacc[tie_free])
+    la, sg = psi.amplitudes(spins)
+    la_ref, sg_ref = orc.log_sign(orc.amplitudes(qc, pi, s))
+    assert np.all(np.abs(la.cpu().numpy()[tie_free] - la_ref[tie_free]) < 1e-5)
+
+
+def test_narrow_agrees_with_matrix_core_kernels(R):
+    """The same chi = 2 train on both paths: evaluation within FP32 rounding,
+    identical sweeps away from near-ties, multi-sweep calls equal to single
+    sweeps."""
+    Lx = Ly = 4
+    N = 16
+    pi = lattice.path(Lx, Ly)
+    bond = wl.open_bonds(len(pi), 2)
+    cores = wl.gaussian_cores(bond, 650)
+    a = R.RTT.create(N, pi, cores, "f32")
+    b = matrix_core(R, N, pi, cores, "f32")
+    assert a.info["narrow"] == 2 and b.info["narrow"] == 0
+    ham = R.TFIM(Lx, Ly, 1.0, 3.0)
+    bits = wl.random_spins(200, N, 651)
+    sp = R.spins_to_device(wl.pack_spins(bits))
+    oa, ob = a.evaluate(sp, ham), b.evaluate(sp, ham)
+    torch.cuda.synchronize()
+    # each path is within 1e-5 (widened by the condition number) of the
+    # exact value, so the two are within twice that of each other
+    qc = device_cores(a, bond)
+    k0 = orc.condition_numbers(qc, pi, bits)
+    kap = orc.flip_condition_numbers(qc, pi, bits)
+    x, y = oa["logabs"].cpu().numpy(), ob["logabs"].cpu().numpy()
+    assert np.all(np.abs(x - y) <= 2e-5 * np.maximum(1.0, k0 / 10.0))
+    x, y = oa["logratio"].cpu().numpy(), ob["logratio"].cpu().numpy()
+    assert np.all(np.abs(x - y) <= 2e-5 * np.maximum(1.0, kap / 10.0))
+    x, y = oa["eloc"].cpu().numpy(), ob["eloc"].cpu().numpy()
+    assert np.all(np.abs(x - y) <= 2e-5 * np.maximum(1.0, np.abs(y)) * np.maximum(1.0, kap.max(axis=1) / 10.0))
+    assert torch.equal(oa["sign"], ob["sign"]) and torch.equal(oa["rsign"], ob["rsign"])
+    s1, s2 = sp.clone(), sp.clone()
+    a.sweep(s1, seed=9, sweep0=0, n_sweeps=3)
+    b.sweep(s2, seed=9, sweep0=0, n_sweeps=3)
+    same = (s1 == s2).all(dim=1).float().mean().item()
+    assert same > 0.97, same
+    s3 = sp.clone()
+    for t in range(3):
+        a.sweep(s3, seed=9, sweep0=t, n_sweeps=1)
+    assert torch.equal(s1, s3)
+
+
+def test_narrow_energy_matches_exact_enumeration(R):
+    """3x3 periodic, H+V+D+D' path, chi = 2: the GPU chain's mean E_loc is
+    within 3 sigma of the exact <H> of the quantised cores."""
+    from oracle import stats
+    Lx = Ly = 3
+    N = 9
+    pi = lattice.path(Lx, Ly)
+    bond = wl.open_bonds(len(pi), 2)
+    psi = R.RTT.create(N, pi, wl.gaussian_cores(bond, 660), "f32")
+    qc = device_cores(psi, bond)
+    exact = orc.exact_energy(qc, pi, N, tfim.bonds(Lx, Ly), 1.0, 3.0)
+    ham = R.TFIM(Lx, Ly, 1.0, 3.0)
+    spins = R.spins_to_device(wl.pack_spins(wl.random_spins(512, N, 661)))
+    psi.sweep(spins, seed=662, sweep0=0, n_sweeps=30)
+    series = []
+    for t in range(200):
+        psi.sweep(spins, seed=662, sweep0=30 + t, n_sweeps=1)
+        series.append(psi.local_energy(spins, ham))
+    mean, sigma, _, _ = stats.energy_estimate(torch.stack(series).cpu().numpy())
+    print(f"narrow chain <E> {mean:.5f} +- {sigma:.5f} exact {exact:.5f}")
+    assert abs(mean - exact) < 3 * sigma
