@@ -447,6 +447,49 @@ def run_dual(steps=5, warmup=1):
     return out
 
 
+def time_narrow(N, pi, cores, ham, W=4096, reps=20):
+    """Sweep and local-energy times of a narrow-bond train (every bond <= 4)
+    with HIP events, and their algorithmic FP32 rates: an amplitude costs
+    sum_k 2 chi_k chi_{k+1} flops (row vector times the selected slice); a
+    local energy needs N + 1 of them, a sweep proposal for spin j the part
+    of the train from its first position on (the prefix is shared)."""
+    import torch
+
+    from paper_2604_22718_amd import rtt as R
+    from paper_2604_22718_amd import workloads as wl
+    psi = R.RTT.create(N, pi, cores, "f32")
+    assert psi.info["narrow"] in (2, 4), "narrow-bond path not taken"
+    bond = [1] + [c.shape[2] for c in cores]
+    per_pos = np.array([2.0 * bond[k] * bond[k + 1] for k in range(len(cores))])
+    tail = np.concatenate([np.cumsum(per_pos[::-1])[::-1], [0.0]])
+    first = {}
+    for k, j in enumerate(pi):
+        first.setdefault(int(j), k)
+    sweep_flops = W * sum(tail[f] for f in first.values())
+    le_flops = W * (len(first) + 1) * tail[0]
+    sp = R.spins_to_device(wl.pack_spins(wl.random_spins(W, N, 77)))
+    psi.sweep(sp, seed=3, n_sweeps=2)
+    psi.local_energy(sp, ham)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev[0].record()
+    for t in range(reps):
+        psi.sweep(sp, seed=3, sweep0=2 + t, n_sweeps=1)
+    ev[1].record()
+    for t in range(reps):
+        psi.local_energy(sp, ham)
+    ev[2].record()
+    torch.cuda.synchronize()
+    sweep_ms, le_ms = ev[0].elapsed_time(ev[1]) / reps, ev[1].elapsed_time(ev[2]) / reps
+    psi.close()
+    peak = 157.3
+    return {"walkers": W, "sweep_ms": sweep_ms, "local_energy_ms": le_ms,
+            "sweep": {"bound": "alu", "achieved": sweep_flops / (sweep_ms * 1e9), "peak": peak,
+                      "unit": "TFLOP/s", "frac": sweep_flops / (sweep_ms * 1e9) / peak},
+            "local_energy": {"bound": "alu", "achieved": le_flops / (le_ms * 1e9), "peak": peak,
+                             "unit": "TFLOP/s", "frac": le_flops / (le_ms * 1e9) / peak}}
+
+
 def run_paper_pipeline(L=10, steps=120, phys_steps=2):
     """The paper's chi = 2 pipeline on an L x L open lattice, h = 3 (the
     setting of its physical-space table): H+V+D+D' path, replica-space power
@@ -483,6 +526,7 @@ def run_paper_pipeline(L=10, steps=120, phys_steps=2):
                                 "step_s": time.perf_counter() - t, **energy(phi, 1400 + it)})
     out["paper_table_context"] = {"replica_HV_only": {"E_per_site": -3.163, "v_score": 0.005},
                                   "with_ZZ_DDp": {"E_per_site": -3.1682, "v_score": 0.0013}}
+    out["narrow_kernels"] = time_narrow(N, pi, phi, ham)
     ham.close()
     return out
 

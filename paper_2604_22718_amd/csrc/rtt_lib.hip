@@ -592,6 +592,45 @@ rtt_status launch_narrow_eval(const rttn::NarrowArgs& a, hipStream_t s) {
   return RTT_OK;
 }
 
+// Segmented sampling (one term, L <= 4096): G lanes per walker with
+// segments of about 32 positions, at most 64.
+size_t narrow_seg_lds(const rtt_s* h, int G) {
+  return ((size_t)h->L * 2 * h->narrow * h->narrow * 4 + 7) / 8 * 8 + (size_t)(64 / G) * h->nw * 8;
+}
+
+int narrow_seg_lanes(const rtt_s* h) {
+  if (h->T != 1 || h->L > 64 * 64) return 0;
+  int gmin = 1, gpref = 1;
+  while (gmin * 64 < h->L) gmin <<= 1;
+  while (gpref * 32 < h->L && gpref < 64) gpref <<= 1;
+  const int G = std::max(gmin, gpref);
+  return narrow_seg_lds(h, G) <= kLdsLimit ? G : 0;
+}
+
+template <int C, int G>
+rtt_status launch_seg(const rttn::NarrowArgs& a, size_t lds, hipStream_t s) {
+  auto kfn = rttn::narrow_chain_seg_kernel<C, G>;
+  HIPX(hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  constexpr int WPB = 64 / G;
+  hipLaunchKernelGGL(kfn, dim3((a.W + WPB - 1) / WPB), dim3(64), lds, s, a);
+  HIPX(hipGetLastError());
+  return RTT_OK;
+}
+
+template <int C>
+rtt_status launch_seg_g(const rttn::NarrowArgs& a, int G, size_t lds, hipStream_t s) {
+  switch (G) {
+    case 1: return launch_seg<C, 1>(a, lds, s);
+    case 2: return launch_seg<C, 2>(a, lds, s);
+    case 4: return launch_seg<C, 4>(a, lds, s);
+    case 8: return launch_seg<C, 8>(a, lds, s);
+    case 16: return launch_seg<C, 16>(a, lds, s);
+    case 32: return launch_seg<C, 32>(a, lds, s);
+    case 64: return launch_seg<C, 64>(a, lds, s);
+  }
+  return fail(RTT_E_UNSUPPORTED, "segmented sampling: %d lanes per walker", G);
+}
+
 template <int C>
 rtt_status launch_narrow_chain(const rttn::NarrowArgs& a, size_t lds, hipStream_t s) {
   auto kfn = rttn::narrow_chain_kernel<C>;
@@ -862,6 +901,12 @@ static rtt_status chain_common(rtt_t h, int32_t W, uint64_t* spins, double* loga
     rttn::NarrowArgs na = narrow_args(h, W);
     na.spins = spins; na.logabs = logabs; na.sign = sign; na.accepts = accepts; na.status = status;
     na.seed = seed; na.rstream = rstream; na.sweep0 = sweep0; na.n_sweeps = n_sweeps; na.mode = mode;
+    const int G = narrow_seg_lanes(h);
+    if (G) {
+      const size_t lds = narrow_seg_lds(h, G);
+      return h->narrow == 2 ? launch_seg_g<2>(na, G, lds, (hipStream_t)stream)
+                            : launch_seg_g<4>(na, G, lds, (hipStream_t)stream);
+    }
     const size_t lds = narrow_chain_lds(h);
     return h->narrow == 2 ? launch_narrow_chain<2>(na, lds, (hipStream_t)stream)
                           : launch_narrow_chain<4>(na, lds, (hipStream_t)stream);

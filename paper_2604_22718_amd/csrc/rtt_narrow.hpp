@@ -316,3 +316,200 @@ __global__ void __launch_bounds__(64) narrow_chain_kernel(NarrowArgs a) {
 }
 
 }  // namespace rttn
+
+namespace rttn {
+
+// ---------------------------------------------------------------- segmented sampling
+// G lanes per walker (64 / G walkers per wave), lane g owning the positions
+// [g S, g S + S) (S = ceil(L / G) <= 64, their slice bits in one register
+// word) and the C x C product of its segment for the current configuration.
+// A proposal recomputes only the segments that hold a replica of the spin;
+// the G products meet in a log2(G)-level tree across lanes, and the walker's
+// lane g = 0 decides.  One term only.  Dynamic LDS: the C x C slices of all
+// positions (shared by the block's walkers), then the spin words.
+template <int C>
+struct SegMat {
+  float m[C * C];
+  int e;
+};
+
+template <int C>
+__device__ __forceinline__ void seg_renorm(SegMat<C>& M) {
+  float mx = 0.f;
+#pragma unroll
+  for (int i = 0; i < C * C; ++i) mx = fmaxf(mx, fabsf(M.m[i]));
+  if (mx == 0.f || !isfinite(mx)) return;
+  const int e = __builtin_amdgcn_frexp_expf(mx);
+#pragma unroll
+  for (int i = 0; i < C * C; ++i) M.m[i] = ldexpf(M.m[i], -e);
+  M.e += e;
+}
+
+// product of positions [k0, k0 + len) with slice bits `bits` (bit i for k0 + i)
+template <int C>
+__device__ __forceinline__ SegMat<C> seg_product(const float* __restrict__ lc, int k0, int len, uint64_t bits) {
+  SegMat<C> M;
+#pragma unroll
+  for (int i = 0; i < C * C; ++i) M.m[i] = (i / C == i % C) ? 1.f : 0.f;
+  M.e = 0;
+  for (int i = 0; i < len; ++i) {
+    const float* A = lc + (size_t)(k0 + i) * (2 * C * C);
+    float a0[C * C], a1[C * C];
+#pragma unroll
+    for (int q = 0; q < C * C; ++q) { a0[q] = A[q]; a1[q] = A[C * C + q]; }
+    const bool b = (bits >> i) & 1ull;
+#pragma unroll
+    for (int r = 0; r < C; ++r) {
+      float y0[C], y1[C];
+#pragma unroll
+      for (int c = 0; c < C; ++c) { y0[c] = 0.f; y1[c] = 0.f; }
+#pragma unroll
+      for (int q = 0; q < C; ++q)
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          y0[c] = fmaf(M.m[r * C + q], a0[q * C + c], y0[c]);
+          y1[c] = fmaf(M.m[r * C + q], a1[q * C + c], y1[c]);
+        }
+#pragma unroll
+      for (int c = 0; c < C; ++c) M.m[r * C + c] = b ? y1[c] : y0[c];
+    }
+    if ((i & 3) == 3) seg_renorm<C>(M);
+  }
+  seg_renorm<C>(M);
+  return M;
+}
+
+// bits [k0, k0 + len) of a position mask stored as 64-bit words
+__device__ __forceinline__ uint64_t mask_bits(const uint64_t* words, int LW, int k0, int len) {
+  if (len <= 0) return 0ull;
+  const int w0 = k0 >> 6, sh = k0 & 63;
+  uint64_t v = words[w0] >> sh;
+  if (sh && w0 + 1 < LW) v |= words[w0 + 1] << (64 - sh);
+  return len >= 64 ? v : (v & ((1ull << len) - 1ull));
+}
+
+// product of the walker's G segment matrices (lanes g = 0..G-1, in order);
+// the result is valid in lane g = 0
+template <int C, int G>
+__device__ __forceinline__ SegMat<C> seg_tree(SegMat<C> M, int g) {
+#pragma unroll
+  for (int d = 1; d < G; d <<= 1) {
+    SegMat<C> O;
+#pragma unroll
+    for (int i = 0; i < C * C; ++i) O.m[i] = __shfl_down(M.m[i], d, 64);
+    O.e = __shfl_down(M.e, d, 64);
+    if ((g & (2 * d - 1)) == 0) {
+      SegMat<C> P;
+#pragma unroll
+      for (int r = 0; r < C; ++r)
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+          float acc = 0.f;
+#pragma unroll
+          for (int q = 0; q < C; ++q) acc = fmaf(M.m[r * C + q], O.m[q * C + c], acc);
+          P.m[r * C + c] = acc;
+        }
+      P.e = M.e + O.e;
+      seg_renorm<C>(P);
+      M = P;
+    }
+  }
+  return M;
+}
+
+template <int C, int G>
+__global__ void __launch_bounds__(64) narrow_chain_seg_kernel(NarrowArgs a) {
+  extern __shared__ uint64_t shs[];
+  float* lc = reinterpret_cast<float*>(shs);                          // [L][2][C][C]
+  const size_t cw = ((size_t)a.L * 2 * C * C * 4 + 7) / 8;
+  uint64_t* sp = shs + cw;                                            // [64 / G][nw]
+  constexpr int WPB = 64 / G;
+  const int lane = threadIdx.x;
+  const int ws = lane / G, g = lane % G;
+  const int w = blockIdx.x * WPB + ws;
+  const bool live = w < a.W;
+  for (int i = lane; i < a.L * 2 * C * C; i += 64) lc[i] = a.cores[i];
+  for (int i = lane; i < WPB * a.nw; i += 64) {
+    const int wv = blockIdx.x * WPB + i / a.nw;
+    sp[i] = wv < a.W ? a.spins[(size_t)wv * a.nw + i % a.nw] : 0ull;
+  }
+  __syncthreads();
+  const int S = (a.L + G - 1) / G;
+  const int k0 = g * S;
+  const int len = max(0, min(a.L, k0 + S) - k0);
+  uint64_t* spw = sp + ws * a.nw;
+  uint64_t pw = 0;
+  for (int i = 0; i < len; ++i) {
+    const int q = a.pi[k0 + i];
+    pw |= ((spw[q >> 6] >> (q & 63)) & 1ull) << i;
+  }
+  SegMat<C> M = seg_product<C>(lc, k0, len, pw);
+  const int esum = a.cesum[a.L];
+  const double LN2 = 0.69314718055994530942;
+  auto amp = [&](const SegMat<C>& T0, double& lab_out, int& sg_out) {  // lane g = 0
+    const double m = (double)T0.m[0] * a.coeffs[0];
+    if (m == 0.0 || !isfinite(m)) { lab_out = m == 0.0 ? -INFINITY : NAN; sg_out = 0; return; }
+    lab_out = log(fabs(m)) + (double)(T0.e + esum) * LN2;
+    sg_out = m > 0 ? 1 : -1;
+  };
+  double lab = NAN;
+  int sgn = 0, stat = 0;
+  {
+    const SegMat<C> T0 = seg_tree<C, G>(M, g);
+    amp(T0, lab, sgn);
+    stat = (sgn != 0 && isfinite(lab)) ? 0 : -5;
+  }
+  uint32_t nacc = 0;
+  if (a.mode == 1) {
+    for (int ts = 0; ts < a.n_sweeps; ++ts) {
+      const uint64_t sweep = a.sweep0 + (uint64_t)ts;
+      for (int qi = 0; qi < a.N; ++qi) {
+        const int j = a.order[qi];
+        if (a.first[j] < 0) {  // spin read by no position: ratio 1, always accepted
+          if (g == 0 && live && stat == 0) {
+            nacc += 1;
+            spw[j >> 6] ^= 1ull << (j & 63);
+          }
+          continue;
+        }
+        const uint64_t fm = mask_bits(a.rmask + (size_t)j * a.LW, a.LW, k0, len);
+        SegMat<C> Mp = M;
+        if (fm) Mp = seg_product<C>(lc, k0, len, pw ^ fm);
+        const SegMat<C> T1 = seg_tree<C, G>(Mp, g);
+        int accept = 0;
+        if (g == 0 && live && stat == 0) {
+          double lnew; int snew;
+          amp(T1, lnew, snew);
+          if (isnan(lnew)) {
+            stat = -5;
+          } else if (snew != 0) {
+            const double u = rttk::philox_uniform(a.seed, a.rstream, (uint64_t)w, sweep, (uint64_t)j);
+            if (u < exp(2.0 * (lnew - lab))) {
+              accept = 1;
+              lab = lnew;
+              sgn = snew;
+              nacc += 1;
+              spw[j >> 6] ^= 1ull << (j & 63);
+            }
+          }
+        }
+        accept = __shfl(accept, ws * G, 64);
+        if (accept && fm) {
+          M = Mp;
+          pw ^= fm;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  if (!live || g != 0) return;
+  if (a.mode == 1)
+    for (int wd = 0; wd < a.nw; ++wd) a.spins[(size_t)w * a.nw + wd] = spw[wd];
+  const bool ok = stat == 0;
+  if (a.logabs) a.logabs[w] = ok ? lab : NAN;
+  if (a.sign) a.sign[w] = ok ? (int8_t)sgn : 0;
+  if (a.accepts && a.mode == 1) a.accepts[w] += nacc;
+  if (a.status) a.status[w] = stat;
+}
+
+}  // namespace rttn

@@ -146,25 +146,57 @@ def test_narrow_lincomb(R):
     assert st["n_bad"] == 0 and st["n_sign_bad"] == 0
 
 
-def test_narrow_sweep_trajectory_parity(R):
-    """Same Philox words: the narrow chain makes the oracle's decisions for
-    every walker up to its first near-tie |u - r^2| < 1e-4, and counts the
-    same acceptances."""
-    Lx = Ly = 3
-    N = 9
-    pi = lattice.path(Lx, Ly)
-    bond = wl.open_bonds(len(pi), 2)
-    psi = R.RTT.create(N, pi, wl.gaussian_cores(bond, 640), "f32")
+SWEEP_CASES = [
+    # name, N, W, sweeps: the segmented kernel with 2, 1, 16 and 8 lanes per
+    # walker, and a two-term combination on the one-thread-per-walker kernel
+    ("hvddp_3x3_chi2", 9, 96, 6),
+    ("unread_chi4", 12, 64, 4),
+    ("hvddp_10x10_chi2", 100, 24, 2),
+    ("line_n256_chi4", 256, 16, 2),
+    ("lincomb2_hvddp_3x3", 9, 64, 4),
+]
+
+
+def sweep_case(R, name):
+    if name.startswith("hvddp") or name.startswith("lincomb"):
+        L = 10 if "10x10" in name else 3
+        pi = lattice.path(L, L)
+        bond = wl.open_bonds(len(pi), 2)
+        if name.startswith("lincomb"):
+            hs = [R.RTT.create(L * L, pi, wl.gaussian_cores(bond, 642 + t), "f32") for t in range(2)]
+            c = np.array([1.0, -0.6])
+            psi = R.RTT.lincomb(hs, c)
+            qcs = device_cores(psi, bond, n_terms=2)
+            return psi, pi, lambda S: orc.lincomb_amplitudes(qcs, c, pi, S)
+        psi = R.RTT.create(L * L, pi, wl.gaussian_cores(bond, 640, std=0.9), "f32")
+    elif name == "unread_chi4":
+        pi, bond = unread_path()
+        psi = R.RTT.create(12, pi, wl.gaussian_cores(bond, 641, std=0.6), "f32")
+    else:
+        pi = np.arange(256, dtype=np.int32)
+        bond = wl.open_bonds(256, 4)
+        psi = R.RTT.create(256, pi, wl.gaussian_cores(bond, 643, std=0.6), "f32")
     qc = device_cores(psi, bond)
-    W = 96
-    bits = wl.random_spins(W, N, 641)
+    return psi, pi, lambda S: orc.amplitudes(qc, pi, S)
+
+
+@pytest.mark.parametrize("name,N,W,S", SWEEP_CASES, ids=[c[0] for c in SWEEP_CASES])
+def test_narrow_sweep_trajectory_parity(R, name, N, W, S):
+    """Same Philox words: the narrow chain makes the oracle's decisions for
+    every walker up to its first near-tie |u - r^2| < 1e-4, counts the same
+    acceptances and ends on the oracle's amplitudes."""
+    print(f"[case] {name}", flush=True)
+    psi, pi, amp = sweep_case(R, name)
+    assert psi.info["narrow"] in (2, 4)
+    bits = wl.random_spins(W, N, 644)
     spins = R.spins_to_device(wl.pack_spins(bits))
     acc = torch.zeros(W, dtype=torch.int32, device="cuda")
     s, tie_free, nacc = bits.copy(), np.ones(W, dtype=bool), np.zeros(W, dtype=np.int64)
-    for t in range(6):
+    for t in range(S):
         psi.sweep(spins, seed=77, rng_stream=3, sweep0=t, n_sweeps=1, accepts=acc)
         torch.cuda.synchronize()
-        s, a, margins = mcmc.metropolis(qc, pi, s, seed=77, stream=3, sweep0=t, n_sweeps=1, record=True)
+        s, a, margins = mcmc.metropolis(None, pi, s, seed=77, stream=3, sweep0=t, n_sweeps=1, record=True,
+                                        amp_fn=amp)
         nacc += a
         tie_free &= np.min(np.abs(margins), axis=(0, 1)) > 1e-4
         got = wl.unpack_spins(R.spins_to_host(spins), N)
@@ -172,8 +204,9 @@ def test_narrow_sweep_trajectory_parity(R):
     assert tie_free.sum() >= W - 3
     assert np.array_equal(acc.cpu().numpy()[tie_free], nacc[tie_free])
     la, sg = psi.amplitudes(spins)
-    la_ref, sg_ref = orc.log_sign(orc.amplitudes(qc, pi, s))
-    assert np.all(np.abs(la.cpu().numpy()[tie_free] - la_ref[tie_free]) < 1e-5)
+    la_ref, sg_ref = orc.log_sign(amp(s))
+    assert np.all(sg.cpu().numpy()[tie_free] == sg_ref[tie_free])
+    assert np.all(np.abs(la.cpu().numpy()[tie_free] - la_ref[tie_free]) < 1e-4)
 
 
 def test_narrow_agrees_with_matrix_core_kernels(R):
