@@ -592,18 +592,24 @@ rtt_status launch_narrow_eval(const rttn::NarrowArgs& a, hipStream_t s) {
   return RTT_OK;
 }
 
-// Segmented sampling (one term, L <= 4096): G lanes per walker with
-// segments of about 32 positions, at most 64.
+// Segmented sampling (one term, L <= 4096): G lanes per walker, segments
+// of at most 64 positions.  More lanes shorten the chain of dependent
+// products per proposal but add tree levels and lanes; G is chosen so that
+// the launch holds about two waves per SIMD (8 per CU), which measured best
+// on the 400-position chi = 2 train at 4096 walkers (G = 32) and at 16384
+// (G = 8).
 size_t narrow_seg_lds(const rtt_s* h, int G) {
   return ((size_t)h->L * 2 * h->narrow * h->narrow * 4 + 7) / 8 * 8 + (size_t)(64 / G) * h->nw * 8;
 }
 
-int narrow_seg_lanes(const rtt_s* h) {
+int narrow_seg_lanes(const rtt_s* h, int W) {
   if (h->T != 1 || h->L > 64 * 64) return 0;
-  int gmin = 1, gpref = 1;
+  int gmin = 1;
   while (gmin * 64 < h->L) gmin <<= 1;
-  while (gpref * 32 < h->L && gpref < 64) gpref <<= 1;
-  const int G = std::max(gmin, gpref);
+  const long lanes = (long)device_cus() * 8 * 64;
+  int G = 1;
+  while (G < 64 && (long)W * G * 2 <= lanes) G <<= 1;
+  G = std::max(G, gmin);
   return narrow_seg_lds(h, G) <= kLdsLimit ? G : 0;
 }
 
@@ -901,7 +907,7 @@ static rtt_status chain_common(rtt_t h, int32_t W, uint64_t* spins, double* loga
     rttn::NarrowArgs na = narrow_args(h, W);
     na.spins = spins; na.logabs = logabs; na.sign = sign; na.accepts = accepts; na.status = status;
     na.seed = seed; na.rstream = rstream; na.sweep0 = sweep0; na.n_sweeps = n_sweeps; na.mode = mode;
-    const int G = narrow_seg_lanes(h);
+    const int G = narrow_seg_lanes(h, W);
     if (G) {
       const size_t lds = narrow_seg_lds(h, G);
       return h->narrow == 2 ? launch_seg_g<2>(na, G, lds, (hipStream_t)stream)

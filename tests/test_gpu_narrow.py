@@ -147,9 +147,11 @@ def test_narrow_lincomb(R):
 
 
 SWEEP_CASES = [
-    # name, N, W, sweeps: the segmented kernel with 2, 1, 16 and 8 lanes per
-    # walker, and a two-term combination on the one-thread-per-walker kernel
-    ("hvddp_3x3_chi2", 9, 96, 6),
+    # name, N, W, sweeps.  The segmented kernel takes about 2 waves per SIMD
+    # worth of lanes: 64 lanes per walker up to 1024 walkers, 32 at 4096,
+    # 8 at 16384; the two-term combination runs one thread per walker.
+    ("hvddp_3x3_chi2_W4096", 9, 4096, 4),
+    ("hvddp_3x3_chi2_W16384", 9, 16384, 3),
     ("unread_chi4", 12, 64, 4),
     ("hvddp_10x10_chi2", 100, 24, 2),
     ("line_n256_chi4", 256, 16, 2),
@@ -201,7 +203,7 @@ def test_narrow_sweep_trajectory_parity(R, name, N, W, S):
         tie_free &= np.min(np.abs(margins), axis=(0, 1)) > 1e-4
         got = wl.unpack_spins(R.spins_to_host(spins), N)
         assert np.array_equal(got[tie_free], s[tie_free]), f"sweep {t}"
-    assert tie_free.sum() >= W - 3
+    assert tie_free.sum() >= min(W - 3, 0.98 * W)
     assert np.array_equal(acc.cpu().numpy()[tie_free], nacc[tie_free])
     la, sg = psi.amplitudes(spins)
     la_ref, sg_ref = orc.log_sign(amp(s))
