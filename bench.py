@@ -114,6 +114,50 @@ def cpu_baseline(w, n_walkers, n_steps):
             "host_cpus_available": len(os.sched_getaffinity(0))}
 
 
+def cpu_baseline_rows(n_dual=16, n_narrow=256):
+    """The FP64 oracle beside two more GPU lines, on samples of their
+    workloads, single-threaded BLAS: a dual Monte Carlo step (one sweep per
+    state, then overlap and mixed-energy estimators against all three
+    states; 8x8 chi=64) and a sweep plus local energies of a chi = 2 train
+    on the 10x10 H+V+D+D' path (400 positions, the narrow-kernel shape)."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import dual, mcmc, rtt as orc, tfim
+    from paper_2604_22718_amd import lattice
+    from paper_2604_22718_amd import workloads as wl
+    out = {}
+    w = wl.MEDIUM_8x8
+    pi = w.pi()
+    a, b = w.cores(), wl.gaussian_cores(w.bond(), w.core_seed + 5)
+    states = [a, b, ([a, b], np.array([0.8, -1.1]))]
+    bonds = tfim.bonds(w.Lx, w.Ly)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        for i, st in enumerate(states):
+            amp = (lambda S, st=st: dual.state_amplitudes(st, pi, S))
+            s, _, _ = mcmc.metropolis(None, pi, w.spins(n_dual), seed=w.chain_seed, stream=100 + i, n_sweeps=1,
+                                      amp_fn=amp)
+            for st_b in states:
+                dual.mixed_estimators(st, st_b, pi, s, bonds, w.J, w.h)
+        dt = time.perf_counter() - t0
+    out["dual_mc"] = {"value": n_dual * 9 / dt, "unit": "mixed estimators/s", "cores": 1, "kind": "oracle",
+                      "sample": f"{n_dual} walkers per state, 3 states: one sweep each and 9 estimator "
+                                f"rows, 8x8 chi=64, FP64 numpy, {dt:.1f} s"}
+    L = 10
+    pi2 = lattice.path(L, L)
+    c2 = wl.gaussian_cores(wl.open_bonds(len(pi2), 2), 5)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        s, _, _ = mcmc.metropolis(c2, pi2, wl.random_spins(n_narrow, L * L, 6), seed=3, n_sweeps=1)
+        orc.local_energy(c2, pi2, s, tfim.bonds(L, L, periodic=False), 1.0, 3.0)
+        dt = time.perf_counter() - t0
+    out["narrow_chi2"] = {"value": n_narrow / dt, "unit": "local-energy evals/s (sweep + local energies)",
+                          "cores": 1, "kind": "oracle",
+                          "sample": f"{n_narrow} walkers x 1 step on the 10x10 open H+V+D+D' chi=2 train, "
+                                    f"FP64 numpy, {dt:.1f} s"}
+    return out
+
+
 def run(dtype, steps, warmup, with_cpu):
     import torch
 
@@ -585,6 +629,7 @@ def main():
     if not a.no_cpu:
         from paper_2604_22718_amd import workloads as wl
         res["cpu_baseline"] = cpu_baseline(wl.MEDIUM_8x8, 64, 8)
+        res["cpu_baseline"]["rows"] = cpu_baseline_rows()
     print(json.dumps(res), flush=True)
 
 

@@ -272,3 +272,52 @@ def test_narrow_energy_matches_exact_enumeration(R):
     mean, sigma, _, _ = stats.energy_estimate(torch.stack(series).cpu().numpy())
     print(f"narrow chain <E> {mean:.5f} +- {sigma:.5f} exact {exact:.5f}")
     assert abs(mean - exact) < 3 * sigma
+
+
+def test_narrow_full_size_sampled_walkers(R):
+    """The chi = 2 pipeline's shape in the launch configuration its timing
+    uses (10x10 open, H+V+D+D', 400 positions, 4096 walkers): evaluation and
+    one sweep of all walkers; the oracle recomputes a sample of walkers one
+    by one (same Philox words for the sweep through their walker ids)."""
+    L, N, W = 10, 100, 4096
+    pi = lattice.path(L, L)
+    bond = wl.open_bonds(len(pi), 2)
+    psi = R.RTT.create(N, pi, wl.gaussian_cores(bond, 670, std=0.9), "f32")
+    qc = device_cores(psi, bond)
+    bits = wl.random_spins(W, N, 671)
+    sp = R.spins_to_device(wl.pack_spins(bits))
+    ham = R.TFIM(L, L, 1.0, 3.0, periodic=False)
+    out = psi.evaluate(sp, ham)
+    torch.cuda.synchronize()
+    out = {k: v.cpu().numpy() for k, v in out.items()}
+    idx = np.array([0, 1, 63, 64, 2047, 4095])
+    check_eval({k: v[idx] for k, v in out.items()}, qc, pi, bits[idx], 1e-5,
+               (tfim.bonds(L, L, periodic=False), 1.0, 3.0))
+    psi.sweep(sp, seed=672, rng_stream=1, sweep0=5, n_sweeps=1)
+    torch.cuda.synchronize()
+    got = wl.unpack_spins(R.spins_to_host(sp), N)[idx]
+    ref, _, margins = mcmc.metropolis(qc, pi, bits[idx], seed=672, stream=1, sweep0=5, n_sweeps=1,
+                                      walker_ids=idx, record=True)
+    clean = np.min(np.abs(margins), axis=(0, 1)) > 1e-4
+    assert clean.sum() >= len(idx) - 1
+    assert np.array_equal(got[clean], ref[clean])
+
+
+def test_tiny_shapes_on_both_paths(R):
+    """One spin and one core, W = 1, and a three-core single-spin train, on
+    the narrow kernels and on the matrix-core kernels (RTT_NARROW=0)."""
+    for pi, bond in [([0], [1, 1]), ([0, 0, 0], [1, 3, 2, 1])]:
+        pi, bond = np.array(pi, dtype=np.int32), np.array(bond)
+        cores = wl.gaussian_cores(bond, 8)
+        for make in (lambda: R.RTT.create(1, pi, cores, "f32"), lambda: matrix_core(R, 1, pi, cores, "f32")):
+            psi = make()
+            qc = device_cores(psi, bond)
+            for bits in (np.array([[1]], dtype=np.uint8), np.array([[0], [1]], dtype=np.uint8)):
+                out = psi.evaluate(R.spins_to_device(wl.pack_spins(bits)))
+                torch.cuda.synchronize()
+                out = {k: v.cpu().numpy() for k, v in out.items()}
+                assert np.all(out["status"] == 0)
+                r_ref = orc.flip_ratios(qc, pi, bits)
+                assert np.allclose(out["rsign"] * np.exp(out["logratio"]), r_ref, rtol=1e-5)
+                la_ref, sg_ref = orc.log_sign(orc.amplitudes(qc, pi, bits))
+                assert np.all(out["sign"] == sg_ref) and np.allclose(out["logabs"], la_ref, atol=1e-5)
