@@ -114,7 +114,7 @@ def cpu_baseline(w, n_walkers, n_steps):
             "host_cpus_available": len(os.sched_getaffinity(0))}
 
 
-def cpu_baseline_rows(n_dual=16, n_narrow=256):
+def cpu_baseline_rows(n_dual=48, n_narrow=1024):
     """The FP64 oracle beside two more GPU lines, on samples of their
     workloads, single-threaded BLAS: a dual Monte Carlo step (one sweep per
     state, then overlap and mixed-energy estimators against all three
