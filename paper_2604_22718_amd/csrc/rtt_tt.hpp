@@ -28,78 +28,88 @@ struct Train {
   double at(int k, int s, int i, int j) const { return core[k][((size_t)s * bond[k] + i) * bond[k + 1] + j]; }
 };
 
-// column-major dense matrix
-struct Mat {
-  int m = 0, n = 0;
-  std::vector<double> v;
-  Mat() = default;
-  Mat(int m_, int n_) : m(m_), n(n_), v((size_t)m_ * n_, 0.0) {}
-  double& operator()(int i, int j) { return v[(size_t)j * m + i]; }
-  double operator()(int i, int j) const { return v[(size_t)j * m + i]; }
+// Scratch buffers of one thread, grown on demand and reused: rounding a long
+// train of small cores would otherwise spend its time in the allocator.
+struct Work {
+  std::vector<double> W, Q, R, V, U, Vs, S, nrm, hv, betas, a, b;
+  std::vector<int> ord;
 };
+inline Work& work() {
+  thread_local Work w;
+  return w;
+}
+inline double* grow(std::vector<double>& v, size_t n) {
+  if (v.size() < n) v.resize(n);
+  return v.data();
+}
 
-// Householder QR of A (m x n): Q (m x r) with orthonormal columns, R (r x n),
-// r = min(m, n), A = Q R.
-inline void qr(const Mat& A, Mat& Q, Mat& R) {
-  const int m = A.m, n = A.n, r = std::min(m, n);
-  Mat W = A;
-  std::vector<std::vector<double>> vs;
-  std::vector<double> betas;
+// Householder QR of the column-major m x n matrix W (overwritten):
+// Q (m x r, orthonormal columns) and R (r x n), r = min(m, n), A = Q R.
+inline void qr(int m, int n, double* W, double* Q, double* R, Work& wk) {
+  const int r = std::min(m, n);
+  double* hv = grow(wk.hv, (size_t)m * r);  // Householder vector k in column k, rows k..m-1
+  double* betas = grow(wk.betas, r);
+  auto w = [&](int i, int j) -> double& { return W[(size_t)j * m + i]; };
   for (int k = 0; k < r; ++k) {
+    double* v = hv + (size_t)k * m;
     double nrm = 0.0;
-    for (int i = k; i < m; ++i) nrm += W(i, k) * W(i, k);
+    for (int i = k; i < m; ++i) nrm += w(i, k) * w(i, k);
     nrm = sqrt(nrm);
-    std::vector<double> v(m - k, 0.0);
     double beta = 0.0;
+    for (int i = k; i < m; ++i) v[i] = 0.0;
     if (nrm > 0.0) {
-      const double alpha = W(k, k) >= 0.0 ? -nrm : nrm;
-      for (int i = k; i < m; ++i) v[i - k] = W(i, k);
-      v[0] -= alpha;
+      const double alpha = w(k, k) >= 0.0 ? -nrm : nrm;
+      for (int i = k; i < m; ++i) v[i] = w(i, k);
+      v[k] -= alpha;
       double vv = 0.0;
-      for (double x : v) vv += x * x;
+      for (int i = k; i < m; ++i) vv += v[i] * v[i];
       beta = vv > 0.0 ? 2.0 / vv : 0.0;
       for (int j = k; j < n; ++j) {
         double d = 0.0;
-        for (int i = k; i < m; ++i) d += v[i - k] * W(i, j);
+        for (int i = k; i < m; ++i) d += v[i] * w(i, j);
         d *= beta;
-        for (int i = k; i < m; ++i) W(i, j) -= d * v[i - k];
+        for (int i = k; i < m; ++i) w(i, j) -= d * v[i];
       }
     }
-    vs.push_back(v);
-    betas.push_back(beta);
+    betas[k] = beta;
   }
-  R = Mat(r, n);
-  for (int i = 0; i < r; ++i)
-    for (int j = i; j < n; ++j) R(i, j) = W(i, j);
-  Q = Mat(m, r);
-  for (int j = 0; j < r; ++j) Q(j, j) = 1.0;
+  for (int j = 0; j < n; ++j)
+    for (int i = 0; i < r; ++i) R[(size_t)j * r + i] = i <= j ? w(i, j) : 0.0;
+  for (size_t i = 0; i < (size_t)m * r; ++i) Q[i] = 0.0;
+  for (int j = 0; j < r; ++j) Q[(size_t)j * m + j] = 1.0;
   for (int k = r - 1; k >= 0; --k) {  // Q = H_0 ... H_{r-1} applied to the first r unit columns
-    const std::vector<double>& v = vs[k];
+    const double* v = hv + (size_t)k * m;
     for (int j = 0; j < r; ++j) {
+      double* q = Q + (size_t)j * m;
       double d = 0.0;
-      for (int i = k; i < m; ++i) d += v[i - k] * Q(i, j);
+      for (int i = k; i < m; ++i) d += v[i] * q[i];
       d *= betas[k];
-      for (int i = k; i < m; ++i) Q(i, j) -= d * v[i - k];
+      for (int i = k; i < m; ++i) q[i] -= d * v[i];
     }
   }
 }
 
-// Thin SVD A = U diag(S) V^T by one-sided Jacobi rotations (Hestenes), for
-// m >= n; singular values in decreasing order.
-inline void svd_tall(const Mat& A, Mat& U, std::vector<double>& S, Mat& V) {
-  const int m = A.m, n = A.n;
-  Mat W = A;
-  V = Mat(n, n);
-  for (int i = 0; i < n; ++i) V(i, i) = 1.0;
+// Thin SVD A = U diag(S) V^T of the column-major m x n matrix A (m >= n) by
+// one-sided Jacobi rotations (Hestenes); singular values decreasing.
+// U is m x n, V is n x n, both column-major.
+inline void svd_tall(int m, int n, const double* A, double* U, double* S, double* Vout, Work& wk) {
+  double* W = grow(wk.W, (size_t)m * n);
+  double* V = grow(wk.V, (size_t)n * n);
+  double* nrm = grow(wk.nrm, n);
+  std::copy(A, A + (size_t)m * n, W);
+  for (size_t i = 0; i < (size_t)n * n; ++i) V[i] = 0.0;
+  for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
   for (int sweep = 0; sweep < 80; ++sweep) {
     double off = 0.0;
     for (int p = 0; p < n - 1; ++p)
       for (int q = p + 1; q < n; ++q) {
+        double* wp = W + (size_t)p * m;
+        double* wq = W + (size_t)q * m;
         double a = 0.0, b = 0.0, g = 0.0;
         for (int i = 0; i < m; ++i) {
-          a += W(i, p) * W(i, p);
-          b += W(i, q) * W(i, q);
-          g += W(i, p) * W(i, q);
+          a += wp[i] * wp[i];
+          b += wq[i] * wq[i];
+          g += wp[i] * wq[i];
         }
         if (g == 0.0) continue;
         const double rel = fabs(g) / sqrt(a * b);
@@ -109,109 +119,110 @@ inline void svd_tall(const Mat& A, Mat& U, std::vector<double>& S, Mat& V) {
         const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
         const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
         for (int i = 0; i < m; ++i) {
-          const double wp = W(i, p), wq = W(i, q);
-          W(i, p) = c * wp - s * wq;
-          W(i, q) = s * wp + c * wq;
+          const double x = wp[i], y = wq[i];
+          wp[i] = c * x - s * y;
+          wq[i] = s * x + c * y;
         }
+        double* vp = V + (size_t)p * n;
+        double* vq = V + (size_t)q * n;
         for (int i = 0; i < n; ++i) {
-          const double vp = V(i, p), vq = V(i, q);
-          V(i, p) = c * vp - s * vq;
-          V(i, q) = s * vp + c * vq;
+          const double x = vp[i], y = vq[i];
+          vp[i] = c * x - s * y;
+          vq[i] = s * x + c * y;
         }
       }
     if (off < 1e-15) break;
   }
-  std::vector<double> nrm(n);
   for (int j = 0; j < n; ++j) {
     double d = 0.0;
-    for (int i = 0; i < m; ++i) d += W(i, j) * W(i, j);
+    for (int i = 0; i < m; ++i) d += W[(size_t)j * m + i] * W[(size_t)j * m + i];
     nrm[j] = sqrt(d);
   }
-  std::vector<int> ord(n);
-  for (int j = 0; j < n; ++j) ord[j] = j;
-  std::sort(ord.begin(), ord.end(), [&](int x, int y) { return nrm[x] > nrm[y]; });
-  U = Mat(m, n);
-  S.assign(n, 0.0);
-  Mat Vs(n, n);
+  wk.ord.resize(n);
+  for (int j = 0; j < n; ++j) wk.ord[j] = j;
+  std::sort(wk.ord.begin(), wk.ord.end(), [&](int x, int y) { return nrm[x] > nrm[y]; });
   for (int jj = 0; jj < n; ++jj) {
-    const int j = ord[jj];
+    const int j = wk.ord[jj];
     S[jj] = nrm[j];
-    for (int i = 0; i < m; ++i) U(i, jj) = nrm[j] > 0.0 ? W(i, j) / nrm[j] : 0.0;
-    for (int i = 0; i < n; ++i) Vs(i, jj) = V(i, j);
+    for (int i = 0; i < m; ++i) U[(size_t)jj * m + i] = nrm[j] > 0.0 ? W[(size_t)j * m + i] / nrm[j] : 0.0;
+    for (int i = 0; i < n; ++i) Vout[(size_t)jj * n + i] = V[(size_t)j * n + i];
   }
-  V = Vs;
 }
 
-// thin SVD of any shape
-inline void svd(const Mat& A, Mat& U, std::vector<double>& S, Mat& V) {
-  if (A.m >= A.n) { svd_tall(A, U, S, V); return; }
-  Mat At(A.n, A.m);
-  for (int i = 0; i < A.m; ++i)
-    for (int j = 0; j < A.n; ++j) At(j, i) = A(i, j);
-  svd_tall(At, V, S, U);  // A^T = V S U^T
+// thin SVD of any shape: U (m x r), S (r), V (n x r), r = min(m, n)
+inline void svd(int m, int n, const double* A, double* U, double* S, double* V, Work& wk) {
+  if (m >= n) { svd_tall(m, n, A, U, S, V, wk); return; }
+  double* At = grow(wk.a, (size_t)m * n);
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < n; ++j) At[(size_t)i * n + j] = A[(size_t)j * m + i];
+  svd_tall(n, m, At, V, S, U, wk);  // A^T = V S U^T
 }
 
 inline void round_train(Train& t, int chi_max, double rel_tol) {
   const int L = t.L();
+  Work& wk = work();
   // right-to-left: core k becomes right-orthonormal, R moves left
   for (int k = L - 1; k > 0; --k) {
     const int a = t.bond[k], b = t.bond[k + 1];
-    Mat Mt(2 * b, a);  // M^T, M[a][(s, b)]
+    const int m = 2 * b, r = std::min(m, a);
+    double* Mt = grow(wk.b, (size_t)m * a);  // M^T, M[a][(s, b)], column-major m x a
     for (int s = 0; s < 2; ++s)
       for (int i = 0; i < a; ++i)
-        for (int j = 0; j < b; ++j) Mt(s * b + j, i) = t.at(k, s, i, j);
-    Mat Q, R;
-    qr(Mt, Q, R);  // M = R^T Q^T
-    const int r = Q.n;
-    std::vector<double> nc((size_t)2 * r * b);
+        for (int j = 0; j < b; ++j) Mt[(size_t)i * m + s * b + j] = t.at(k, s, i, j);
+    double* Q = grow(wk.Q, (size_t)m * r);
+    double* R = grow(wk.R, (size_t)r * a);
+    qr(m, a, Mt, Q, R, wk);  // M = R^T Q^T
+    std::vector<double>& cur = t.core[k];
+    cur.assign((size_t)2 * r * b, 0.0);
     for (int s = 0; s < 2; ++s)
       for (int i = 0; i < r; ++i)
-        for (int j = 0; j < b; ++j) nc[((size_t)s * r + i) * b + j] = Q(s * b + j, i);
+        for (int j = 0; j < b; ++j) cur[((size_t)s * r + i) * b + j] = Q[(size_t)i * m + s * b + j];
     const int x = t.bond[k - 1];
-    std::vector<double> pc((size_t)2 * x * r, 0.0);  // A_{k-1}[s] R^T
+    double* pc = grow(wk.U, (size_t)2 * x * r);  // A_{k-1}[s] R^T
     for (int s = 0; s < 2; ++s)
       for (int i = 0; i < x; ++i)
         for (int j = 0; j < r; ++j) {
           double d = 0.0;
-          for (int l = 0; l < a; ++l) d += t.at(k - 1, s, i, l) * R(j, l);
+          for (int l = 0; l < a; ++l) d += t.at(k - 1, s, i, l) * R[(size_t)l * r + j];
           pc[((size_t)s * x + i) * r + j] = d;
         }
-    t.core[k] = nc;
-    t.core[k - 1] = pc;
+    t.core[k - 1].assign(pc, pc + (size_t)2 * x * r);
     t.bond[k] = r;
   }
   // left-to-right: truncated SVD, S V^T moves right
   for (int k = 0; k < L - 1; ++k) {
     const int a = t.bond[k], b = t.bond[k + 1];
-    Mat M(2 * a, b);  // M[(a, s)][b]
+    const int m = 2 * a, r = std::min(m, b);
+    double* M = grow(wk.b, (size_t)m * b);  // M[(a, s)][b], column-major
     for (int s = 0; s < 2; ++s)
       for (int i = 0; i < a; ++i)
-        for (int j = 0; j < b; ++j) M(i * 2 + s, j) = t.at(k, s, i, j);
-    Mat U, V;
-    std::vector<double> S;
-    svd(M, U, S, V);
+        for (int j = 0; j < b; ++j) M[(size_t)j * m + i * 2 + s] = t.at(k, s, i, j);
+    double* U = grow(wk.U, (size_t)m * r);
+    double* S = grow(wk.S, r);
+    double* V = grow(wk.Vs, (size_t)b * r);
+    svd(m, b, M, U, S, V, wk);
     int keep = 1;
     if (S[0] > 0.0) {
       keep = 0;
-      for (double x : S)
-        if (x > rel_tol * S[0]) ++keep;
+      for (int i = 0; i < r; ++i)
+        if (S[i] > rel_tol * S[0]) ++keep;
       keep = std::max(1, std::min(chi_max, keep));
     }
-    std::vector<double> nc((size_t)2 * a * keep);
-    for (int s = 0; s < 2; ++s)
-      for (int i = 0; i < a; ++i)
-        for (int j = 0; j < keep; ++j) nc[((size_t)s * a + i) * keep + j] = U(i * 2 + s, j);
     const int y = t.bond[k + 2];
-    std::vector<double> next((size_t)2 * keep * y, 0.0);  // (S V^T) A_{k+1}[s]
+    double* nx = grow(wk.R, (size_t)2 * keep * y);  // (S V^T) A_{k+1}[s]
     for (int s = 0; s < 2; ++s)
       for (int i = 0; i < keep; ++i)
         for (int j = 0; j < y; ++j) {
           double d = 0.0;
-          for (int l = 0; l < b; ++l) d += S[i] * V(l, i) * t.at(k + 1, s, l, j);
-          next[((size_t)s * keep + i) * y + j] = d;
+          for (int l = 0; l < b; ++l) d += S[i] * V[(size_t)i * b + l] * t.at(k + 1, s, l, j);
+          nx[((size_t)s * keep + i) * y + j] = d;
         }
-    t.core[k] = nc;
-    t.core[k + 1] = next;
+    std::vector<double>& cur = t.core[k];
+    cur.assign((size_t)2 * a * keep, 0.0);
+    for (int s = 0; s < 2; ++s)
+      for (int i = 0; i < a; ++i)
+        for (int j = 0; j < keep; ++j) cur[((size_t)s * a + i) * keep + j] = U[(size_t)j * m + i * 2 + s];
+    t.core[k + 1].assign(nx, nx + (size_t)2 * keep * y);
     t.bond[k + 1] = keep;
   }
 }
