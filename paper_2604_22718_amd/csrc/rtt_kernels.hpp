@@ -21,7 +21,9 @@
 namespace rttk {
 
 constexpr int kMaxTerms = 8;
-constexpr int kRenormEvery = 4;  // steps between power-of-two renormalisations
+// steps between power-of-two renormalisations: a row grows by at most chi
+// per step, so 8 steps stay below 2^64 even at chi = 256 (FP32 range 2^128)
+constexpr int kRenormEvery = 8;
 
 template <int CHI>
 struct Geo {
