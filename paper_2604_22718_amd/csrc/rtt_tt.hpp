@@ -43,10 +43,24 @@ inline double* grow(std::vector<double>& v, size_t n) {
   return v.data();
 }
 
+// frexp exponent of the largest |x_i| (0 for an all-zero array)
+inline int max_exponent(size_t n, const double* x) {
+  double mx = 0.0;
+  for (size_t i = 0; i < n; ++i) mx = std::max(mx, fabs(x[i]));
+  int e = 0;
+  if (mx > 0.0) frexp(mx, &e);
+  return e;
+}
+
 // Householder QR of the column-major m x n matrix W (overwritten):
 // Q (m x r, orthonormal columns) and R (r x n), r = min(m, n), A = Q R.
 inline void qr(int m, int n, double* W, double* Q, double* R, Work& wk) {
   const int r = std::min(m, n);
+  // exact power-of-two prescaling: the squared norms below stay finite for
+  // entries up to the top of the FP64 range (a long train's norm can reach
+  // 2^800 before it is normalised)
+  const int e = max_exponent((size_t)m * n, W);
+  for (size_t i = 0; i < (size_t)m * n; ++i) W[i] = ldexp(W[i], -e);
   double* hv = grow(wk.hv, (size_t)m * r);  // Householder vector k in column k, rows k..m-1
   double* betas = grow(wk.betas, r);
   auto w = [&](int i, int j) -> double& { return W[(size_t)j * m + i]; };
@@ -74,7 +88,7 @@ inline void qr(int m, int n, double* W, double* Q, double* R, Work& wk) {
     betas[k] = beta;
   }
   for (int j = 0; j < n; ++j)
-    for (int i = 0; i < r; ++i) R[(size_t)j * r + i] = i <= j ? w(i, j) : 0.0;
+    for (int i = 0; i < r; ++i) R[(size_t)j * r + i] = i <= j ? ldexp(w(i, j), e) : 0.0;
   for (size_t i = 0; i < (size_t)m * r; ++i) Q[i] = 0.0;
   for (int j = 0; j < r; ++j) Q[(size_t)j * m + j] = 1.0;
   for (int k = r - 1; k >= 0; --k) {  // Q = H_0 ... H_{r-1} applied to the first r unit columns
@@ -96,7 +110,8 @@ inline void svd_tall(int m, int n, const double* A, double* U, double* S, double
   double* W = grow(wk.W, (size_t)m * n);
   double* V = grow(wk.V, (size_t)n * n);
   double* nrm = grow(wk.nrm, n);
-  std::copy(A, A + (size_t)m * n, W);
+  const int e = max_exponent((size_t)m * n, A);  // exact prescaling, as in qr
+  for (size_t i = 0; i < (size_t)m * n; ++i) W[i] = ldexp(A[i], -e);
   for (size_t i = 0; i < (size_t)n * n; ++i) V[i] = 0.0;
   for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
   for (int sweep = 0; sweep < 80; ++sweep) {
@@ -143,7 +158,7 @@ inline void svd_tall(int m, int n, const double* A, double* U, double* S, double
   std::sort(wk.ord.begin(), wk.ord.end(), [&](int x, int y) { return nrm[x] > nrm[y]; });
   for (int jj = 0; jj < n; ++jj) {
     const int j = wk.ord[jj];
-    S[jj] = nrm[j];
+    S[jj] = ldexp(nrm[j], e);
     for (int i = 0; i < m; ++i) U[(size_t)jj * m + i] = nrm[j] > 0.0 ? W[(size_t)j * m + i] / nrm[j] : 0.0;
     for (int i = 0; i < n; ++i) Vout[(size_t)jj * n + i] = V[(size_t)j * n + i];
   }

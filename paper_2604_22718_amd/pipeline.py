@@ -19,9 +19,12 @@ from . import workloads as wl
 
 def normalise(cores):
     """Scale a train so that its last core has unit Frobenius norm (after a
-    left-to-right rounding the norm of the whole train sits there)."""
+    left-to-right rounding the norm of the whole train sits there).  The
+    norm is taken of the core divided by its largest entry: the constant
+    train on 1600 positions has norm 2^800, whose square overflows."""
     out = [np.array(c, copy=True) for c in cores]
-    out[-1] /= np.linalg.norm(out[-1])
+    m = np.abs(out[-1]).max()
+    out[-1] /= m * np.linalg.norm(out[-1] / m)
     return out
 
 

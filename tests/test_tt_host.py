@@ -95,3 +95,22 @@ def test_host_argument_errors(R):
     assert L.rtt_tfim_power_step(2, 2, pi.ctypes.data, bond.ctypes.data, cores.ctypes.data, 2, 1, 0, 1.0, 1.0, 0.1,
                                  4, 1e-14, out_b.ctypes.data, out.ctypes.data, 8, C.byref(n)) == -1
     assert b"read by no position" in L.rtt_last_error()
+
+
+def test_long_constant_train_stays_finite(R):
+    """The constant train on 1600 positions (a 20x20 lattice, four parts) has
+    norm 2^800: rounding squares no entry of that size, a power step with
+    the full replica Hamiltonian stays finite, and normalisation works."""
+    from paper_2604_22718_amd import lattice, pipeline
+    L = 20
+    pi = lattice.path(L, L)
+    phi = pipeline.constant_train(len(pi))
+    r = R.rtt_tt_round(phi, 2)
+    assert all(np.all(np.isfinite(c)) for c in r)
+    assert np.isclose(np.abs(r[-1]).max() * np.sqrt(2), 2.0 ** 800, rtol=1e-12)
+    c, o = lattice.replica_hamiltonian(L, L, "HV", 3.0, periodic=False)
+    sel = np.r_[0:40, 760:800]                      # ZZ and X strings
+    out = R.rtt_pauli_apply(phi, c[sel], o[sel], 1.0, -0.1, 2, 4)
+    assert all(np.all(np.isfinite(x)) for x in out)
+    n = pipeline.normalise(out)
+    assert np.isclose(np.linalg.norm(n[-1]), 1.0) and all(np.all(np.isfinite(x)) for x in n)
