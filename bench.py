@@ -554,8 +554,13 @@ def run_paper_pipeline(L=10, steps=120, phys_steps=2):
     from paper_2604_22718_amd import rtt as R
     N, hx = L * L, 3.0
     ham = R.TFIM(L, L, 1.0, hx, periodic=False)
+    def progress(p, _):
+        if (p + 1) % 20 == 0:
+            print(f"[paper pipeline] power step {p + 1}/{steps}", file=sys.stderr, flush=True)
+
     t0 = time.perf_counter()
-    pi, phi = pipeline.power_method(L, L, "HV", hx, 0.1, steps, chi=2, chi_sum=8, periodic=False)
+    pi, phi = pipeline.power_method(L, L, "HV", hx, 0.1, steps, chi=2, chi_sum=8, periodic=False,
+                                    callback=progress)
     host_ms = (time.perf_counter() - t0) * 1e3 / steps
 
     def energy(cores, seed):
