@@ -643,7 +643,7 @@ def main():
         res["learned"] = run_learned()
     if not a.no_cpu:
         from paper_2604_22718_amd import workloads as wl
-        res["cpu_baseline"] = cpu_baseline(wl.MEDIUM_8x8, 64, 8)
+        res["cpu_baseline"] = cpu_baseline(wl.MEDIUM_8x8, 64, 12)
         res["cpu_baseline"]["rows"] = cpu_baseline_rows()
     print(json.dumps(res), flush=True)
 
