@@ -114,3 +114,29 @@ def test_long_constant_train_stays_finite(R):
     assert all(np.all(np.isfinite(x)) for x in out)
     n = pipeline.normalise(out)
     assert np.isclose(np.linalg.norm(n[-1]), 1.0) and all(np.all(np.isfinite(x)) for x in n)
+
+
+def test_degenerate_trains(R):
+    """One core; a train that is exactly zero; beta = 0 (rounding alone);
+    a single Pauli string."""
+    from oracle import replica as orep
+    one = [np.array([[[0.7]], [[-1.3]]])]
+    x = R.rtt_pauli_apply(one, [2.0], np.array([[1]], dtype=np.uint8), 0.5, 1.0, 4)
+    assert np.allclose(x[0].ravel(), 0.5 * np.array([0.7, -1.3]) + 2.0 * np.array([-1.3, 0.7]))
+    assert np.allclose(R.rtt_tt_combine([one, one], [1.0, -3.0], 2)[0].ravel(), -2.0 * one[0].ravel())
+    c = wl.gaussian_cores(wl.open_bonds(6, 3), 950)
+    pi = np.arange(6, dtype=np.int32)
+    S = orc.all_configs(6)
+    z = R.rtt_tt_combine([c, c], [1.0, -1.0], 3)            # zero up to rounding
+    assert all(np.all(np.isfinite(k)) for k in z)
+    assert np.abs(orc.amplitudes(z, pi, S)).max() < 1e-13 * np.abs(orc.amplitudes(c, pi, S)).max()
+    zero = [np.zeros((2, a, b)) for a, b in zip(wl.open_bonds(6, 3)[:-1], wl.open_bonds(6, 3)[1:])]
+    z = R.rtt_tt_round(zero, 3)                              # exactly zero: one bond kept, psi = 0
+    assert max(k.shape[2] for k in z) == 1 and np.all(orc.amplitudes(z, pi, S) == 0.0)
+    r = R.rtt_pauli_apply(c, [1.0], np.zeros((1, 6), dtype=np.uint8), 1.0, 0.0, 2)
+    ref = orep.round_tt(c, 2)
+    assert np.allclose(orc.amplitudes(r, pi, S), orc.amplitudes(ref, pi, S), rtol=0, atol=1e-12)
+    ops = np.array([[3, 0, 2, 1, 0, 3]], dtype=np.uint8)
+    got = R.rtt_pauli_apply(c, [-0.4], ops, 0.0, 1.0, 64)
+    want = orep.pauli_apply(c, [-0.4], ops, 0.0, 1.0, 64)
+    assert np.allclose(orc.amplitudes(got, pi, S), orc.amplitudes(want, pi, S), rtol=0, atol=1e-12)
