@@ -156,3 +156,36 @@ def test_two_column_groups_many_walkers(R, dtype):
     clean = np.min(np.abs(margins), axis=(0, 1)) > 1e-4
     assert clean.sum() >= len(idx) - 3
     assert np.array_equal(got[clean], ref[clean])
+
+
+def test_maximum_spin_count_matrix_cores(R):
+    """N = 1024 (the largest the library takes), one replica, bond 16 on the
+    matrix-core kernels: 16 spin words per walker, long flip-ratio rows.
+    Ratios, amplitudes and one sweep of the sampled walkers against the
+    oracle."""
+    N, chi, W = 1024, 16, 3
+    pi = np.arange(N, dtype=np.int32)
+    bond = wl.open_bonds(N, chi)
+    cores = wl.gaussian_cores(bond, 64)
+    psi = R.RTT.create(N, pi, cores, "f32")
+    assert psi.info["narrow"] == 0 and psi.info["nw"] == 16
+    qc = device_cores(psi, bond)
+    bits = wl.random_spins(W, N, 65)
+    sp = R.spins_to_device(wl.pack_spins(bits))
+    out = psi.evaluate(sp)
+    torch.cuda.synchronize()
+    out = {k: v.cpu().numpy() for k, v in out.items()}
+    assert np.all(out["status"] == 0)
+    kap = orc.flip_condition_numbers(qc, pi, bits)
+    st = check_ratios(out["logratio"], out["rsign"], orc.flip_ratios(qc, pi, bits), kap, 1e-5)
+    print(psi.info, st)
+    assert st["n_bad"] == 0 and st["n_sign_bad"] == 0
+    la, sg = orc.log_sign(orc.amplitudes(qc, pi, bits))
+    k0 = orc.condition_numbers(qc, pi, bits)
+    assert np.all(out["sign"] == sg) and np.all(np.abs(out["logabs"] - la) <= 1e-5 * np.maximum(1.0, k0 / 10.0))
+    psi.sweep(sp, seed=66, n_sweeps=1)
+    torch.cuda.synchronize()
+    got = wl.unpack_spins(R.spins_to_host(sp), N)
+    ref, _, margins = mcmc.metropolis(qc, pi, bits, seed=66, n_sweeps=1, record=True)
+    clean = np.min(np.abs(margins), axis=(0, 1)) > 1e-4
+    assert np.array_equal(got[clean], ref[clean])
