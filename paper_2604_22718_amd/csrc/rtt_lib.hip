@@ -9,6 +9,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <stdexcept>
 #include <string>
 #include <vector>
 
@@ -646,6 +647,19 @@ rtt_status launch_narrow_chain(const rttn::NarrowArgs& a, size_t lds, hipStream_
   return RTT_OK;
 }
 
+// The host tensor-train algebra allocates freely: a failed allocation, or
+// any other exception, becomes a status code instead of crossing the C ABI.
+template <class F>
+rtt_status host_guard(const char* who, F&& f) {
+  try {
+    return f();
+  } catch (const std::bad_alloc&) {
+    return fail(RTT_E_OOM, "%s: host memory exhausted", who);
+  } catch (const std::exception& e) {
+    return fail(RTT_E_ARG, "%s: %s", who, e.what());
+  }
+}
+
 }  // namespace
 
 // ============================================================================
@@ -985,7 +999,7 @@ rtt_status rtt_mixed_estimators(int32_t M, const rtt_t* targets, rtt_ham_t ham, 
   return RTT_OK;
 }
 
-rtt_status rtt_tt_round(int32_t n_cores, const int32_t* bond, const double* cores, int32_t chi_max,
+static rtt_status rtt_tt_round_impl(int32_t n_cores, const int32_t* bond, const double* cores, int32_t chi_max,
                         double rel_tol, int32_t* bond_out, double* cores_out, int64_t cap, int64_t* n_out) {
   g_err.clear();
   if (chi_max < 1 || !(rel_tol >= 0.0)) return fail(RTT_E_ARG, "rtt_tt_round: chi_max %d, rel_tol %g", chi_max, rel_tol);
@@ -996,7 +1010,7 @@ rtt_status rtt_tt_round(int32_t n_cores, const int32_t* bond, const double* core
   return write_train("rtt_tt_round", t, bond_out, cores_out, cap, n_out);
 }
 
-rtt_status rtt_tfim_power_step(int32_t n_spins, int32_t n_cores, const int32_t* pi, const int32_t* bond,
+static rtt_status rtt_tfim_power_step_impl(int32_t n_spins, int32_t n_cores, const int32_t* pi, const int32_t* bond,
                                const double* cores, int32_t Lx, int32_t Ly, int32_t periodic, double J, double h,
                                double tau, int32_t chi_max, double rel_tol, int32_t* bond_out, double* cores_out,
                                int64_t cap, int64_t* n_out) {
@@ -1023,7 +1037,7 @@ rtt_status rtt_tfim_power_step(int32_t n_spins, int32_t n_cores, const int32_t* 
   return write_train("rtt_tfim_power_step", out, bond_out, cores_out, cap, n_out);
 }
 
-rtt_status rtt_pauli_apply(int32_t n_cores, const int32_t* bond, const double* cores, int32_t n_terms,
+static rtt_status rtt_pauli_apply_impl(int32_t n_cores, const int32_t* bond, const double* cores, int32_t n_terms,
                            const double* coeffs, const uint8_t* ops, double alpha, double beta, int32_t chi_max,
                            int32_t chi_sum, double rel_tol, int32_t* bond_out, double* cores_out, int64_t cap, int64_t* n_out) {
   g_err.clear();
@@ -1044,7 +1058,7 @@ rtt_status rtt_pauli_apply(int32_t n_cores, const int32_t* bond, const double* c
   return write_train("rtt_pauli_apply", out, bond_out, cores_out, cap, n_out);
 }
 
-rtt_status rtt_tt_combine(int32_t n_trains, int32_t n_cores, const int32_t* bonds, const double* const* cores,
+static rtt_status rtt_tt_combine_impl(int32_t n_trains, int32_t n_cores, const int32_t* bonds, const double* const* cores,
                           const double* coeffs, int32_t chi_max, double rel_tol, int32_t* bond_out,
                           double* cores_out, int64_t cap, int64_t* n_out) {
   g_err.clear();
@@ -1058,6 +1072,42 @@ rtt_status rtt_tt_combine(int32_t n_trains, int32_t n_cores, const int32_t* bond
   }
   const rtt_tt::Train out = rtt_tt::combine(std::move(trains), coeffs, chi_max, rel_tol);
   return write_train("rtt_tt_combine", out, bond_out, cores_out, cap, n_out);
+}
+
+rtt_status rtt_tt_round(int32_t n_cores, const int32_t* bond, const double* cores, int32_t chi_max,
+                        double rel_tol, int32_t* bond_out, double* cores_out, int64_t cap, int64_t* n_out) {
+  return host_guard("rtt_tt_round", [&] {
+    return rtt_tt_round_impl(n_cores, bond, cores, chi_max, rel_tol, bond_out, cores_out, cap, n_out);
+  });
+}
+
+rtt_status rtt_tfim_power_step(int32_t n_spins, int32_t n_cores, const int32_t* pi, const int32_t* bond,
+                               const double* cores, int32_t Lx, int32_t Ly, int32_t periodic, double J, double h,
+                               double tau, int32_t chi_max, double rel_tol, int32_t* bond_out, double* cores_out,
+                               int64_t cap, int64_t* n_out) {
+  return host_guard("rtt_tfim_power_step", [&] {
+    return rtt_tfim_power_step_impl(n_spins, n_cores, pi, bond, cores, Lx, Ly, periodic, J, h, tau, chi_max,
+                                    rel_tol, bond_out, cores_out, cap, n_out);
+  });
+}
+
+rtt_status rtt_pauli_apply(int32_t n_cores, const int32_t* bond, const double* cores, int32_t n_terms,
+                           const double* coeffs, const uint8_t* ops, double alpha, double beta, int32_t chi_max,
+                           int32_t chi_sum, double rel_tol, int32_t* bond_out, double* cores_out, int64_t cap,
+                           int64_t* n_out) {
+  return host_guard("rtt_pauli_apply", [&] {
+    return rtt_pauli_apply_impl(n_cores, bond, cores, n_terms, coeffs, ops, alpha, beta, chi_max, chi_sum,
+                                rel_tol, bond_out, cores_out, cap, n_out);
+  });
+}
+
+rtt_status rtt_tt_combine(int32_t n_trains, int32_t n_cores, const int32_t* bonds, const double* const* cores,
+                          const double* coeffs, int32_t chi_max, double rel_tol, int32_t* bond_out,
+                          double* cores_out, int64_t cap, int64_t* n_out) {
+  return host_guard("rtt_tt_combine", [&] {
+    return rtt_tt_combine_impl(n_trains, n_cores, bonds, cores, coeffs, chi_max, rel_tol, bond_out, cores_out,
+                               cap, n_out);
+  });
 }
 
 rtt_status rtt_energy_reduce(int32_t n, const double* x, double* out, void* stream) {

@@ -15,6 +15,8 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <atomic>
+#include <new>
 #include <thread>
 #include <vector>
 
@@ -313,10 +315,15 @@ inline Train pairwise_sum(std::vector<Train> terms, int chi_max, double rel_tol)
   while (terms.size() > 1) {
     const size_t pairs = terms.size() / 2;
     std::vector<Train> nxt((terms.size() + 1) / 2);
+    std::atomic<bool> failed{false};
     auto work = [&](size_t p0, size_t p1) {
-      for (size_t p = p0; p < p1; ++p) {
-        nxt[p] = add(terms[2 * p], terms[2 * p + 1]);
-        round_train(nxt[p], chi_max, rel_tol);
+      try {
+        for (size_t p = p0; p < p1; ++p) {
+          nxt[p] = add(terms[2 * p], terms[2 * p + 1]);
+          round_train(nxt[p], chi_max, rel_tol);
+        }
+      } catch (...) {  // an exception must not leave a worker thread
+        failed = true;
       }
     };
     const size_t nt = std::min<size_t>(hw, pairs);
@@ -327,6 +334,7 @@ inline Train pairwise_sum(std::vector<Train> terms, int chi_max, double rel_tol)
       for (size_t w = 0; w < nt; ++w) th.emplace_back(work, pairs * w / nt, pairs * (w + 1) / nt);
       for (auto& t : th) t.join();
     }
+    if (failed) throw std::bad_alloc();
     if (terms.size() % 2) nxt.back() = std::move(terms.back());
     terms.swap(nxt);
   }
