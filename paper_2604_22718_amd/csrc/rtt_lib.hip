@@ -671,7 +671,7 @@ const char* rtt_last_error(void) { return g_err.c_str(); }
 
 int32_t rtt_abi_version(void) { return 3; }
 
-rtt_status rtt_create(int32_t n_spins, int32_t n_cores, const int32_t* pi, const int32_t* bond,
+static rtt_status rtt_create_impl(int32_t n_spins, int32_t n_cores, const int32_t* pi, const int32_t* bond,
                       const double* cores, int32_t dtype, rtt_t* out) {
   g_err.clear();
   if (!out) return fail(RTT_E_ARG, "rtt_create: out is null");
@@ -719,7 +719,7 @@ rtt_status rtt_create(int32_t n_spins, int32_t n_cores, const int32_t* pi, const
   return RTT_OK;
 }
 
-rtt_status rtt_lincomb(int32_t n_terms, const rtt_t* terms, const double* coeffs, rtt_t* out) {
+static rtt_status rtt_lincomb_impl(int32_t n_terms, const rtt_t* terms, const double* coeffs, rtt_t* out) {
   g_err.clear();
   if (!out) return fail(RTT_E_ARG, "rtt_lincomb: out is null");
   *out = nullptr;
@@ -813,7 +813,7 @@ rtt_status rtt_get_cores(rtt_t h, int32_t term, double* out) {
   return RTT_OK;
 }
 
-rtt_status rtt_tfim_create(int32_t Lx, int32_t Ly, int32_t periodic, double J, double h, rtt_ham_t* out) {
+static rtt_status rtt_tfim_create_impl(int32_t Lx, int32_t Ly, int32_t periodic, double J, double h, rtt_ham_t* out) {
   g_err.clear();
   if (!out) return fail(RTT_E_ARG, "rtt_tfim_create: out is null");
   *out = nullptr;
@@ -1110,6 +1110,39 @@ rtt_status rtt_tt_combine(int32_t n_trains, int32_t n_cores, const int32_t* bond
   });
 }
 
+static rtt_status rtt_batch_create_impl(int32_t n, const rtt_t* rtts, const rtt_ham_t* hams, const int32_t* walkers,
+                                        uint64_t* const* spins, double* const* eloc, uint64_t seed, rtt_batch_t* out);
+static rtt_status rtt_batch_autotune_impl(rtt_batch_t b, int32_t n_sweeps, int32_t reps, const char* cache_path,
+                                          int32_t* choice, void* stream);
+static rtt_status rtt_net_create_impl(int32_t Lx, int32_t Ly, const double* params, rtt_net_t* out);
+
+rtt_status rtt_create(int32_t n_spins, int32_t n_cores, const int32_t* pi, const int32_t* bond,
+                      const double* cores, int32_t dtype, rtt_t* out) {
+  return host_guard("rtt_create", [&] { return rtt_create_impl(n_spins, n_cores, pi, bond, cores, dtype, out); });
+}
+
+rtt_status rtt_lincomb(int32_t n_terms, const rtt_t* terms, const double* coeffs, rtt_t* out) {
+  return host_guard("rtt_lincomb", [&] { return rtt_lincomb_impl(n_terms, terms, coeffs, out); });
+}
+
+rtt_status rtt_tfim_create(int32_t Lx, int32_t Ly, int32_t periodic, double J, double h, rtt_ham_t* out) {
+  return host_guard("rtt_tfim_create", [&] { return rtt_tfim_create_impl(Lx, Ly, periodic, J, h, out); });
+}
+
+rtt_status rtt_batch_create(int32_t n, const rtt_t* rtts, const rtt_ham_t* hams, const int32_t* walkers,
+                            uint64_t* const* spins, double* const* eloc, uint64_t seed, rtt_batch_t* out) {
+  return host_guard("rtt_batch_create", [&] { return rtt_batch_create_impl(n, rtts, hams, walkers, spins, eloc, seed, out); });
+}
+
+rtt_status rtt_batch_autotune(rtt_batch_t b, int32_t n_sweeps, int32_t reps, const char* cache_path,
+                              int32_t* choice, void* stream) {
+  return host_guard("rtt_batch_autotune", [&] { return rtt_batch_autotune_impl(b, n_sweeps, reps, cache_path, choice, stream); });
+}
+
+rtt_status rtt_net_create(int32_t Lx, int32_t Ly, const double* params, rtt_net_t* out) {
+  return host_guard("rtt_net_create", [&] { return rtt_net_create_impl(Lx, Ly, params, out); });
+}
+
 rtt_status rtt_energy_reduce(int32_t n, const double* x, double* out, void* stream) {
   g_err.clear();
   if (n < 0 || (n > 0 && !x) || !out) return fail(RTT_E_ARG, "rtt_energy_reduce: bad argument");
@@ -1327,7 +1360,7 @@ std::string batch_signature(const rtt_batch_s* b) {
 
 extern "C" {
 
-rtt_status rtt_batch_create(int32_t n, const rtt_t* rtts, const rtt_ham_t* hams, const int32_t* walkers,
+static rtt_status rtt_batch_create_impl(int32_t n, const rtt_t* rtts, const rtt_ham_t* hams, const int32_t* walkers,
                             uint64_t* const* spins, double* const* eloc, uint64_t seed, rtt_batch_t* out) {
   g_err.clear();
   if (!out) return fail(RTT_E_ARG, "rtt_batch_create: out is null");
@@ -1494,7 +1527,7 @@ rtt_status rtt_batch_step(rtt_batch_t b, int32_t n_sweeps, double* esum, void* s
   return RTT_OK;
 }
 
-rtt_status rtt_batch_autotune(rtt_batch_t b, int32_t n_sweeps, int32_t reps, const char* cache_path,
+static rtt_status rtt_batch_autotune_impl(rtt_batch_t b, int32_t n_sweeps, int32_t reps, const char* cache_path,
                               int32_t* choice, void* stream) {
   g_err.clear();
   if (!b || reps < 1 || n_sweeps < 0) return fail(RTT_E_ARG, "rtt_batch_autotune: bad argument");
@@ -1630,7 +1663,7 @@ rtt_status net_grad_launch(rtt_net_s* n, int B, const uint64_t* spins, const int
 
 extern "C" {
 
-rtt_status rtt_net_create(int32_t Lx, int32_t Ly, const double* params, rtt_net_t* out) {
+static rtt_status rtt_net_create_impl(int32_t Lx, int32_t Ly, const double* params, rtt_net_t* out) {
   g_err.clear();
   if (!out) return fail(RTT_E_ARG, "rtt_net_create: out is null");
   *out = nullptr;
