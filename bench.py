@@ -540,7 +540,18 @@ def time_narrow(N, pi, cores, ham, W=4096, reps=20):
                              "unit": "TFLOP/s", "frac": le_flops / (le_ms * 1e9) / peak}}
 
 
-def run_paper_pipeline(L=10, steps=120, phys_steps=2):
+# Operator sets of the paper's physical-space table (rows in its order) and
+# the energies per site and V-scores it reports for them at 10x10, h = 3.
+PAPER_TABLE = [
+    (("ZZ_HV", "ZZ_DD'"), -3.1682, 0.0013),
+    (("ZZ_HV", "ZZ_DD'", "X"), -3.1682, 0.0013),
+    (("ZZ_HV", "X"), -3.163, 0.005),
+    (("ZZ_DD'", "X"), -3.1682, 0.0013),
+    ((), -3.163, 0.005),
+]
+
+
+def run_paper_pipeline(L=10, steps=120, phys_steps=2, table=False):
     """The paper's chi = 2 pipeline on an L x L open lattice, h = 3 (the
     setting of its physical-space table): H+V+D+D' path, replica-space power
     method with H-bar_HV (tau = 0.1, host rounding, partial sums at rank 8)
@@ -569,6 +580,7 @@ def run_paper_pipeline(L=10, steps=120, phys_steps=2):
         psi.close()
         return {"E_per_site": r["mean"] / N, "sigma_per_site": r["sigma"] / N, "v_score": r["v_score"]}
 
+    phi0 = phi
     out = {"workload": f"tfim{L}x{L}_open_h3_path_HVDDp_chi2", "power_steps": steps,
            "power_step_host_ms": host_ms, "replica_HV": energy(phi, 1200), "physical": []}
     for it in range(phys_steps):
@@ -582,6 +594,21 @@ def run_paper_pipeline(L=10, steps=120, phys_steps=2):
     if L == 10:
         out["paper_table_context"] = {"replica_HV_only": {"E_per_site": -3.163, "v_score": 0.005},
                                       "with_ZZ_DDp": {"E_per_site": -3.1682, "v_score": 0.0013}}
+    if table:   # every operator set of the table, each from the same replica-space state
+        rows = []
+        for ops, e_paper, v_paper in PAPER_TABLE:
+            cur = phi0
+            row = {"operators": ["I", *ops], "paper_E_per_site": e_paper, "paper_v_score": v_paper}
+            for it in range(phys_steps if ops else 0):
+                cur, info = pipeline.physical_space_step(pi, cur, L, L, ["I", *ops], 2, ham, 4096, 300, 200,
+                                                         seed=1500 + 10 * it + len(rows), chi_sum=8,
+                                                         periodic=False)
+                row["lambda_per_site"] = info["lambda"] / N
+            row.update(energy(cur, 1600 + len(rows)))
+            rows.append(row)
+            print(f"[paper pipeline] table row {len(rows)}: {row['operators']} E/N {row['E_per_site']:.5f}",
+                  file=sys.stderr, flush=True)
+        out["table"] = rows
     if L == 20:   # reference energy quoted by the paper for its replica-space runs at this size
         out["paper_reference_E_per_site"] = -3.18185
     out["narrow_kernels"] = time_narrow(N, pi, phi, ham)
@@ -605,6 +632,8 @@ def main():
     ap.add_argument("--paper-pipeline", type=int, default=0, metavar="STEPS",
                     help="also run the chi=2 power method for STEPS steps plus two physical-space steps")
     ap.add_argument("--paper-side", type=int, default=10, help="lattice side of the chi=2 pipeline (10 or 20)")
+    ap.add_argument("--paper-table", action="store_true",
+                    help="with --paper-pipeline: also every operator set of the physical-space table")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="only copy this many MiB device-to-device 3 times (counter calibration) and exit")
     a = ap.parse_args()
@@ -636,7 +665,7 @@ def main():
     if not a.no_dual:
         res["dual_mc"] = run_dual()
     if a.paper_pipeline:
-        res["paper_pipeline"] = run_paper_pipeline(L=a.paper_side, steps=a.paper_pipeline)
+        res["paper_pipeline"] = run_paper_pipeline(L=a.paper_side, steps=a.paper_pipeline, table=a.paper_table)
     if a.batched:
         res["batched"] = run_batched(a.batched)
     if a.learned:
