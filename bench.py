@@ -638,7 +638,7 @@ def main():
                     help="only copy this many MiB device-to-device 3 times (counter calibration) and exit")
     a = ap.parse_args()
     if a.gpus != 1:
-        print(f"bench.py measures one GPU only: this build has no multi-GPU path (asked for {a.gpus}).",
+        print(f"bench.py measures one GPU only: the library has no multi-GPU path (asked for {a.gpus}).",
               file=sys.stderr)
         sys.exit(2)
     import torch

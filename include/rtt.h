@@ -52,7 +52,7 @@ typedef enum {
   RTT_E_ARG = -1,          /* invalid argument */
   RTT_E_OOM = -2,          /* device allocation failed */
   RTT_E_HIP = -3,          /* a HIP runtime call failed */
-  RTT_E_UNSUPPORTED = -4,  /* valid input outside what this build supports */
+  RTT_E_UNSUPPORTED = -4,  /* valid input outside what the library supports */
   RTT_E_NONFINITE = -5     /* per-walker status: zero or non-finite amplitude */
 } rtt_status;
 
