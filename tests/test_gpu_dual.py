@@ -8,7 +8,7 @@ import scipy.linalg
 import torch
 
 from helpers import case, device_cores
-from oracle import dual, rtt as orc, stats, tfim
+from oracle import dual, rtt as orc, stats, tfim, tt
 from paper_2604_22718_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
@@ -172,3 +172,38 @@ def test_z_only_shortcut_single_chain(R):
                 m, s, _, _ = stats.energy_estimate(X[:, a, b:b + 1])
                 s = s if np.isfinite(s) else 0.0          # constant series (S~_aa = 1)
                 assert abs(m - ex[a, b]) < 3 * s + 1e-5 * (1.0 + abs(ex[a, b])), (a, b, m, ex[a, b], s)
+
+
+def test_full_size_dual_step_sampled_walkers(R):
+    """The dual Monte Carlo line's shape in bench.py's launch configuration
+    (8x8, chi = 64, 4096 walkers, FP32, the workload's RTT, a second seeded
+    RTT and 0.8 a - 1.1 b): estimators of every walker against all three
+    states; the oracle recomputes a sample of walkers one by one."""
+    w = wl.MEDIUM_8x8
+    pi, bond = w.pi(), w.bond()
+    a = R.RTT.create(w.N, pi, w.cores(), "f32")
+    b = R.RTT.create(w.N, pi, wl.gaussian_cores(bond, w.core_seed + 5), "f32")
+    c = R.RTT.lincomb([a, b], np.array([0.8, -1.1]))
+    qa, qb = device_cores(a, bond), device_cores(b, bond)
+    ref = [qa, qb, ([qa, qb], np.array([0.8, -1.1]))]
+    ham = R.TFIM(w.Lx, w.Ly, w.J, w.h)
+    bits = w.spins()
+    spins = R.spins_to_device(wl.pack_spins(bits))
+    idx = np.array([0, 1, 2047, 4095])
+    bonds = tfim.bonds(w.Lx, w.Ly)
+    for sa, state in enumerate((a, c)):
+        la, sg = state.amplitudes(spins)
+        ratio, mixed, st = R.mixed_estimators([a, b, c], ham, spins, la, sg)
+        torch.cuda.synchronize()
+        ratio, mixed, st = ratio.cpu().numpy(), mixed.cpu().numpy(), st.cpu().numpy()
+        assert np.all(st == 0)
+        def kap(x):   # cancellation measure of a state on the sampled walkers
+            if isinstance(x, tuple):
+                return orc.condition_numbers(tt.direct_sum(x[0], x[1]), pi, bits[idx])
+            return orc.condition_numbers(x, pi, bits[idx])
+        for t in range(3):
+            o_ref, e_ref = dual.mixed_estimators(ref[2 * sa], ref[t], pi, bits[idx], bonds, w.J, w.h)
+            allow = 1e-5 * np.maximum(1.0, np.maximum(kap(ref[2 * sa]), kap(ref[t])) / 10.0)
+            assert np.all(np.abs(np.log(np.abs(ratio[t][idx] / o_ref))) <= 2 * allow), (sa, t)
+            assert np.all(np.sign(ratio[t][idx]) == np.sign(o_ref))
+            assert np.all(np.abs(mixed[t][idx] - e_ref) <= 1e-3 * np.abs(e_ref).max()), (sa, t)
