@@ -596,14 +596,20 @@ def run_paper_pipeline(L=10, steps=120, phys_steps=2, table=False):
                                       "with_ZZ_DDp": {"E_per_site": -3.1682, "v_score": 0.0013}}
     if table:   # every operator set of the table, each from the same replica-space state
         rows = []
-        for ops, e_paper, v_paper in PAPER_TABLE:
+        # Z-only sets run twice: dual Monte Carlo, and one chain on the first state
+        cases = [(ops, e, v, "dual") for ops, e, v in PAPER_TABLE]
+        cases += [(ops, e, v, "single") for ops, e, v in PAPER_TABLE if ops and "X" not in ops]
+        for ops, e_paper, v_paper, sampling in cases:
             cur = phi0
-            row = {"operators": ["I", *ops], "paper_E_per_site": e_paper, "paper_v_score": v_paper}
+            row = {"operators": ["I", *ops], "sampling": sampling, "paper_E_per_site": e_paper,
+                   "paper_v_score": v_paper}
+            t_row = time.perf_counter()
             for it in range(phys_steps if ops else 0):
                 cur, info = pipeline.physical_space_step(pi, cur, L, L, ["I", *ops], 2, ham, 4096, 300, 200,
                                                          seed=1500 + 10 * it + len(rows), chi_sum=8,
-                                                         periodic=False)
+                                                         periodic=False, sampling=sampling)
                 row["lambda_per_site"] = info["lambda"] / N
+            row["steps_s"] = time.perf_counter() - t_row
             row.update(energy(cur, 1600 + len(rows)))
             rows.append(row)
             print(f"[paper pipeline] table row {len(rows)}: {row['operators']} E/N {row['E_per_site']:.5f}",

@@ -114,6 +114,33 @@ def dual_matrices(states, ham, walkers, burn, sweeps, seed, blocks=10, rows=None
     return Ht, St, sH, sS
 
 
+def single_chain_matrices(states, ham, walkers, burn, sweeps, seed, blocks=10):
+    """H and S of a list of states up to one common factor from a single
+    chain on |psi^0|^2 (importance sampling): S_ab = <r_a r_b>, H_ab =
+    <r_a m_b>, with r_b = psi^b/psi^0 and m_b = sum_t H_st psi^b(t)/psi^0(s).
+    This is the single-simulation route the paper notes for operators made
+    of Z's (Sec. 4.1.3): psi^a = d_a psi^0 with d_a diagonal, so no chain
+    has to sample |psi^a|^2; it holds for any states whose support lies in
+    that of psi^0.  Returns H, S and their block-average error bars."""
+    M, N = len(states), states[0].N
+    spins = _walkers(walkers, N, seed)
+    la = torch.empty(walkers, dtype=torch.float64, device=spins.device)
+    sg = torch.empty(walkers, dtype=torch.int8, device=spins.device)
+    states[0].sweep(spins, seed=seed, rng_stream=0, sweep0=0, n_sweeps=burn, logabs=la, sign=sg)
+    s_rows, h_rows = [], []
+    for t in range(sweeps):
+        states[0].sweep(spins, seed=seed, rng_stream=0, sweep0=burn + t, n_sweeps=1, logabs=la, sign=sg)
+        ratio, mixed, st = R.mixed_estimators(states, ham, spins, la, sg)
+        s_rows.append((ratio[:, None, :] * ratio[None, :, :]).mean(dim=2))
+        h_rows.append((ratio[:, None, :] * mixed[None, :, :]).mean(dim=2))
+    Sx = torch.stack(s_rows).cpu().numpy()   # (sweeps, M, M)
+    Hx = torch.stack(h_rows).cpu().numpy()
+    S, H = Sx.mean(axis=0), Hx.mean(axis=0)
+    sS = np.array([[_blocked_sigma(Sx[:, a, b], blocks) for b in range(M)] for a in range(M)])
+    sH = np.array([[_blocked_sigma(Hx[:, a, b], blocks) for b in range(M)] for a in range(M)])
+    return H, S, sH, sS
+
+
 def lowest_eigenpair(Ht, St):
     """Lowest real eigenvalue of H~ c = lambda S~ c and its vector, scaled so
     that c^T S~ c = 1 (with c[0] >= 0)."""
@@ -129,12 +156,15 @@ def lowest_eigenpair(Ht, St):
 
 
 def physical_space_step(pi, phi, Lx, Ly, operators, chi, ham, walkers, burn, sweeps, seed, chi_sum=None,
-                        periodic=False, orthogonalise=True, dtype="f32"):
+                        periodic=False, orthogonalise=True, dtype="f32", sampling="dual"):
     """One physical-space optimisation step (Sec. 3.3, Sec. 4.3): states
     psi^a = C O-bar_a phi for the named operators (each compressed to chi),
     re-orthogonalised against psi^1 with a GPU overlap estimate, dual Monte
-    Carlo H~ and S~, the lowest generalised eigenpair, and the combination
+    Carlo H~ and S~ (or, with sampling="single", H and S from one chain on
+    the first state), the lowest generalised eigenpair, and the combination
     sum_a c_a psi^a compressed to chi.  Returns (new cores, info)."""
+    if sampling not in ("dual", "single"):
+        raise ValueError(f"sampling must be 'dual' or 'single', not {sampling!r}")
     N = Lx * Ly
     trains = []
     for name in operators:
@@ -154,11 +184,14 @@ def physical_space_step(pi, phi, Lx, Ly, operators, chi, ham, walkers, burn, swe
         for x in [first] + others:
             x.close()
     states = [R.RTT.create(N, pi, t, dtype) for t in trains]
-    Ht, St, sH, sS = dual_matrices(states, ham, walkers, burn, sweeps, seed)
+    if sampling == "single":
+        Ht, St, sH, sS = single_chain_matrices(states, ham, walkers, burn, sweeps, seed)
+    else:
+        Ht, St, sH, sS = dual_matrices(states, ham, walkers, burn, sweeps, seed)
     lam, c = lowest_eigenpair(Ht, St)
     new = normalise(R.rtt_tt_combine(trains, c, chi))
     for x in states:
         x.close()
-    return new, {"lambda": lam, "coeffs": c.tolist(), "H_tilde": Ht.tolist(), "S_tilde": St.tolist(),
+    return new, {"lambda": lam, "coeffs": c.tolist(), "sampling": sampling, "H_tilde": Ht.tolist(), "S_tilde": St.tolist(),
                  "sigma_H": sH.tolist(), "sigma_S": sS.tolist(), "gram_schmidt": gs.tolist(),
                  "trains": trains}

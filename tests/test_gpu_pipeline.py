@@ -86,3 +86,31 @@ def test_physical_space_step(R, projected):
     assert abs(info["lambda"] - lam_ex) < 2e-3 * abs(lam_ex)
     assert e_new < e_start + 1e-3 * abs(e_start)
     assert max(c.shape[2] for c in new) <= 2
+
+
+def test_single_chain_matrices_for_z_operators(R, projected):
+    """Operators made of Z's (I, O_ZZ,HV, O_ZZ,DD'): H and S from one chain
+    on the first state agree with enumeration (up to the common factor
+    <psi^0|psi^0>) within 4 sigma, and the lowest eigenvalue with the one
+    of the enumerated matrices."""
+    from paper_2604_22718_amd import pipeline
+    pi, phi = projected
+    N = Lx * Ly
+    ham = R.TFIM(Lx, Ly, J, HX, periodic=False)
+    new, info = pipeline.physical_space_step(pi, phi, Lx, Ly, ["I", "ZZ_HV", "ZZ_DD'"], 2, ham, walkers=2048,
+                                             burn=50, sweeps=200, seed=830, chi_sum=8, periodic=False,
+                                             sampling="single")
+    q = [quantised(R, pi, t) for t in info["trains"]]
+    S_all = orc.all_configs(N)
+    amps = [orc.amplitudes(t, pi, S_all) for t in q]
+    H = tfim.sparse_hamiltonian(Lx, Ly, J, HX, periodic=False)
+    z0 = amps[0] @ amps[0]
+    S_ex = np.array([[a @ b for b in amps] for a in amps]) / z0
+    H_ex = np.array([[a @ (H @ b) for b in amps] for a in amps]) / z0
+    Hs, Ss = np.array(info["H_tilde"]), np.array(info["S_tilde"])
+    sH, sS = np.array(info["sigma_H"]), np.array(info["sigma_S"])
+    assert np.all(np.abs(Ss - S_ex) < 4 * sS + 1e-5 * (1 + np.abs(S_ex)))
+    assert np.all(np.abs(Hs - H_ex) < 4 * sH + 1e-5 * (1 + np.abs(H_ex)))
+    lam_ex = dual.lowest_generalised_eigenvalue(H_ex, S_ex)
+    print(f"single chain: lambda {info['lambda'] / N:.5f} exact {lam_ex / N:.5f}")
+    assert abs(info["lambda"] - lam_ex) < 2e-3 * abs(lam_ex)
