@@ -192,6 +192,6 @@ def physical_space_step(pi, phi, Lx, Ly, operators, chi, ham, walkers, burn, swe
     new = normalise(R.rtt_tt_combine(trains, c, chi))
     for x in states:
         x.close()
-    return new, {"lambda": lam, "coeffs": c.tolist(), "sampling": sampling, "H_tilde": Ht.tolist(), "S_tilde": St.tolist(),
-                 "sigma_H": sH.tolist(), "sigma_S": sS.tolist(), "gram_schmidt": gs.tolist(),
-                 "trains": trains}
+    return new, {"lambda": lam, "coeffs": c.tolist(), "sampling": sampling,
+                 "H_tilde": Ht.tolist(), "S_tilde": St.tolist(), "sigma_H": sH.tolist(), "sigma_S": sS.tolist(),
+                 "gram_schmidt": gs.tolist(), "trains": trains}
