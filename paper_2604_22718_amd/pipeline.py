@@ -156,9 +156,10 @@ def lowest_eigenpair(Ht, St):
 
 
 def physical_space_step(pi, phi, Lx, Ly, operators, chi, ham, walkers, burn, sweeps, seed, chi_sum=None,
-                        periodic=False, orthogonalise=True, dtype="f32", sampling="dual"):
+                        periodic=False, orthogonalise=True, dtype="f32", sampling="dual", chi_state=None):
     """One physical-space optimisation step (Sec. 3.3, Sec. 4.3): states
-    psi^a = C O-bar_a phi for the named operators (each compressed to chi),
+    psi^a = C O-bar_a phi for the named operators (each compressed to
+    chi_state, by default chi),
     re-orthogonalised against psi^1 with a GPU overlap estimate, dual Monte
     Carlo H~ and S~ (or, with sampling="single", H and S from one chain on
     the first state), the lowest generalised eigenpair, and the combination
@@ -172,7 +173,8 @@ def physical_space_step(pi, phi, Lx, Ly, operators, chi, ham, walkers, burn, swe
             trains.append(normalise(phi))
             continue
         c, o = lattice.operator(Lx, Ly, name, periodic)
-        trains.append(normalise(R.rtt_pauli_apply(phi, c, o, 0.0, 1.0, chi, chi_sum)))
+        cs = chi if chi_state is None else chi_state
+        trains.append(normalise(R.rtt_pauli_apply(phi, c, o, 0.0, 1.0, cs, max(cs, chi_sum or cs))))
     gs = np.zeros(len(trains))
     if orthogonalise and len(trains) > 1:
         first = R.RTT.create(N, pi, trains[0], dtype)
@@ -180,7 +182,8 @@ def physical_space_step(pi, phi, Lx, Ly, operators, chi, ham, walkers, burn, swe
         _, St, _, _ = dual_matrices([first] + others, ham, walkers, burn, sweeps, seed + 1000, rows=[0])
         for m in range(1, len(trains)):
             gs[m] = St[0, m]
-            trains[m] = normalise(R.rtt_tt_combine([trains[m], trains[0]], [1.0, -gs[m]], chi))
+            trains[m] = normalise(R.rtt_tt_combine([trains[m], trains[0]], [1.0, -gs[m]],
+                                                   chi if chi_state is None else chi_state))
         for x in [first] + others:
             x.close()
     states = [R.RTT.create(N, pi, t, dtype) for t in trains]
