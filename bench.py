@@ -43,13 +43,18 @@ def schedule_rowsteps(pi, N, L, cut):
 
 
 def sweep_rowsteps(pi, N, L):
-    """Row-vector x core products of one sweep per walker: the amplitude pass
-    (L) plus, for each proposal, the flipped row from its first position to
-    the end of the train."""
-    first = {}
+    """Row-vector x core products a sweep needs per walker: the amplitude (L)
+    plus, for each proposal, the positions from the spin's first replica to
+    its last one (with the prefix and the right environment of the current
+    configuration at hand, the rest of the train is the current amplitude's).
+    The sampler performs somewhat more: its right environments are kept only
+    at checkpoint bonds, and the batched kernels contract every proposal's
+    columns from the right boundary."""
+    first, last = {}, {}
     for k, j in enumerate(pi):
         first.setdefault(int(j), k)
-    return L + sum(L - f for f in first.values())
+        last[int(j)] = k
+    return L + sum(last[j] - first[j] + 1 for j in first)
 
 
 # Sources that define or launch the matrix-core kernels, and the build flags:

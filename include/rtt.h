@@ -79,6 +79,11 @@ int32_t rtt_abi_version(void);
  * sampling take vector-ALU kernels on C x C slices instead (C = 2 or 4, FP32
  * arithmetic on the same quantised values); the environment variable
  * RTT_NARROW=0 at creation keeps such a train on the matrix-core kernels.
+ * Matrix-core sweeps at padded bonds up to 64 keep the right environments of
+ * a few bonds (column checkpoints) on chip between proposals;
+ * RTT_CHAIN_CHECKPOINTS=0 at creation
+ * makes every proposal contract its columns from the right boundary (the
+ * batched entry points always do, so results then match them bit for bit).
  * The batched entry points always use the matrix-core kernels.
  * RTT_E_UNSUPPORTED if the working set of one walker exceeds on-chip memory.
  */

@@ -136,22 +136,31 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// Load a lane's KPL-element fragment (contiguous, 16-byte aligned).
+// Fragment tiles hold 64 lanes x KPL elements in 16-byte chunks, chunk-major:
+// element e of lane l sits at ((e / CE) * 64 + l) * CE + e % CE, CE = 16 /
+// element size.  One 16-byte load of the 64 lanes then reads 1 KB of
+// consecutive bytes (8 cache lines) instead of touching 32 lines a quarter
+// each, which is what limited the rate at which CUs take fragments from L2.
+__host__ __device__ constexpr size_t frag_offset(int lane, int e, int ce) {
+  return ((size_t)(e / ce) * 64 + lane) * ce + e % ce;
+}
+
+// Load a lane's KPL-element fragment from a tile (16-byte aligned).
 template <int KPL>
-__device__ __forceinline__ void load_frag(float (&dst)[KPL], const float* src) {
-  const float4* s = reinterpret_cast<const float4*>(src);
+__device__ __forceinline__ void load_frag(float (&dst)[KPL], const float* tile, int lane) {
+  const float4* s = reinterpret_cast<const float4*>(tile) + lane;
 #pragma unroll
   for (int i = 0; i < KPL / 4; ++i) {
-    float4 v = s[i];
+    float4 v = s[64 * i];
     dst[4 * i + 0] = v.x; dst[4 * i + 1] = v.y; dst[4 * i + 2] = v.z; dst[4 * i + 3] = v.w;
   }
 }
 template <int KPL>
-__device__ __forceinline__ void load_frag(uint16_t (&dst)[KPL], const uint16_t* src) {
-  const uint4* s = reinterpret_cast<const uint4*>(src);
+__device__ __forceinline__ void load_frag(uint16_t (&dst)[KPL], const uint16_t* tile, int lane) {
+  const uint4* s = reinterpret_cast<const uint4*>(tile) + lane;
 #pragma unroll
   for (int i = 0; i < KPL / 8; ++i) {
-    uint4 v = s[i];
+    uint4 v = s[64 * i];
     uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
     for (int j = 0; j < 4; ++j) {

@@ -108,9 +108,9 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int bx, int ty) {
     const int bit = spin_bit(spw, st.y);
 #pragma unroll
     for (int q = 0; q < MTI; ++q) {
-      const size_t tile = ((size_t)(wv * MT + ig * MTI + q) * 64 + lane) * KPL;
-      load_frag<KPL>(F.m[q], cores + ((size_t)st.x * 2 + bit) * (CHI * CHI) + tile);
-      load_frag<KPL>(F.o[q], cores + ((size_t)st.x * 2 + (bit ^ 1)) * (CHI * CHI) + tile);
+      const size_t tile = (size_t)(wv * MT + ig * MTI + q) * 64 * KPL;
+      load_frag<KPL>(F.m[q], cores + ((size_t)st.x * 2 + bit) * (CHI * CHI) + tile, lane);
+      load_frag<KPL>(F.o[q], cores + ((size_t)st.x * 2 + (bit ^ 1)) * (CHI * CHI) + tile, lane);
     }
   };
   auto compute = [&](const Frags& F, int item) {
@@ -360,6 +360,10 @@ struct ChainArgs {
   uint64_t seed, rstream, sweep0;
   int n_sweeps;
   int mode;                  // 0: amplitudes only, 1: sweeps
+  // Column checkpoints (sweeps, all terms together): the right environments
+  // of bonds ck_first + i * ck_step, i < n_ck, for the current configuration,
+  // kept in LDS with a per-walker validity mask (0: none).
+  int n_ck, ck_first, ck_step;
 };
 
 // Layout of one block's walkers' state in LDS (offsets in bytes), for
@@ -367,22 +371,27 @@ struct ChainArgs {
 // U and F, row ping-pong X/Y and column ping-pong CX/CY (7 buffers), all
 // terms advancing together when that fits; otherwise ("sequential") each
 // term keeps only its prefix and the terms share F, X, Y, CX, CY, one term
-// at a time, the prefix being advanced after the decision.
+// at a time, the prefix being advanced after the decision.  Vectors are
+// stored buffer-major ([buffer][term]); with all terms together nck column
+// checkpoints per term and as many candidates follow as buffers 7 ...
+// 6 + 2 nck, their exponents at the end.
 struct ChainLayout {
-  int nb, rows, exps, vals, pm, sp, total;
+  int nb, rows, exps, vals, pm, sp, ckexp, total;
   bool seq;
-  __host__ __device__ ChainLayout(int chi, int T, int LW, int nw, int cg) {
+  __host__ __device__ ChainLayout(int chi, int T, int LW, int nw, int cg, int nck = 0) {
     nb = 16 * cg;
     const int bufb = nb * (chi + 4) * 4;
     const int tail = 4 * T * nb * 4 + T * nb * 12 + 8 + nb * LW * 8 + nb * nw * 8;
     seq = (T * 7 * bufb + tail) > 160 * 1024;
-    rows = 0;                                      // float vectors
-    exps = rows + (seq ? T + 5 : 7 * T) * bufb;    // int [4][T][nb]: prefix, first step, row, column
+    if (seq) nck = 0;
+    rows = 0;                                                 // float vectors
+    exps = rows + (seq ? T + 5 : (7 + 2 * nck) * T) * bufb;  // int [4][T][nb]: prefix, first step, row, column
     vals = exps + 4 * T * nb * 4;                  // double [T][nb] end values, int [T][nb] exponents
     pm = vals + T * nb * 12;
     pm = (pm + 7) & ~7;
     sp = pm + nb * LW * 8;                         // uint64 [nb][LW] position bits; [nb][nw] spins
-    total = sp + nb * nw * 8;
+    ckexp = sp + nb * nw * 8;                      // int [2][nck][T][nb] checkpoint exponents
+    total = ckexp + 2 * nck * T * nb * 4;
   }
 };
 
@@ -404,8 +413,10 @@ struct ChainGeo {
 // from the left (forward fragment layout), the other SW waves column vectors
 // from the right boundary (backward layout); the two meet half way and are
 // joined by an FP64 dot product.  The number of dependent steps per
-// amplitude is halved and each SIMD runs two independent chains.
-template <class D, int CHI, int CG>
+// amplitude is halved and each SIMD runs two independent chains.  CKP
+// compiles the column checkpoints in (bonds up to 64: wider bonds leave LDS
+// for too few of them, and their register-bound kernels stay as they are).
+template <class D, int CHI, int CG, bool CKP = false>
 __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t sweep0) {
   using E = typename D::elem;
   using G = Geo<CHI>;
@@ -420,7 +431,7 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
   const int nthr = blockDim.x, nwave = nthr >> 6;
   const int T = a.T, L = a.L, LW = a.LW, nw = a.nw;
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  const ChainLayout lay(CHI, T, LW, nw, CG);
+  const ChainLayout lay(CHI, T, LW, nw, CG, a.n_ck);
   float* rows = reinterpret_cast<float*>(lds_raw + lay.rows);
   int* Ep = reinterpret_cast<int*>(lds_raw + lay.exps);   // [T][NB] prefix
   int* Ef = Ep + T * NB;                                   // [T][NB] after the first step
@@ -432,11 +443,26 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
   uint64_t* sp = reinterpret_cast<uint64_t*>(lds_raw + lay.sp);
   const bool seq = lay.seq;
   const int nbuf = seq ? T + 5 : 7 * T;
+  const int NCK = (CKP && !seq) ? a.n_ck : 0;
+  int* cke = reinterpret_cast<int*>(lds_raw + lay.ckexp);
 
-  enum { P = 0, U = 1, F = 2, X = 3, Y = 4, CX = 5, CY = 6 };
+  // Buffer ids: the seven vectors of a term, then CK + i for the saved
+  // column of checkpoint i and CD + i for its candidate.
+  enum { P = 0, U = 1, F = 2, X = 3, Y = 4, CX = 5, CY = 6, CK = 7 };
+  const int CD = CK + NCK;
   auto buf = [&](int t, int b) {
-    if (!seq) return rows + (t * 7 + b) * BUF;
+    if (!seq) return rows + (b * T + t) * BUF;
     return b == P ? rows + t * BUF : rows + (T + b - F) * BUF;  // U is not used then
+  };
+  auto ckexp = [&](int b, int t, int wn) -> int& { return cke[((b - CK) * T + t) * NB + wn]; };
+  // index of the first checkpoint whose bond is >= b (NCK if none)
+  auto ck_ceil = [&](int b) {
+    const int d = b - a.ck_first;
+    return d <= 0 ? 0 : min(NCK, (d + a.ck_step - 1) / a.ck_step);
+  };
+  // bits [lo, hi) of a checkpoint mask
+  auto ck_bits = [](int lo, int hi) -> uint32_t {
+    return hi > lo ? ((1u << hi) - 1u) & ~((1u << lo) - 1u) : 0u;
   };
 
   const int w0 = bx * NB;
@@ -461,7 +487,6 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
   }
 
   const E* cores = static_cast<const E*>(side == 0 ? a.cores : a.cores_bwd);
-  const size_t lane_off = (size_t)lane * KPL;
   struct Frags { E f0[KPL]; E f1[KPL]; };
   typename D::template BOp<KPL> bo[CG];
 
@@ -471,7 +496,11 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
 
   // For terms [t0, t0+tn) with spin jflip flipped (-1: none): advance the
   // row vectors from P through positions [k0, k1) and, at the same time,
-  // column vectors from the right boundary through positions L-1 down to kc.
+  // column vectors from bond ks (the right boundary if ks = L, else the
+  // saved column of that checkpoint) through positions ks-1 down to kc.
+  // Columns reaching a checkpoint bond are kept: as its saved column when
+  // the bond lies past lj, the last position of the flipped spin (they are
+  // then the current configuration's), else as its candidate.
   // Work items of a wave are (step, term, output tile) in that order; the
   // two core fragments of the next item are loaded while the current one
   // computes, and each serves all CG column groups.  Each joint step ends
@@ -479,31 +508,42 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
   // With `split` the first row step stores the walker's own slice product in
   // F and the other slice's in U.  Vectors are renormalised every
   // kRenormEvery steps; the exponent sums live in Er and Ec.
-  auto segment = [&](int k0, int k1, int kc, int jflip, bool split, int t0, int tn) {
-    const int nr = k1 > k0 ? k1 - k0 : 0, nc = L - kc;
+  auto segment = [&](int k0, int k1, int kc, int ks, int lj, int jflip, bool split, int t0, int tn) {
+    const int nr = k1 > k0 ? k1 - k0 : 0, nc = ks - kc;
+    const int cks = (CKP && ks < L) ? CK + (ks - a.ck_first) / a.ck_step : -1;
     if (nr == 0) rb = P;
     else if (split) rb = nr == 1 ? F : (((nr - 1) & 1) ? X : Y);
     else rb = (nr & 1) ? X : Y;
-    cb = nc == 0 ? -1 : ((nc & 1) ? CX : CY);
+    cb = nc == 0 ? cks : ((nc & 1) ? CX : CY);
     const int S = nr > nc ? nr : nc;
     const int n = side == 0 ? nr : nc;
+    if (CKP && side == 1 && n == 0 && cks >= 0 && wv == 0 && g == 0)
+      for (int t = t0; t < t0 + tn; ++t)
+#pragma unroll
+        for (int cg = 0; cg < CG; ++cg) Ec[t * NB + 16 * cg + m] = ckexp(cks, t, 16 * cg + m);
     if (n > 0) {
       const uint64_t* rmj = jflip >= 0 ? a.rmask + (size_t)jflip * LW : nullptr;
-      int cur = side == 0 ? P : -1;
+      int cur = side == 0 ? P : cks;
       int out = side == 0 ? (split ? F : X) : CX;
       const int tend = t0 + tn;
       int i = 0, t = t0, mt = 0;
+      // the next checkpoint the columns reach (bond ckb, index cki; -1: none)
+      int cki = -1, ckb = -1;
+      if (CKP && side == 1 && NCK > 0 && ks - 1 >= a.ck_first) {
+        cki = min(NCK - 1, (ks - 1 - a.ck_first) / a.ck_step);
+        ckb = a.ck_first + cki * a.ck_step;
+      }
       int bit[CG];
       uint64_t word[CG];
 #pragma unroll
       for (int cg = 0; cg < CG; ++cg) { bit[cg] = 0; word[cg] = 0; }
-      auto pos_of = [&](int ii) { return side == 0 ? k0 + ii : L - 1 - ii; };
+      auto pos_of = [&](int ii) { return side == 0 ? k0 + ii : ks - 1 - ii; };
       auto load = [&](Frags& Fr, int ii, int tt, int mm) {
         const int kk = pos_of(ii < n ? ii : n - 1);
         const E* base = cores + (((size_t)tt * L + kk) * 2) * (CHI * CHI) +
-                        (size_t)(wv * MT + mm) * 64 * KPL + lane_off;
-        load_frag<KPL>(Fr.f0, base);
-        load_frag<KPL>(Fr.f1, base + CHI * CHI);
+                        (size_t)(wv * MT + mm) * 64 * KPL;
+        load_frag<KPL>(Fr.f0, base, lane);
+        load_frag<KPL>(Fr.f1, base + CHI * CHI, lane);
       };
       auto step = [&](const Frags& Fr) {
         const int k = pos_of(i);
@@ -530,7 +570,7 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
                 const int e = renorm_row<KPL>(v);
                 if (wv == 0 && g == 0) {
                   if (side == 1) {
-                    Ec[t * NB + wn] += e;
+                    Ec[t * NB + wn] = ((CKP && i == 0) ? ckexp(cur, t, wn) : Ec[t * NB + wn]) + e;
                   } else if (split && i == 0) {
                     const int ne = Ep[t * NB + wn] + e;
                     Ef[t * NB + wn] = ne;
@@ -564,7 +604,22 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
                 make_float4(oth[0], oth[1], oth[2], oth[3]);
           }
         }
+        if (CKP && k == ckb) {  // columns only
+          const int slot = k > lj ? CK + cki : CD + cki;
+#pragma unroll
+          for (int cg = 0; cg < CG; ++cg) {
+            const int wn = 16 * cg + m;
+            const f4 sel = bit[cg] ? c1[cg] : c0[cg];
+            *reinterpret_cast<float4*>(buf(t, slot) + wn * RS + 16 * tt + 4 * g) =
+                make_float4(sel[0], sel[1], sel[2], sel[3]);
+            if (wv == 0 && g == 0 && mt == 0) ckexp(slot, t, wn) = Ec[t * NB + wn];
+          }
+        }
         if (mt == MT - 1 && t == tend - 1) {
+          if (CKP && k == ckb) {
+            --cki;
+            ckb = cki >= 0 ? ckb - a.ck_step : -1;
+          }
           lds_barrier();
           cur = out;
           out = side == 0 ? ((cur == X) ? Y : X) : ((cur == CX) ? CY : CX);
@@ -656,8 +711,10 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
     }
     for (int i = threadIdx.x; i < T * NB; i += nthr) Ep[i] = 0;
   };
-  // the meeting bond of a contraction that starts at position f
-  auto meet = [&](int f) { return f + (L - f + 1) / 2; };
+  // the meeting bond of a contraction over positions [f, ks)
+  auto meet = [&](int f, int ks) { return f + (ks - f + 1) / 2; };
+  // bond of checkpoint i
+  auto ck_bond = [&](int i) { return a.ck_first + i * a.ck_step; };
 
   // amplitude of the current configuration (identical in every lane of a walker)
   reset_prefix();
@@ -665,14 +722,25 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
   double lab[CG];
   int sgn[CG], stat[CG];
   uint32_t nacc[CG];
+  const int c0 = meet(0, L);
   if (!seq) {
-    segment(0, meet(0), meet(0), -1, false, 0, T);
+    segment(0, c0, c0, L, -1, -1, false, 0, T);
     record(0, T);
   } else {
     for (int t = 0; t < T; ++t) {
-      segment(0, meet(0), meet(0), -1, false, t, 1);
+      segment(0, c0, c0, L, -1, -1, false, t, 1);
       record(t, 1);
     }
+  }
+  // checkpoints the columns passed are valid (same mask in every lane of a
+  // walker, in every wave)
+  uint32_t vmask[CG];
+  {
+    uint32_t v0 = 0;
+    for (int i = 0; i < NCK; ++i)
+      if (ck_bond(i) >= c0) v0 |= 1u << i;
+#pragma unroll
+    for (int cg = 0; cg < CG; ++cg) vmask[cg] = v0;
   }
 #pragma unroll
   for (int cg = 0; cg < CG; ++cg) {
@@ -703,7 +771,7 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
         }
         // bring the prefix of terms [t0, t0+tn) from pos up to position kk
         auto advance_prefix = [&](int kk, int t0, int tn) {
-          segment(pos, kk, L, -1, false, t0, tn);
+          segment(pos, kk, L, L, -1, -1, false, t0, tn);
           for (int i = threadIdx.x; i < tn * NB * RS; i += nthr) {
             const int t = t0 + i / (NB * RS), r = i % (NB * RS);
             buf(t, P)[r] = buf(t, rb)[r];
@@ -716,16 +784,40 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
           else for (int t = 0; t < T; ++t) advance_prefix(f, t, 1);
           pos = f;
         }
-        // the flipped amplitude from position f, rows and columns meeting
-        // half way; with all terms at once the first row step also leaves
-        // the unflipped prefix extension in U
-        const int c = meet(f);
+        // the columns start from the first checkpoint past the spin's last
+        // position that every walker of the block holds valid (else from
+        // the right boundary)
+        int lj = -1;
+        for (int wd = LW - 1; wd >= 0; --wd) {
+          const uint64_t x = a.rmask[(size_t)j * LW + wd];
+          if (x) { lj = 64 * wd + 63 - __clzll((long long)x); break; }
+        }
+        int ks = L;
+        const int il = ck_ceil(lj + 1);  // checkpoints below il lie at or before lj
+        if (CKP && NCK > 0) {
+          uint32_t av = ~0u;
+#pragma unroll
+          for (int cg = 0; cg < CG; ++cg) {
+            uint32_t x = vmask[cg];
+            x &= (uint32_t)__shfl_xor((int)x, 1);
+            x &= (uint32_t)__shfl_xor((int)x, 2);
+            x &= (uint32_t)__shfl_xor((int)x, 4);
+            x &= (uint32_t)__shfl_xor((int)x, 8);
+            av &= x;
+          }
+          const uint32_t elig = av & ~ck_bits(0, il);
+          if (elig) ks = ck_bond(__builtin_ctz(elig));
+        }
+        // the flipped amplitude over [f, ks), rows and columns meeting half
+        // way; with all terms at once the first row step also leaves the
+        // unflipped prefix extension in U
+        const int c = meet(f, ks);
         if (!seq) {
-          segment(f, c, c, j, true, 0, T);
+          segment(f, c, c, ks, lj, j, true, 0, T);
           record(0, T);
         } else {
           for (int t = 0; t < T; ++t) {
-            segment(f, c, c, j, false, t, 1);
+            segment(f, c, c, L, lj, j, false, t, 1);
             record(t, 1);
           }
         }
@@ -760,6 +852,33 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
                 *reinterpret_cast<float4*>(buf(t, P) + off) =
                     *reinterpret_cast<const float4*>(buf(t, accept[cg] ? F : U) + off);
               }
+        }
+        // checkpoints: the columns computed past lj hold the current
+        // configuration for every walker; those at or before lj become the
+        // saved ones of the walkers that accepted (copied by the 4 * nwave
+        // lanes of each walker), and earlier ones at or before lj go stale
+        // for them
+        if (CKP && NCK > 0) {
+          const int ic0 = ck_ceil(c), ic1 = ck_ceil(ks);  // computed: [ic0, ic1)
+          const int icand = min(ic1, il);                  // candidates: [ic0, icand)
+          const uint32_t past = ck_bits(max(ic0, il), ic1);
+          const uint32_t cand = ck_bits(ic0, icand), stale = ck_bits(0, min(ic0, il));
+          const int r = wave * 4 + g;  // index among a walker's lanes
+#pragma unroll
+          for (int cg = 0; cg < CG; ++cg) {
+            vmask[cg] |= past;
+            if (accept[cg]) {
+              vmask[cg] = (vmask[cg] | cand) & ~stale;
+              const int wn = 16 * cg + m;
+              for (int i = ic0; i < icand; ++i)
+                for (int t = 0; t < T; ++t) {
+                  for (int q = r; q < CHI / 4; q += 4 * nwave)
+                    reinterpret_cast<float4*>(buf(t, CK + i) + wn * RS)[q] =
+                        reinterpret_cast<const float4*>(buf(t, CD + i) + wn * RS)[q];
+                  if (r == 0) ckexp(CK + i, t, wn) = ckexp(CD + i, t, wn);
+                }
+            }
+          }
         }
         if (wave == 0 && g == 0) {
 #pragma unroll
@@ -800,9 +919,9 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
   }
 }
 
-template <class D, int CHI, int CG>
+template <class D, int CHI, int CG, bool CKP>
 __global__ void __launch_bounds__(ChainGeo<CHI>::NT) chain_kernel(ChainArgs a) {
-  chain_body<D, CHI, CG>(a, blockIdx.x, a.sweep0);
+  chain_body<D, CHI, CG, CKP>(a, blockIdx.x, a.sweep0);
 }
 
 // ============================================================================

@@ -203,6 +203,7 @@ struct rtt_s {
   double* d_coeffs = nullptr;
   // narrow-bond path (every bond <= 4): C x C slices, prescaled, zero padded
   int narrow = 0;             // C = 2 or 4, 0 when the matrix-core path runs
+  int chain_ck = 1;           // sweeps keep column checkpoints in LDS
   float* d_ncores = nullptr;  // [T][L][2][C][C]
   // workspace
   size_t ws_W = 0;
@@ -230,7 +231,8 @@ size_t elem_bytes(int dtype) { return dtype == RTT_F32 ? 4 : 2; }
 
 // Pack one term: element (t, lane, e) of slice (k, b) in the forward layout
 // is core[b][g*KPL + e][16t + m] (transposed), in the backward layout
-// core[b][16t + m][g*KPL + e]; lane = 16 g + m, KPL = chi / 4.
+// core[b][16t + m][g*KPL + e]; lane = 16 g + m, KPL = chi / 4.  Within the
+// 64 * KPL elements of tile t the order is rttk::frag_offset's.
 void pack_term(const rtt_s* h, int term, const std::vector<double>& q, std::vector<uint8_t>& fw,
                std::vector<uint8_t>& bw) {
   const int chi = h->chi, L = h->L, KPL = chi / 4;
@@ -254,7 +256,7 @@ void pack_term(const rtt_s* h, int term, const std::vector<double>& q, std::vect
         for (int lane = 0; lane < 64; ++lane)
           for (int e = 0; e < KPL; ++e) {
             const int g = lane >> 4, m = lane & 15;
-            const size_t idx = base + ((size_t)t * 64 + lane) * KPL + e;
+            const size_t idx = base + (size_t)t * 64 * KPL + rttk::frag_offset(lane, e, (int)(16 / eb));
             const double vf = pad[s * slice + (size_t)(g * KPL + e) * chi + 16 * t + m];
             const double vb = pad[s * slice + (size_t)(16 * t + m) * chi + g * KPL + e];
             if (eb == 4) {
@@ -428,6 +430,8 @@ rtt_status finish_create(rtt_s* h) {
   if ((st = upload((void**)&h->d_first, h->first.data(), h->first.size() * 4)) != RTT_OK) return st;
   if ((st = upload((void**)&h->d_coeffs, h->coeffs.data(), h->coeffs.size() * 8)) != RTT_OK) return st;
   if ((st = setup_narrow(h)) != RTT_OK) return st;
+  const char* ck = getenv("RTT_CHAIN_CHECKPOINTS");
+  h->chain_ck = (ck && ck[0] == '0') ? 0 : 1;
   HIPX(hipDeviceSynchronize());
   return RTT_OK;
 }
@@ -469,12 +473,37 @@ int device_cus() {
   return n;
 }
 
+// Column checkpoints for a sweep launch: as many as fit in the LDS left over
+// (without lowering the blocks per CU the launch needs, at most 16), evenly
+// spaced over the bonds a proposal can start its columns from, [lo, L), lo
+// being passed in ck_first.
+void chain_checkpoints(rttk::ChainArgs& a, int chi, int cg, int blocks) {
+  const int lo = a.ck_first, LW = (a.L + 63) / 64;
+  a.n_ck = 0; a.ck_first = 0; a.ck_step = 1;
+  if (a.mode != 1 || lo >= a.L || lo < 1 || chi > 64) return;
+  const rttk::ChainLayout l0(chi, a.T, LW, a.nw, cg, 0), l1(chi, a.T, LW, a.nw, cg, 1);
+  if (l0.seq) return;
+  const size_t budget = kLdsLimit / (blocks > device_cus() ? 2 : 1);
+  const size_t per = (size_t)(l1.total - l0.total);
+  if ((size_t)l0.total + per > budget) return;
+  const int nmax = std::min<int>(16, (int)((budget - l0.total) / per));
+  const int span = a.L - lo;
+  const int step = (span + nmax - 1) / nmax;
+  a.n_ck = (span + step - 1) / step;
+  a.ck_first = lo;
+  a.ck_step = step;
+}
+
 template <class D, int CHI, int CG>
-rtt_status launch_chain_cg(const rttk::ChainArgs& a, hipStream_t s) {
-  const size_t lds = chain_lds_bytes(CHI, a.T, a.L, a.nw, CG);
-  auto kfn = rttk::chain_kernel<D, CHI, CG>;
-  HIPX(hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+rtt_status launch_chain_cg(const rttk::ChainArgs& a0, hipStream_t s) {
+  rttk::ChainArgs a = a0;
   dim3 grid((a.W + 16 * CG - 1) / (16 * CG));
+  chain_checkpoints(a, CHI, CG, (int)grid.x);
+  const size_t lds = (size_t)rttk::ChainLayout(CHI, a.T, (a.L + 63) / 64, a.nw, CG, a.n_ck).total;
+  auto kfn = rttk::chain_kernel<D, CHI, CG, false>;
+  if constexpr (CHI <= 64)
+    if (a.n_ck > 0) kfn = rttk::chain_kernel<D, CHI, CG, true>;
+  HIPX(hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   hipLaunchKernelGGL(kfn, grid, dim3(rttk::ChainGeo<CHI>::NT), lds, s, a);
   HIPX(hipGetLastError());
   return RTT_OK;
@@ -802,7 +831,8 @@ rtt_status rtt_get_cores(rtt_t h, int32_t term, double* out) {
         for (int j = 0; j < b; ++j) {
           // forward layout holds core[s][i][j] at g*KPL+e = i, 16t+m = j
           const int g = i / KPL, e = i % KPL, t = j / 16, m = j % 16;
-          const size_t idx = ((size_t)k * 2 + s) * slice + ((size_t)t * 64 + 16 * g + m) * KPL + e;
+          const size_t idx = ((size_t)k * 2 + s) * slice + (size_t)t * 64 * KPL +
+                             rttk::frag_offset(16 * g + m, e, (int)(16 / eb));
           double v;
           if (eb == 4) { float f; memcpy(&f, &fw[idx * 4], 4); v = f; }
           else { uint16_t u; memcpy(&u, &fw[idx * 2], 2); v = bf16_value(u); }
@@ -939,6 +969,16 @@ static rtt_status chain_common(rtt_t h, int32_t W, uint64_t* spins, double* loga
   ca.T = h->T; ca.L = h->L; ca.N = h->N; ca.nw = h->nw; ca.LW = (h->L + 63) / 64; ca.W = W;
   ca.spins = spins; ca.logabs = logabs; ca.sign = sign; ca.accepts = accepts; ca.status = status;
   ca.seed = seed; ca.rstream = rstream; ca.sweep0 = sweep0; ca.n_sweeps = n_sweeps; ca.mode = mode;
+  // the lowest bond a proposal's columns can start from: one past the
+  // smallest last position over the spins
+  {
+    std::vector<int> last(h->N, -1);
+    for (int k = 0; k < h->L; ++k) last[h->pi[k]] = k;
+    int lo = h->L;
+    for (int j = 0; j < h->N; ++j)
+      if (last[j] >= 0) lo = std::min(lo, last[j] + 1);
+    ca.ck_first = h->chain_ck ? lo : h->L;
+  }
   return dispatch<ChainL>(h->dtype, h->chi, ca, (hipStream_t)stream);
 }
 

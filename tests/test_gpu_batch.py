@@ -2,6 +2,7 @@
 bit-identical results to stepping each RTT on its own through the C ABI
 (which is itself parity-tested against the oracle), on every graph replay."""
 import math
+import os
 
 import numpy as np
 import pytest
@@ -32,11 +33,18 @@ def R():
 
 
 def build(R):
+    """The runs, created without column checkpoints: the persistent batch
+    kernels contract every proposal's columns from the right boundary, and
+    the eager reference must do the same to agree bit for bit."""
     rtts, hams, spins, meta = [], [], [], []
     for i, (Lx, Ly, Rr, chi, dtype, W) in enumerate(RUNS):
         N = Lx * Ly
         pi, bond, cores = case(N, Rr, chi, "perm", seed=40 + i)
-        rtts.append(R.RTT.create(N, pi, cores, dtype))
+        os.environ["RTT_CHAIN_CHECKPOINTS"] = "0"
+        try:
+            rtts.append(R.RTT.create(N, pi, cores, dtype))
+        finally:
+            del os.environ["RTT_CHAIN_CHECKPOINTS"]
         hams.append(R.TFIM(Lx, Ly, 1.0, 2.0 + 0.3 * i))
         spins.append(R.spins_to_device(wl.pack_spins(wl.random_spins(W, N, 50 + i))))
         meta.append((pi, bond, N, Lx, Ly, 2.0 + 0.3 * i))

