@@ -160,6 +160,12 @@ rtt_status rtt_local_energy(rtt_t h, rtt_ham_t ham, int32_t W, const uint64_t* s
  * train position (spins read by no position last); the move is accepted iff
  * u < r_j^2, with u = (x >> 11) * 2^-53 and x word 0 of Philox4x64-10 under
  * key (seed, rng_stream) and counter (walker index, sweep0 + t, j, 0).
+ * Each proposal's flipped amplitude is contracted from the prefix of the
+ * spin's first position to a right environment of the current configuration
+ * (the right boundary, or a checkpoint bond past the spin's last position
+ * kept on chip since an earlier proposal), so the rounding of an amplitude
+ * depends on which checkpoints are valid: decisions agree with an exact
+ * evaluation except at near-ties (|u - r^2| within the FP32/BF16 error).
  *   spins    device uint64[W][ceil(N/64)], updated in place
  *   logabs   device double[W] or NULL: log|psi| of the final configuration
  *   sign     device int8[W] or NULL
