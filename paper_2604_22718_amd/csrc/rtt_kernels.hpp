@@ -403,7 +403,9 @@ struct ChainGeo {
   static constexpr int SW = CHI >= 128 ? 2 : Geo<CHI>::WPW;  // waves per side
   static constexpr int MT = CHI / (16 * SW);                   // output tiles per wave
   static constexpr int NT = 2 * SW * 64;                       // threads per block
-  static constexpr int PF = 2;                                 // fragment sets in flight + 1
+  // fragment sets in the prefetch ring (see chain_body)
+  template <class E>
+  static constexpr int PF = (CHI == 128 && sizeof(E) == 2) ? 4 : 2;
 };
 
 // Block of 2 * SW waves for 16 * CG walkers: CG groups of 16 matrix-core
@@ -421,7 +423,11 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
   using E = typename D::elem;
   using G = Geo<CHI>;
   constexpr int RS = G::RS, KPL = G::KPL;
-  constexpr int MT = ChainGeo<CHI>::MT, SW = ChainGeo<CHI>::SW, PF = ChainGeo<CHI>::PF;
+  // Prefetch ring of fragment sets: 4 for BF16 fragments at bond 128 (10x10
+  // sweep 37.4 -> 30.9 ms), 2 elsewhere (deeper rings slowed the bond-64
+  // sweep; FP32 at 128 would spill and at 256 the fragments would not fit
+  // the register file).
+  constexpr int MT = ChainGeo<CHI>::MT, SW = ChainGeo<CHI>::SW, PF = ChainGeo<CHI>::template PF<E>;
   constexpr int NB = 16 * CG;
   constexpr int BUF = NB * RS;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
