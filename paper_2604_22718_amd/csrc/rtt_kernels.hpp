@@ -374,11 +374,12 @@ struct ChainArgs {
 // at a time, the prefix being advanced after the decision.  Vectors are
 // stored buffer-major ([buffer][term]); with all terms together nck column
 // checkpoints per term and as many candidates follow as buffers 7 ...
-// 6 + 2 nck, their exponents at the end.
+// 6 + 2 nck, their exponents after the spins, and last the replica bitmasks
+// of the n_spins spins when they fit (else they are read from global memory).
 struct ChainLayout {
-  int nb, rows, exps, vals, pm, sp, ckexp, total;
-  bool seq;
-  __host__ __device__ ChainLayout(int chi, int T, int LW, int nw, int cg, int nck = 0) {
+  int nb, rows, exps, vals, pm, sp, ckexp, rm, total;
+  bool seq, rml;
+  __host__ __device__ ChainLayout(int chi, int T, int LW, int nw, int cg, int nck, int n_spins) {
     nb = 16 * cg;
     const int bufb = nb * (chi + 4) * 4;
     const int tail = 4 * T * nb * 4 + T * nb * 12 + 8 + nb * LW * 8 + nb * nw * 8;
@@ -392,6 +393,9 @@ struct ChainLayout {
     sp = pm + nb * LW * 8;                         // uint64 [nb][LW] position bits; [nb][nw] spins
     ckexp = sp + nb * nw * 8;                      // int [2][nck][T][nb] checkpoint exponents
     total = ckexp + 2 * nck * T * nb * 4;
+    rm = (total + 7) & ~7;                         // uint64 [n_spins][LW] replica bitmasks
+    rml = rm + n_spins * LW * 8 <= 160 * 1024;
+    if (rml) total = rm + n_spins * LW * 8;
   }
 };
 
@@ -437,7 +441,7 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
   const int nthr = blockDim.x, nwave = nthr >> 6;
   const int T = a.T, L = a.L, LW = a.LW, nw = a.nw;
   extern __shared__ __align__(16) unsigned char lds_raw[];
-  const ChainLayout lay(CHI, T, LW, nw, CG, a.n_ck);
+  const ChainLayout lay(CHI, T, LW, nw, CG, a.n_ck, a.N);
   float* rows = reinterpret_cast<float*>(lds_raw + lay.rows);
   int* Ep = reinterpret_cast<int*>(lds_raw + lay.exps);   // [T][NB] prefix
   int* Ef = Ep + T * NB;                                   // [T][NB] after the first step
@@ -481,6 +485,16 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
     const int n = i / nw, wd = i % nw;
     sp[i] = (w0 + n < a.W) ? a.spins[(size_t)(w0 + n) * nw + wd] : 0ull;
   }
+  // replica bitmask word wd of spin j (from LDS when the masks fit there)
+  uint64_t* rml = reinterpret_cast<uint64_t*>(lds_raw + lay.rm);
+  if (lay.rml)
+    for (int i = threadIdx.x; i < a.N * LW; i += nthr) rml[i] = a.rmask[i];
+  auto rword = [&](int j, int wd) -> uint64_t {
+    uint64_t x;
+    if (lay.rml) x = rml[j * LW + wd];
+    else x = a.rmask[(size_t)j * LW + wd];
+    return x;
+  };
   __syncthreads();
   for (int i = threadIdx.x; i < NB * LW; i += nthr) {
     const int n = i / LW, wd = i % LW;
@@ -528,7 +542,7 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
 #pragma unroll
         for (int cg = 0; cg < CG; ++cg) Ec[t * NB + 16 * cg + m] = ckexp(cks, t, 16 * cg + m);
     if (n > 0) {
-      const uint64_t* rmj = jflip >= 0 ? a.rmask + (size_t)jflip * LW : nullptr;
+
       int cur = side == 0 ? P : cks;
       int out = side == 0 ? (split ? F : X) : CX;
       const int tend = t0 + tn;
@@ -557,7 +571,7 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
           const bool fresh = i == 0 || (k & 63) == (side == 0 ? 0 : 63);
 #pragma unroll
           for (int cg = 0; cg < CG; ++cg) {
-            if (fresh) word[cg] = pm[(16 * cg + m) * LW + (k >> 6)] ^ (rmj ? rmj[k >> 6] : 0ull);
+            if (fresh) word[cg] = pm[(16 * cg + m) * LW + (k >> 6)] ^ (jflip >= 0 ? rword(jflip, k >> 6) : 0ull);
             bit[cg] = (int)((word[cg] >> (k & 63)) & 1ull);
           }
         }
@@ -795,7 +809,7 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
         // the right boundary)
         int lj = -1;
         for (int wd = LW - 1; wd >= 0; --wd) {
-          const uint64_t x = a.rmask[(size_t)j * LW + wd];
+          const uint64_t x = rword(j, wd);
           if (x) { lj = 64 * wd + 63 - __clzll((long long)x); break; }
         }
         int ks = L;
@@ -894,8 +908,7 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
               for (int t = 0; t < T; ++t) Ep[t * NB + wn] = Ef[t * NB + wn];
             if (accept[cg]) {
               sp[wn * nw + (j >> 6)] ^= (1ull << (j & 63));
-              const uint64_t* rmj = a.rmask + (size_t)j * LW;
-              for (int wd = 0; wd < LW; ++wd) pm[wn * LW + wd] ^= rmj[wd];
+              for (int wd = 0; wd < LW; ++wd) pm[wn * LW + wd] ^= rword(j, wd);
             }
           }
         }

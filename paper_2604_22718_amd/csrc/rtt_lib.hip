@@ -168,8 +168,8 @@ size_t pass_lds_bytes(int chi, int nslot, int nw) {
   return (size_t)wpb * (2 * nslot * rs * 4 + 2 * nslot * 4 + nw * 8);
 }
 
-size_t chain_lds_bytes(int chi, int T, int L, int nw, int cg = 1) {
-  return (size_t)rttk::ChainLayout(chi, T, (L + 63) / 64, nw, cg).total;
+size_t chain_lds_bytes(int chi, int T, int L, int nw, int n_spins, int cg = 1) {
+  return (size_t)rttk::ChainLayout(chi, T, (L + 63) / 64, nw, cg, 0, n_spins).total;
 }
 
 }  // namespace
@@ -392,7 +392,7 @@ rtt_status finish_create(rtt_s* h) {
     }
   }
   if (!have) return fail(RTT_E_UNSUPPORTED, "rtt_create: flip-ratio rows of one walker exceed on-chip memory");
-  if (chain_lds_bytes(h->chi, h->T, h->L, h->nw) > kLdsLimit)
+  if (chain_lds_bytes(h->chi, h->T, h->L, h->nw, h->N) > kLdsLimit)
     return fail(RTT_E_UNSUPPORTED, "rtt_create: sampling state of 16 walkers exceeds on-chip memory");
   h->sched = best;
   // proposal order: spins by first position, unread spins last
@@ -481,7 +481,7 @@ void chain_checkpoints(rttk::ChainArgs& a, int chi, int cg, int blocks) {
   const int lo = a.ck_first, LW = (a.L + 63) / 64;
   a.n_ck = 0; a.ck_first = 0; a.ck_step = 1;
   if (a.mode != 1 || lo >= a.L || lo < 1 || chi > 64) return;
-  const rttk::ChainLayout l0(chi, a.T, LW, a.nw, cg, 0), l1(chi, a.T, LW, a.nw, cg, 1);
+  const rttk::ChainLayout l0(chi, a.T, LW, a.nw, cg, 0, a.N), l1(chi, a.T, LW, a.nw, cg, 1, a.N);
   if (l0.seq) return;
   const size_t budget = kLdsLimit / (blocks > device_cus() ? 2 : 1);
   const size_t per = (size_t)(l1.total - l0.total);
@@ -499,7 +499,7 @@ rtt_status launch_chain_cg(const rttk::ChainArgs& a0, hipStream_t s) {
   rttk::ChainArgs a = a0;
   dim3 grid((a.W + 16 * CG - 1) / (16 * CG));
   chain_checkpoints(a, CHI, CG, (int)grid.x);
-  const size_t lds = (size_t)rttk::ChainLayout(CHI, a.T, (a.L + 63) / 64, a.nw, CG, a.n_ck).total;
+  const size_t lds = (size_t)rttk::ChainLayout(CHI, a.T, (a.L + 63) / 64, a.nw, CG, a.n_ck, a.N).total;
   auto kfn = rttk::chain_kernel<D, CHI, CG, false>;
   if constexpr (CHI <= 64)
     if (a.n_ck > 0) kfn = rttk::chain_kernel<D, CHI, CG, true>;
@@ -517,7 +517,7 @@ template <class D, int CHI>
 rtt_status launch_chain(const rttk::ChainArgs& a, hipStream_t s) {
   if constexpr (CHI == 128) {
     const int LW = (a.L + 63) / 64;
-    const rttk::ChainLayout l1(CHI, a.T, LW, a.nw, 1), l2(CHI, a.T, LW, a.nw, 2);
+    const rttk::ChainLayout l1(CHI, a.T, LW, a.nw, 1, 0, a.N), l2(CHI, a.T, LW, a.nw, 2, 0, a.N);
     if (a.W >= 32 * device_cus() && l2.seq == l1.seq && (size_t)l2.total <= kLdsLimit)
       return launch_chain_cg<D, CHI, 2>(a, s);
   }
@@ -1487,7 +1487,7 @@ static rtt_status rtt_batch_create_impl(int32_t n, const rtt_t* rtts, const rtt_
       ca.T = h->T; ca.L = h->L; ca.N = h->N; ca.nw = h->nw; ca.LW = (h->L + 63) / 64; ca.W = W;
       ca.spins = b->spins[i]; ca.seed = seed; ca.rstream = (uint64_t)i; ca.mode = 1;
       c.chain.push_back(ca);
-      c.chain_lds = std::max(c.chain_lds, chain_lds_bytes(c.chi, h->T, h->L, h->nw));
+      c.chain_lds = std::max(c.chain_lds, chain_lds_bytes(c.chi, h->T, h->L, h->nw, h->N));
       rttk::PassArgs pa{};
       pa.core_exp = h->d_cexp; pa.nslot = h->sched.nslot; pa.L = h->L; pa.nw = h->nw; pa.W = W;
       pa.spins = b->spins[i];
