@@ -135,12 +135,13 @@ def cpu_baseline(w, n_walkers, n_steps):
                                     f"{dt_all:.1f} s"}}
 
 
-def cpu_baseline_rows(n_dual=48, n_narrow=1024):
-    """The FP64 oracle beside two more GPU lines, on samples of their
+def cpu_baseline_rows(n_dual=48, n_narrow=1024, n_wide=8):
+    """The FP64 oracle beside three more GPU lines, on samples of their
     workloads, single-threaded BLAS: a dual Monte Carlo step (one sweep per
     state, then overlap and mixed-energy estimators against all three
-    states; 8x8 chi=64) and a sweep plus local energies of a chi = 2 train
-    on the 10x10 H+V+D+D' path (400 positions, the narrow-kernel shape)."""
+    states; 8x8 chi=64), a sweep plus local energies of a chi = 2 train on
+    the 10x10 H+V+D+D' path (400 positions, the narrow-kernel shape), and
+    local energies of the 10x10 R=3 chi=128 workload (the wide-bond line)."""
     from threadpoolctl import threadpool_limits
 
     from oracle import dual, mcmc, rtt as orc, tfim
@@ -176,6 +177,14 @@ def cpu_baseline_rows(n_dual=48, n_narrow=1024):
                           "cores": 1, "kind": "oracle",
                           "sample": f"{n_narrow} walkers x 1 step on the 10x10 open H+V+D+D' chi=2 train, "
                                     f"FP64 numpy, {dt:.1f} s"}
+    ww = wl.WORKLOADS["tfim10x10_R3_chi128_W8192"]
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        orc.local_energy(ww.cores(), ww.pi(), ww.spins(n_wide), tfim.bonds(ww.Lx, ww.Ly), ww.J, ww.h)
+        dt = time.perf_counter() - t0
+    out["wide_chi128"] = {"value": n_wide / dt, "unit": "local-energy evals/s", "cores": 1, "kind": "oracle",
+                          "sample": f"{n_wide} walkers x 1 local-energy evaluation of the 10x10 R=3 chi=128 "
+                                    f"workload, FP64 cores, FP64 numpy, {dt:.1f} s"}
     return out
 
 
