@@ -250,6 +250,12 @@ struct Act<DF32, CHI> {
   __device__ __forceinline__ static void store1(float* row, int col, float x) { row[col] = x; }
   __device__ __forceinline__ static float get(const float* row, int i) { return row[i]; }
   __device__ __forceinline__ static void set_unit(float* row) { row[0] = 1.f; }
+  // the first dword of a stored unit vector e_0 (the rest are zero)
+  __device__ __forceinline__ static float unit_dword() { return 1.f; }
+  // copy the four activations at col..col+3 of a row
+  __device__ __forceinline__ static void copy4(float* dst, const float* src, int col) {
+    *reinterpret_cast<float4*>(dst + col) = *reinterpret_cast<const float4*>(src + col);
+  }
 };
 
 template <int CHI>
@@ -316,6 +322,13 @@ struct Act<DBF16, CHI> {
     return bf16_to_f32(hi(row)[i]) + bf16_to_f32(hi(row)[CHI + i]);
   }
   __device__ __forceinline__ static void set_unit(float* row) { hi(row)[0] = 0x3F80u; }
+  // the first dword of a stored unit vector e_0: hi[0] = 1, hi[1] = 0
+  __device__ __forceinline__ static float unit_dword() { return __uint_as_float(0x3F80u); }
+  // copy the four activations at col..col+3 of a row (hi and lo parts)
+  __device__ __forceinline__ static void copy4(float* dst, const float* src, int col) {
+    *reinterpret_cast<uint2*>(hi(dst) + col) = *reinterpret_cast<const uint2*>(hi(src) + col);
+    *reinterpret_cast<uint2*>(hi(dst) + CHI + col) = *reinterpret_cast<const uint2*>(hi(src) + CHI + col);
+  }
 };
 
 // ---------------------------------------------------------------- Philox4x64-10

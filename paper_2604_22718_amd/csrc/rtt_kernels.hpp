@@ -508,7 +508,12 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
 
   const E* cores = static_cast<const E*>(side == 0 ? a.cores : a.cores_bwd);
   struct Frags { E f0[KPL]; E f1[KPL]; };
+  // vectors are kept in LDS in the form the matrix ops take (Act: FP32, or
+  // the hi and lo BF16 parts), split once by the wave that writes them;
+  // renormalisation scales the products, not the stored inputs
+  using A = Act<D, CHI>;
   typename D::template BOp<KPL> bo[CG];
+  float psc[CG];
 
   // Results of the last segment: rb holds the rows, cb the columns (-1: the
   // right boundary vector itself).  Every wave knows both.
@@ -579,15 +584,18 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
 #pragma unroll
           for (int cg = 0; cg < CG; ++cg) {
             const int wn = 16 * cg + m;
-            float v[KPL];
+            psc[cg] = 1.f;
             if (cur < 0) {  // the right boundary vector e_0
+              float v[KPL];
 #pragma unroll
               for (int e = 0; e < KPL; ++e) v[e] = (g == 0 && e == 0) ? 1.f : 0.f;
+              D::template prep<KPL>(v, bo[cg]);
               if (wv == 0 && g == 0) Ec[t * NB + wn] = 0;
             } else {
-              lds_read<KPL>(v, buf(t, cur) + wn * RS + g * KPL);
+              A::template load_b<KPL>(buf(t, cur) + wn * RS, g, bo[cg]);
               if (i % kRenormEvery == 0) {
-                const int e = renorm_row<KPL>(v);
+                const int e = A::template row_exp<KPL>(bo[cg]);
+                psc[cg] = __builtin_amdgcn_ldexpf(1.f, -e);  // exact power of two
                 if (wv == 0 && g == 0) {
                   if (side == 1) {
                     Ec[t * NB + wn] = ((CKP && i == 0) ? ckexp(cur, t, wn) : Ec[t * NB + wn]) + e;
@@ -601,7 +609,6 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
                 }
               }
             }
-            D::template prep<KPL>(v, bo[cg]);
           }
         }
         const int tt = wv * MT + mt;
@@ -615,13 +622,13 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
 #pragma unroll
         for (int cg = 0; cg < CG; ++cg) {
           const int wn = 16 * cg + m;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) { c0[cg][q] *= psc[cg]; c1[cg][q] *= psc[cg]; }
           const f4 sel = bit[cg] ? c1[cg] : c0[cg];
-          *reinterpret_cast<float4*>(buf(t, out) + wn * RS + 16 * tt + 4 * g) =
-              make_float4(sel[0], sel[1], sel[2], sel[3]);
+          A::store4(buf(t, out) + wn * RS, 16 * tt + 4 * g, sel);
           if (split && side == 0 && i == 0) {
             const f4 oth = bit[cg] ? c0[cg] : c1[cg];
-            *reinterpret_cast<float4*>(buf(t, U) + wn * RS + 16 * tt + 4 * g) =
-                make_float4(oth[0], oth[1], oth[2], oth[3]);
+            A::store4(buf(t, U) + wn * RS, 16 * tt + 4 * g, oth);
           }
         }
         if (CKP && k == ckb) {  // columns only
@@ -630,8 +637,7 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
           for (int cg = 0; cg < CG; ++cg) {
             const int wn = 16 * cg + m;
             const f4 sel = bit[cg] ? c1[cg] : c0[cg];
-            *reinterpret_cast<float4*>(buf(t, slot) + wn * RS + 16 * tt + 4 * g) =
-                make_float4(sel[0], sel[1], sel[2], sel[3]);
+            A::store4(buf(t, slot) + wn * RS, 16 * tt + 4 * g, sel);
             if (wv == 0 && g == 0 && mt == 0) ckexp(slot, t, wn) = Ec[t * NB + wn];
           }
         }
@@ -681,12 +687,14 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
 #pragma unroll
       for (int cg = 0; cg < CG; ++cg) {
         const int wn = 16 * cg + m;
-        const float* r = buf(t, rb) + wn * RS + g * KPL;
+        float r[KPL];
+        A::template load_f32<KPL>(buf(t, rb) + wn * RS, g, r);
         double s = 0.0;
         if (cb < 0) {
           s = (g == 0) ? (double)r[0] : 0.0;
         } else {
-          const float* c = buf(t, cb) + wn * RS + g * KPL;
+          float c[KPL];
+          A::template load_f32<KPL>(buf(t, cb) + wn * RS, g, c);
           for (int e = 0; e < KPL; ++e) s = fma((double)r[e], (double)c[e], s);
         }
         s += __shfl_xor(s, 16);
@@ -727,7 +735,7 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
   auto reset_prefix = [&]() {
     for (int i = threadIdx.x; i < T * NB * RS; i += nthr) {
       const int t = i / (NB * RS), r = i % (NB * RS);
-      buf(t, P)[r] = (r % RS == 0) ? 1.f : 0.f;
+      buf(t, P)[r] = (r % RS == 0) ? A::unit_dword() : 0.f;
     }
     for (int i = threadIdx.x; i < T * NB; i += nthr) Ep[i] = 0;
   };
@@ -868,9 +876,8 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
             for (int cg = 0; cg < CG; ++cg)
 #pragma unroll
               for (int mt = 0; mt < MT; ++mt) {
-                const int off = (16 * cg + m) * RS + 16 * (wv * MT + mt) + 4 * g;
-                *reinterpret_cast<float4*>(buf(t, P) + off) =
-                    *reinterpret_cast<const float4*>(buf(t, accept[cg] ? F : U) + off);
+                const int off = (16 * cg + m) * RS;
+                A::copy4(buf(t, P) + off, buf(t, accept[cg] ? F : U) + off, 16 * (wv * MT + mt) + 4 * g);
               }
         }
         // checkpoints: the columns computed past lj hold the current
