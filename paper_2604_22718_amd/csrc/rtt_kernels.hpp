@@ -592,10 +592,19 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
               D::template prep<KPL>(v, bo[cg]);
               if (wv == 0 && g == 0) Ec[t * NB + wn] = 0;
             } else {
-              A::template load_b<KPL>(buf(t, cur) + wn * RS, g, bo[cg]);
+              // FP32 rows are renormalised in place as read; BF16 rows scale
+              // the products instead (their stored split stays as written)
+              float v[KPL];
+              if constexpr (sizeof(E) == 4) lds_read<KPL>(v, buf(t, cur) + wn * RS + g * KPL);
+              else A::template load_b<KPL>(buf(t, cur) + wn * RS, g, bo[cg]);
               if (i % kRenormEvery == 0) {
-                const int e = A::template row_exp<KPL>(bo[cg]);
-                psc[cg] = __builtin_amdgcn_ldexpf(1.f, -e);  // exact power of two
+                int e;
+                if constexpr (sizeof(E) == 4) {
+                  e = renorm_row<KPL>(v);
+                } else {
+                  e = A::template row_exp<KPL>(bo[cg]);
+                  psc[cg] = __builtin_amdgcn_ldexpf(1.f, -e);  // exact power of two
+                }
                 if (wv == 0 && g == 0) {
                   if (side == 1) {
                     Ec[t * NB + wn] = ((CKP && i == 0) ? ckexp(cur, t, wn) : Ec[t * NB + wn]) + e;
@@ -608,6 +617,7 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
                   }
                 }
               }
+              if constexpr (sizeof(E) == 4) D::template prep<KPL>(v, bo[cg]);
             }
           }
         }
@@ -622,8 +632,10 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
 #pragma unroll
         for (int cg = 0; cg < CG; ++cg) {
           const int wn = 16 * cg + m;
+          if constexpr (sizeof(E) == 2) {
 #pragma unroll
-          for (int q = 0; q < 4; ++q) { c0[cg][q] *= psc[cg]; c1[cg][q] *= psc[cg]; }
+            for (int q = 0; q < 4; ++q) { c0[cg][q] *= psc[cg]; c1[cg][q] *= psc[cg]; }
+          }
           const f4 sel = bit[cg] ? c1[cg] : c0[cg];
           A::store4(buf(t, out) + wn * RS, 16 * tt + 4 * g, sel);
           if (split && side == 0 && i == 0) {
