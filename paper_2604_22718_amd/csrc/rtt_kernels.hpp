@@ -315,9 +315,12 @@ __device__ __forceinline__ void combine_body(const CombineArgs& a, int bx) {
         combined_value(a, w, a.grp[j], fs, bs, c16, mj, ej);
         if (mj == 0.0) { lr = -INFINITY; sg = 1; r = 0.0; }
         else {
-          lr = log(fabs(mj)) - log(fabs(m0)) + (double)(ej - e0) * LN2;
+          // the ratio from the mantissa quotient and the exponent difference
+          // (no logarithms unless log-ratios are asked for)
+          const double qm = fabs(mj) / fabs(m0);
           sg = ((mj > 0) == (m0 > 0)) ? 1 : -1;
-          r = sg * exp(lr);
+          r = sg * ldexp(qm, ej - e0);
+          if (a.logratio) lr = log(qm) + (double)(ej - e0) * LN2;
         }
       }
     }
