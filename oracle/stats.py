@@ -21,13 +21,19 @@ def fsum_mean(x) -> float:
 
 def autocorr(series) -> np.ndarray:
     """Normalised autocorrelation rho(t) of a (T,) or (T, W) series; for many
-    walkers the covariances are averaged over walkers."""
+    walkers the covariances are averaged over walkers.  A series without
+    fluctuations (zero variance, e.g. E_loc of an exact eigenstate) has no
+    correlations to measure: rho = (1, 0, 0, ...), so tau_int = 1."""
     x = np.asarray(series, dtype=np.float64)
     if x.ndim == 1:
         x = x[:, None]
     T = x.shape[0]
     d = x - x.mean()
     c = np.array([np.mean(d[: T - t] * d[t:]) for t in range(T)])
+    if not c[0] > 0.0:
+        rho = np.zeros(T)
+        rho[0] = 1.0
+        return rho
     return c / c[0]
 
 

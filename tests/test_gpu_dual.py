@@ -169,8 +169,7 @@ def test_z_only_shortcut_single_chain(R):
     for X, ex in ((Hs, Ht_ex), (Ss, St_ex)):
         for a in range(3):
             for b in range(3):
-                m, s, _, _ = stats.energy_estimate(X[:, a, b:b + 1])
-                s = s if np.isfinite(s) else 0.0          # constant series (S~_aa = 1)
+                m, s, _, _ = stats.energy_estimate(X[:, a, b:b + 1])   # S~_aa = 1: sigma 0
                 assert abs(m - ex[a, b]) < 3 * s + 1e-5 * (1.0 + abs(ex[a, b])), (a, b, m, ex[a, b], s)
 
 

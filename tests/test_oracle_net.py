@@ -112,3 +112,42 @@ def test_shared_initial_weights_match_the_oracle_draw():
     from paper_2604_22718_amd import workloads as wl
     for seed in (3, 33, 4004):
         assert np.array_equal(wl.net_init_params(seed), net.init_params(seed))
+
+
+def test_sample_move_is_the_inverse_cdf():
+    """sample_move draws the centre c and then the size k by inverse CDF: the
+    first index whose cumulative probability exceeds the uniform.  Pinned on
+    both sides of every cell boundary (a relative 1e-12 below a cumulative
+    value stays in the cell, as far above moves to the next one) and by the
+    frequencies of (c, k) under many seeded uniforms, which must follow
+    p(c) p(k | c) (binomial bounds per cell and a chi-square over all cells).
+    An off-by-one in c or k, the size drawn from the wrong axis or from
+    unnormalised weights each fail one of these."""
+    N = 6
+    o = np.random.default_rng(11).standard_normal((9, N)) * 1.3
+    pc = np.exp(o[0] - o[0].max()); pc /= pc.sum()
+    pk = np.exp(o[1:9] - o[1:9].max(axis=0)); pk /= pk.sum(axis=0)   # (8, N)
+    cum_c = np.cumsum(pc)
+    lo, hi = 1.0 - 1e-12, 1.0 + 1e-12
+    for i in range(N - 1):      # centre cells (size uniform 0: k = 1)
+        assert net.sample_move(o, cum_c[i] * lo, 0.0) == (i, 1)
+        assert net.sample_move(o, cum_c[i] * hi, 0.0) == (i + 1, 1)
+    assert net.sample_move(o, 0.0, 0.0) == (0, 1)
+    assert net.sample_move(o, 1.0 - 1e-12, 0.0)[0] == N - 1
+    for c in range(N):          # size cells at every centre
+        uc = 0.5 * (cum_c[c] + (0.0 if c == 0 else cum_c[c - 1]))
+        cum_k = np.cumsum(pk[:, c])
+        for k in range(1, 8):
+            assert net.sample_move(o, uc, cum_k[k - 1] * lo) == (c, k)
+            assert net.sample_move(o, uc, cum_k[k - 1] * hi) == (c, k + 1)
+        assert net.sample_move(o, uc, 1.0 - 1e-12) == (c, 8)
+    n = 60000                   # frequencies
+    u = wl.generator(12).random((n, 2))
+    counts = np.zeros((N, 8))
+    for uc, uk in u:
+        c, k = net.sample_move(o, uc, uk)
+        counts[c, k - 1] += 1
+    p = pc[:, None] * pk.T                                # (N, 8)
+    assert np.all(np.abs(counts - n * p) <= 5 * np.sqrt(n * p * (1 - p)) + 1)
+    chi2 = float(np.sum((counts - n * p) ** 2 / (n * p)))
+    assert chi2 < 47 + 5 * math.sqrt(2 * 47)               # 47 degrees of freedom

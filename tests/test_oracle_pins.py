@@ -373,6 +373,14 @@ def test_fsum_and_tau_int_ar1():
         blk = stats.blocking_error(y[:, 0])
         naive = math.sqrt(np.var(y[:, 0]) / T)
         assert blk / naive == pytest.approx(math.sqrt((1 + rho) / (1 - rho)), rel=0.25)
+    # zero variance (E_loc of an exact eigenstate): no correlation, tau = 1,
+    # sigma_E = 0, and no division by zero on the way
+    const = np.full((50, 4), -3.25)
+    with np.errstate(all="raise"):
+        assert stats.tau_int(const) == 1.0
+        assert list(stats.autocorr(const[:, 0])[:3]) == [1.0, 0.0, 0.0]
+        mean, sigma, tau, var = stats.energy_estimate(const)
+    assert (mean, sigma, tau, var) == (-3.25, 0.0, 1.0, 0.0)
 
 
 def test_quantisation():
