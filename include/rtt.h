@@ -22,7 +22,12 @@
  *     Z_j |s> = (1 - 2 s_j) |s>.
  *   - `stream` is a hipStream_t (NULL = the null stream).  Evaluation and
  *     sampling calls only enqueue work on it and never synchronise; create,
- *     lincomb and destroy synchronise the device.
+ *     lincomb and destroy synchronise the device.  Workspace a call needs
+ *     beyond what a handle already holds (flip-ratio rows for more walkers
+ *     than any earlier call, proposal buffers) comes from HIP's
+ *     stream-ordered allocator on `stream`, which does not synchronise
+ *     either; a handle's workspace is used by one stream at a time, so calls
+ *     on one handle (RTT or network) must not overlap on different streams.
  *   - A walker whose amplitude is zero or not finite gets status
  *     RTT_E_NONFINITE in the optional per-walker status array and NaN
  *     outputs; it is never skipped silently and never advanced by sampling.
@@ -197,7 +202,7 @@ rtt_status rtt_mcmc_sweep(rtt_t h, int32_t W, uint64_t* spins, double* logabs,
  *   status     device int32[W] or NULL: 0, or RTT_E_NONFINITE (-5) if the
  *              sampled or any target amplitude is zero or non-finite (that
  *              walker's outputs are NaN)
- * Each target keeps a W-sized workspace, grown on demand (hipMalloc);
+ * Each target keeps a W-sized workspace, grown on demand in stream order;
  * calls on one target must not overlap.  Errors: RTT_E_ARG for null
  * pointers, M < 1, W < 1, invalid handles or spin counts differing from the
  * lattice; otherwise as rtt_evaluate.

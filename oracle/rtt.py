@@ -176,3 +176,41 @@ def flip_condition_numbers(cores, pi, spins) -> np.ndarray:
     k0 = condition_numbers(cores, pi, spins)
     return np.stack([np.maximum(k0, condition_numbers(cores, pi, flip(spins, j)))
                      for j in range(spins.shape[1])], axis=1)
+
+
+def lincomb_condition_numbers(terms, coeffs, pi, spins) -> np.ndarray:
+    """kappa(s) of psi = sum_a c_a psi^a evaluated term by term:
+    max over bonds c of sum_a |c_a| ||l^a_c(s)|| ||r^a_c(s)|| / |psi(s)|, with
+    l^a_c, r^a_c the row and column products of term a split at bond c (as in
+    condition_numbers).  Each term's product at bond c carries rounding error
+    ~ gamma ||l^a_c|| ||r^a_c||, so this measures the cancellation an
+    evaluation that sums the terms' amplitudes must resolve.  It is >= 1
+    (triangle and Cauchy-Schwarz inequalities), equals condition_numbers for
+    one term with coefficient 1, and is at most the kappa of the direct-sum
+    train (Cauchy-Schwarz over the terms)."""
+    spins = np.asarray(spins)
+    W = spins.shape[0]
+    L = len(terms[0])
+    num = np.zeros((L + 1, W))
+    psi = np.zeros(W)
+    for ca, cores in zip(coeffs, terms):
+        left = [np.ones((W, 1))]
+        for k in range(L):
+            left.append(np.einsum("wa,wab->wb", left[-1], cores[k][spins[:, int(pi[k])].astype(np.int64)]))
+        right = [np.ones((W, 1))]
+        for k in reversed(range(L)):
+            right.append(np.einsum("wab,wb->wa", cores[k][spins[:, int(pi[k])].astype(np.int64)], right[-1]))
+        right = right[::-1]
+        psi = psi + ca * left[-1][:, 0]
+        num += abs(ca) * np.stack([np.linalg.norm(left[c], axis=1) * np.linalg.norm(right[c], axis=1)
+                                   for c in range(L + 1)])
+    with np.errstate(divide="ignore"):
+        return num.max(axis=0) / np.abs(psi)
+
+
+def lincomb_flip_condition_numbers(terms, coeffs, pi, spins) -> np.ndarray:
+    """max(kappa(s), kappa(s with s_j flipped)) of a linear combination, (W, N)."""
+    spins = np.asarray(spins)
+    k0 = lincomb_condition_numbers(terms, coeffs, pi, spins)
+    return np.stack([np.maximum(k0, lincomb_condition_numbers(terms, coeffs, pi, flip(spins, j)))
+                     for j in range(spins.shape[1])], axis=1)

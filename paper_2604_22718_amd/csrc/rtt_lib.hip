@@ -279,12 +279,18 @@ rtt_status upload(void** dst, const void* src, size_t bytes) {
   return RTT_OK;
 }
 
+// Frees every device buffer of a handle; the caller has synchronised.  The
+// workspace came from the stream-ordered allocator and goes back to it.
 void free_dev(rtt_s* h) {
   void* ptrs[] = {h->d_grp, h->d_fgs, h->d_bgs, h->d_fwd, h->d_bwd, h->d_cexp, h->d_cesum, h->d_rmask, h->d_sf, h->d_sb, h->d_fslot, h->d_bslot,
-                  h->d_pi, h->d_order, h->d_first, h->d_coeffs, h->d_u, h->d_v, h->d_ue, h->d_ve,
-                  h->d_mla, h->d_msg, h->d_mel, h->d_mst, h->d_ncores};
+                  h->d_pi, h->d_order, h->d_first, h->d_coeffs, h->d_ncores};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
+  void* ws[] = {h->d_u, h->d_v, h->d_ue, h->d_ve, h->d_mla, h->d_msg, h->d_mel, h->d_mst};
+  bool any = false;
+  for (void* p : ws)
+    if (p) { (void)hipFreeAsync(p, nullptr); any = true; }
+  if (any) (void)hipDeviceSynchronize();
 }
 
 // Quantised copy of the cores (rtt_create layout) and per-position exponents.
@@ -436,18 +442,27 @@ rtt_status finish_create(rtt_s* h) {
   return RTT_OK;
 }
 
-rtt_status ensure_ws(rtt_s* h, int W) {
+// Grow a workspace buffer in stream order (the stream-ordered allocator):
+// the old buffer is released after the work already queued on `s`, the new
+// one is ready for the work queued after it, and the device is never
+// synchronised.  Workspace of a handle therefore belongs to one stream at a
+// time.
+rtt_status grow_async(void** p, size_t bytes, hipStream_t s) {
+  if (*p) HIPX(hipFreeAsync(*p, s));
+  *p = nullptr;
+  HIPX(hipMallocAsync(p, std::max<size_t>(bytes, 16), s));
+  return RTT_OK;
+}
+
+rtt_status ensure_ws(rtt_s* h, int W, hipStream_t s) {
   if ((size_t)W <= h->ws_W) return RTT_OK;
-  for (void* p : {(void*)h->d_u, (void*)h->d_v, (void*)h->d_ue, (void*)h->d_ve})
-    if (p) HIPX(hipFree(p));
-  h->d_u = h->d_v = nullptr;
-  h->d_ue = h->d_ve = nullptr;
   h->ws_W = 0;
   const size_t rows = (size_t)h->T * h->sched.ng * W * h->sched.nslot;
-  HIPX(hipMalloc(&h->d_u, rows * h->chi * 4));
-  HIPX(hipMalloc(&h->d_v, rows * h->chi * 4));
-  HIPX(hipMalloc(&h->d_ue, rows * 4));
-  HIPX(hipMalloc(&h->d_ve, rows * 4));
+  rtt_status st;
+  if ((st = grow_async((void**)&h->d_u, rows * h->chi * 4, s)) != RTT_OK) return st;
+  if ((st = grow_async((void**)&h->d_v, rows * h->chi * 4, s)) != RTT_OK) return st;
+  if ((st = grow_async((void**)&h->d_ue, rows * 4, s)) != RTT_OK) return st;
+  if ((st = grow_async((void**)&h->d_ve, rows * 4, s)) != RTT_OK) return st;
   h->ws_W = W;
   return RTT_OK;
 }
@@ -481,12 +496,19 @@ void chain_checkpoints(rttk::ChainArgs& a, int chi, int cg, int blocks) {
   const int lo = a.ck_first, LW = (a.L + 63) / 64;
   a.n_ck = 0; a.ck_first = 0; a.ck_step = 1;
   if (a.mode != 1 || lo >= a.L || lo < 1 || chi > 64) return;
-  const rttk::ChainLayout l0(chi, a.T, LW, a.nw, cg, 0, a.N), l1(chi, a.T, LW, a.nw, cg, 1, a.N);
+  const rttk::ChainLayout l0(chi, a.T, LW, a.nw, cg, 0, a.N);
   if (l0.seq) return;
   const size_t budget = kLdsLimit / (blocks > device_cus() ? 2 : 1);
-  const size_t per = (size_t)(l1.total - l0.total);
-  if ((size_t)l0.total + per > budget) return;
-  const int nmax = std::min<int>(16, (int)((budget - l0.total) / per));
+  // the largest count whose layout fits, preferring counts that keep the
+  // replica bitmasks in LDS as they are without checkpoints (each layout is
+  // sized in full: the masks may stop fitting as checkpoints are added)
+  int nmax = 0;
+  for (int pass = 0; pass < 2 && nmax == 0; ++pass)
+    for (int n = 16; n >= 1; --n) {
+      const rttk::ChainLayout ln(chi, a.T, LW, a.nw, cg, n, a.N);
+      if ((size_t)ln.total <= budget && (pass == 1 || ln.rml == l0.rml)) { nmax = n; break; }
+    }
+  if (nmax < 1) return;
   const int span = a.L - lo;
   const int step = (span + nmax - 1) / nmax;
   a.n_ck = (span + step - 1) / step;
@@ -887,7 +909,7 @@ rtt_status rtt_evaluate(rtt_t h, rtt_ham_t ham, int32_t W, const uint64_t* spins
     na.status = status;
     return h->narrow == 2 ? launch_narrow_eval<2>(na, s) : launch_narrow_eval<4>(na, s);
   }
-  rtt_status st = ensure_ws(h, W);
+  rtt_status st = ensure_ws(h, W, s);
   if (st != RTT_OK) return st;
   const size_t tslice = (size_t)h->L * 2 * h->chi * h->chi * elem_bytes(h->dtype);
   (void)tslice;
@@ -1018,14 +1040,12 @@ rtt_status rtt_mixed_estimators(int32_t M, const rtt_t* targets, rtt_ham_t ham, 
   for (int m = 0; m < M; ++m) {
     rtt_s* b = targets[m];
     if ((size_t)W > b->mix_W) {
-      for (void* p : {(void*)b->d_mla, (void*)b->d_msg, (void*)b->d_mel, (void*)b->d_mst})
-        if (p) HIPX(hipFree(p));
-      b->d_mla = nullptr; b->d_msg = nullptr; b->d_mel = nullptr; b->d_mst = nullptr;
       b->mix_W = 0;
-      HIPX(hipMalloc(&b->d_mla, (size_t)W * 8));
-      HIPX(hipMalloc(&b->d_msg, (size_t)W));
-      HIPX(hipMalloc(&b->d_mel, (size_t)W * 8));
-      HIPX(hipMalloc(&b->d_mst, (size_t)W * 4));
+      rtt_status st;
+      if ((st = grow_async((void**)&b->d_mla, (size_t)W * 8, s)) != RTT_OK) return st;
+      if ((st = grow_async((void**)&b->d_msg, (size_t)W, s)) != RTT_OK) return st;
+      if ((st = grow_async((void**)&b->d_mel, (size_t)W * 8, s)) != RTT_OK) return st;
+      if ((st = grow_async((void**)&b->d_mst, (size_t)W * 4, s)) != RTT_OK) return st;
       b->mix_W = W;
     }
     rtt_status st = rtt_evaluate(b, ham, W, spins, b->d_mla, b->d_msg, nullptr, nullptr, b->d_mel, b->d_mst,
@@ -1649,23 +1669,26 @@ namespace {
 
 void free_net(rtt_net_s* n) {
   for (void* p : {(void*)n->d_master, (void*)n->d_infer, (void*)n->d_m, (void*)n->d_v, (void*)n->d_grad,
-                  (void*)n->d_baseline, (void*)n->d_prop, (void*)n->d_moves, (void*)n->d_lqf,
-                  (void*)n->d_lqr, (void*)n->d_la, (void*)n->d_sg, (void*)n->d_st, (void*)n->d_partial})
+                  (void*)n->d_baseline})
     if (p) (void)hipFree(p);
+  bool any = false;
+  for (void* p : {(void*)n->d_prop, (void*)n->d_moves, (void*)n->d_lqf, (void*)n->d_lqr, (void*)n->d_la,
+                  (void*)n->d_sg, (void*)n->d_st, (void*)n->d_partial})
+    if (p) { (void)hipFreeAsync(p, nullptr); any = true; }
+  if (any) (void)hipDeviceSynchronize();
 }
 
-rtt_status net_ws(rtt_net_s* n, int W) {
+rtt_status net_ws(rtt_net_s* n, int W, hipStream_t s) {
   if (W <= n->W_ws) return RTT_OK;
-  for (void* p : {(void*)n->d_prop, (void*)n->d_moves, (void*)n->d_lqf, (void*)n->d_lqr, (void*)n->d_la,
-                  (void*)n->d_sg, (void*)n->d_st})
-    if (p) HIPX(hipFree(p));
-  HIPX(hipMalloc(&n->d_prop, (size_t)W * n->nw * 8));
-  HIPX(hipMalloc(&n->d_moves, (size_t)W * 4));
-  HIPX(hipMalloc(&n->d_lqf, (size_t)W * 8));
-  HIPX(hipMalloc(&n->d_lqr, (size_t)W * 8));
-  HIPX(hipMalloc(&n->d_la, (size_t)W * 8));
-  HIPX(hipMalloc(&n->d_sg, (size_t)W));
-  HIPX(hipMalloc(&n->d_st, (size_t)W * 4));
+  n->W_ws = 0;
+  rtt_status st;
+  if ((st = grow_async((void**)&n->d_prop, (size_t)W * n->nw * 8, s)) != RTT_OK) return st;
+  if ((st = grow_async((void**)&n->d_moves, (size_t)W * 4, s)) != RTT_OK) return st;
+  if ((st = grow_async((void**)&n->d_lqf, (size_t)W * 8, s)) != RTT_OK) return st;
+  if ((st = grow_async((void**)&n->d_lqr, (size_t)W * 8, s)) != RTT_OK) return st;
+  if ((st = grow_async((void**)&n->d_la, (size_t)W * 8, s)) != RTT_OK) return st;
+  if ((st = grow_async((void**)&n->d_sg, (size_t)W, s)) != RTT_OK) return st;
+  if ((st = grow_async((void**)&n->d_st, (size_t)W * 4, s)) != RTT_OK) return st;
   n->W_ws = W;
   return RTT_OK;
 }
@@ -1678,10 +1701,9 @@ rtt_status net_set_lds(const void* f, size_t bytes) {
 rtt_status net_grad_launch(rtt_net_s* n, int B, const uint64_t* spins, const int32_t* moves,
                            const float* accept_prob, float* grad, hipStream_t s) {
   if (B > n->B_ws) {
-    if (n->d_partial) HIPX(hipFree(n->d_partial));
-    n->d_partial = nullptr;
     n->B_ws = 0;
-    HIPX(hipMalloc(&n->d_partial, (size_t)B * rttk::kNetParams * 4));
+    rtt_status st = grow_async((void**)&n->d_partial, (size_t)B * rttk::kNetParams * 4, s);
+    if (st != RTT_OK) return st;
     n->B_ws = B;
   }
   rttk::NetGradArgs ga{};
@@ -1774,7 +1796,7 @@ rtt_status rtt_mh_learned_step(rtt_t h, rtt_net_t n, int32_t W, uint64_t* spins,
   if (!n || W < 1 || !spins || !logabs || !sign) return fail(RTT_E_ARG, "rtt_mh_learned_step: bad argument");
   if (n->N != h->N) return fail(RTT_E_ARG, "rtt_mh_learned_step: network has %d sites, RTT %d spins", n->N, h->N);
   hipStream_t s = (hipStream_t)stream;
-  rtt_status st = net_ws(n, W);
+  rtt_status st = net_ws(n, W, s);
   if (st != RTT_OK) return st;
   rttk::NetMoveArgs a{};
   a.P = n->d_infer; a.Lx = n->Lx; a.Ly = n->Ly; a.nw = n->nw; a.W = W; a.spins = spins;

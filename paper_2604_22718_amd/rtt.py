@@ -17,11 +17,50 @@ from ._lib import check, lib
 DTYPES = {"f32": 1, "bf16": 2, "fp8": 3}
 
 
-def _ptr(t):
+def _ptr(t, name="tensor", dtypes=None, numel=None):
+    """Device pointer of a contiguous CUDA tensor of one of ``dtypes`` with
+    ``numel`` elements (None: no such check); None passes through.  The
+    kernels read and write exactly that many elements, so anything else is
+    refused here instead of becoming an out-of-bounds access on the GPU."""
     if t is None:
         return None
-    assert t.is_cuda and t.is_contiguous(), "device tensors must be contiguous CUDA tensors"
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name}: expected a torch.Tensor, got {type(t).__name__}")
+    if dtypes is not None and t.dtype not in dtypes:
+        raise TypeError(f"{name}: dtype {t.dtype}, expected one of {[str(d) for d in dtypes]}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name}: {t.numel()} elements, expected {numel}")
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name}: device tensors must be contiguous CUDA tensors")
     return C.c_void_p(t.data_ptr())
+
+
+F64, F32, I32, I8, I64 = (torch.float64,), (torch.float32,), (torch.int32,), (torch.int8,), (torch.int64,)
+U32 = (torch.int32, torch.uint32)   # accept counts: the library adds uint32 values
+
+
+def _spins_ptr(spins, nw, name="spins"):
+    """spins: int64 [W][nw] holding the uint64 spin words; returns (W, ptr)."""
+    if not isinstance(spins, torch.Tensor) or spins.dim() != 2 or spins.shape[1] != nw:
+        shape = tuple(spins.shape) if isinstance(spins, torch.Tensor) else type(spins).__name__
+        raise ValueError(f"{name}: expected an int64 tensor [W][{nw}], got {shape}")
+    W = int(spins.shape[0])
+    if W < 1:
+        raise ValueError(f"{name}: no walkers")
+    return W, _ptr(spins, name, I64)
+
+
+def _words(h):
+    """Spin count and words per walker of an RTT handle."""
+    info = np.zeros(10, dtype=np.int32)
+    check(lib().rtt_info(h, info.ctypes.data))
+    return int(info[0]), int(info[5])
+
+
+# spin counts of the network handles created here (the C ABI keeps them opaque)
+_NET_SITES = {}
+# run counts of the batch handles created here
+_BATCH_RUNS = {}
 
 
 def _stream():
@@ -75,31 +114,41 @@ def rtt_tfim_destroy(H):
 
 def rtt_evaluate(h, ham, spins, logabs=None, sign=None, logratio=None, rsign=None, eloc=None,
                  status=None):
-    check(lib().rtt_evaluate(h, ham, spins.shape[0], _ptr(spins), _ptr(logabs), _ptr(sign),
-                             _ptr(logratio), _ptr(rsign), _ptr(eloc), _ptr(status), _stream()))
+    N, nw = _words(h)
+    W, sp = _spins_ptr(spins, nw)
+    check(lib().rtt_evaluate(h, ham, W, sp, _ptr(logabs, "logabs", F64, W), _ptr(sign, "sign", I8, W),
+                             _ptr(logratio, "logratio", F64, W * N), _ptr(rsign, "rsign", I8, W * N),
+                             _ptr(eloc, "eloc", F64, W), _ptr(status, "status", I32, W), _stream()))
 
 
 def rtt_amplitudes(h, spins, logabs, sign):
-    check(lib().rtt_amplitudes(h, spins.shape[0], _ptr(spins), _ptr(logabs), _ptr(sign), _stream()))
+    W, sp = _spins_ptr(spins, _words(h)[1])
+    check(lib().rtt_amplitudes(h, W, sp, _ptr(logabs, "logabs", F64, W), _ptr(sign, "sign", I8, W),
+                               _stream()))
 
 
 def rtt_flip_ratios(h, spins, logratio, rsign):
-    check(lib().rtt_flip_ratios(h, spins.shape[0], _ptr(spins), _ptr(logratio), _ptr(rsign), _stream()))
+    N, nw = _words(h)
+    W, sp = _spins_ptr(spins, nw)
+    check(lib().rtt_flip_ratios(h, W, sp, _ptr(logratio, "logratio", F64, W * N),
+                                _ptr(rsign, "rsign", I8, W * N), _stream()))
 
 
 def rtt_local_energy(h, ham, spins, eloc):
-    check(lib().rtt_local_energy(h, ham, spins.shape[0], _ptr(spins), _ptr(eloc), _stream()))
+    W, sp = _spins_ptr(spins, _words(h)[1])
+    check(lib().rtt_local_energy(h, ham, W, sp, _ptr(eloc, "eloc", F64, W), _stream()))
 
 
 def rtt_mcmc_sweep(h, spins, seed, rng_stream, sweep0, n_sweeps, logabs=None, sign=None,
                    accepts=None, status=None):
-    check(lib().rtt_mcmc_sweep(h, spins.shape[0], _ptr(spins), _ptr(logabs), _ptr(sign),
+    W, sp = _spins_ptr(spins, _words(h)[1])
+    check(lib().rtt_mcmc_sweep(h, W, sp, _ptr(logabs, "logabs", F64, W), _ptr(sign, "sign", I8, W),
                                int(seed), int(rng_stream), int(sweep0), int(n_sweeps),
-                               _ptr(accepts), _ptr(status), _stream()))
+                               _ptr(accepts, "accepts", U32, W), _ptr(status, "status", I32, W), _stream()))
 
 
 def rtt_energy_reduce(x, out):
-    check(lib().rtt_energy_reduce(x.numel(), _ptr(x), _ptr(out), _stream()))
+    check(lib().rtt_energy_reduce(x.numel(), _ptr(x, "x", F64), _ptr(out, "out", F64, 3), _stream()))
 
 
 def _flat_cores(cores):
@@ -196,14 +245,25 @@ def rtt_tt_combine(trains, coeffs, chi_max, rel_tol=1e-14):
 def rtt_mixed_estimators(targets, ham, spins, logabs_a, sign_a, ratio, mixed, status=None):
     """targets: list of RTT handles; ratio, mixed: float64 [M][W] device tensors."""
     M = len(targets)
+    if M < 1:
+        raise ValueError("rtt_mixed_estimators: no targets")
     arr = (C.c_void_p * M)(*[t.value for t in targets])
-    W = spins.shape[0]
-    check(lib().rtt_mixed_estimators(M, C.cast(arr, C.c_void_p), ham, W, _ptr(spins), _ptr(logabs_a),
-                                      _ptr(sign_a), _ptr(ratio), _ptr(mixed), _ptr(status), _stream()))
+    W, sp = _spins_ptr(spins, _words(targets[0])[1])
+    check(lib().rtt_mixed_estimators(M, C.cast(arr, C.c_void_p), ham, W, sp, _ptr(logabs_a, "logabs_a", F64, W),
+                                      _ptr(sign_a, "sign_a", I8, W), _ptr(ratio, "ratio", F64, M * W),
+                                      _ptr(mixed, "mixed", F64, M * W), _ptr(status, "status", I32, W),
+                                      _stream()))
 
 
 def rtt_batch_create(rtts, hams, walkers, spins, eloc, seed):
     n = len(rtts)
+    if not (len(hams) == len(walkers) == len(spins) == len(eloc) == n) or n < 1:
+        raise ValueError("rtt_batch_create: one Hamiltonian, walker count, spin and energy buffer per run")
+    for i in range(n):
+        Wi, _ = _spins_ptr(spins[i], _words(rtts[i])[1], f"spins[{i}]")
+        if Wi != int(walkers[i]):
+            raise ValueError(f"rtt_batch_create: run {i} has {Wi} spin rows for {walkers[i]} walkers")
+        _ptr(eloc[i], f"eloc[{i}]", F64, Wi)
     arr = lambda xs: (C.c_void_p * n)(*xs)
     w = np.ascontiguousarray(walkers, dtype=np.int32)
     b = C.c_void_p()
@@ -212,11 +272,14 @@ def rtt_batch_create(rtts, hams, walkers, spins, eloc, seed):
                                  C.cast(arr([t.data_ptr() for t in spins]), C.c_void_p),
                                  C.cast(arr([t.data_ptr() for t in eloc]), C.c_void_p),
                                  int(seed), C.byref(b)))
+    _BATCH_RUNS[b.value] = n
     return b
 
 
 def rtt_batch_step(b, n_sweeps, esum=None):
-    check(lib().rtt_batch_step(b, int(n_sweeps), _ptr(esum), _stream()))
+    n = _BATCH_RUNS.get(b.value)
+    check(lib().rtt_batch_step(b, int(n_sweeps), _ptr(esum, "esum", F64, None if n is None else 3 * n),
+                               _stream()))
 
 
 def rtt_batch_autotune(b, n_sweeps, reps, cache_path=None):
@@ -229,6 +292,7 @@ def rtt_batch_autotune(b, n_sweeps, reps, cache_path=None):
 
 def rtt_batch_destroy(b):
     check(lib().rtt_batch_destroy(b))
+    _BATCH_RUNS.pop(b.value, None)
 
 
 N_NET_PARAMS = 19113
@@ -236,14 +300,23 @@ N_NET_PARAMS = 19113
 
 def rtt_net_create(Lx, Ly, params):
     p = np.ascontiguousarray(params, dtype=np.float64)
-    assert p.size == N_NET_PARAMS
+    if p.size != N_NET_PARAMS:
+        raise ValueError(f"rtt_net_create: {p.size} parameters, expected {N_NET_PARAMS}")
     h = C.c_void_p()
     check(lib().rtt_net_create(int(Lx), int(Ly), p.ctypes.data, C.byref(h)))
+    _NET_SITES[h.value] = int(Lx) * int(Ly)
     return h
 
 
 def rtt_net_destroy(h):
     check(lib().rtt_net_destroy(h))
+    _NET_SITES.pop(h.value, None)
+
+
+def _net_sites(h):
+    if h is None or h.value not in _NET_SITES:
+        raise ValueError("unknown network handle")
+    return _NET_SITES[h.value]
 
 
 def rtt_net_get_params(h, which=0):
@@ -253,24 +326,37 @@ def rtt_net_get_params(h, which=0):
 
 
 def rtt_net_forward(h, spins, out):
-    check(lib().rtt_net_forward(h, spins.shape[0], _ptr(spins), _ptr(out), _stream()))
+    N = _net_sites(h)
+    W, sp = _spins_ptr(spins, (N + 63) // 64)
+    check(lib().rtt_net_forward(h, W, sp, _ptr(out, "out", F32, W * 9 * N), _stream()))
 
 
 def rtt_mh_learned_step(rtt_h, net_h, spins, logabs, sign, seed, rng_stream, step, moves=None,
                         accept_prob=None, before=None, accepts=None, status=None):
-    check(lib().rtt_mh_learned_step(rtt_h, net_h, spins.shape[0], _ptr(spins), _ptr(logabs), _ptr(sign),
-                                    int(seed), int(rng_stream), int(step), _ptr(moves), _ptr(accept_prob),
-                                    _ptr(before), _ptr(accepts), _ptr(status), _stream()))
+    N, nw = _words(rtt_h)
+    W, sp = _spins_ptr(spins, nw)
+    if before is not None and tuple(before.shape) != tuple(spins.shape):
+        raise ValueError(f"before: shape {tuple(before.shape)}, expected {tuple(spins.shape)}")
+    check(lib().rtt_mh_learned_step(rtt_h, net_h, W, sp, _ptr(logabs, "logabs", F64, W),
+                                    _ptr(sign, "sign", I8, W), int(seed), int(rng_stream), int(step),
+                                    _ptr(moves, "moves", I32, W), _ptr(accept_prob, "accept_prob", F32, W),
+                                    _ptr(before, "before", I64, W * nw), _ptr(accepts, "accepts", U32, W),
+                                    _ptr(status, "status", I32, W), _stream()))
+
+
+def _train_args(h, spins, moves, accept_prob):
+    B, sp = _spins_ptr(spins, (_net_sites(h) + 63) // 64)
+    return B, sp, _ptr(moves, "moves", I32, B), _ptr(accept_prob, "accept_prob", F32, B)
 
 
 def rtt_net_grad(h, spins, moves, accept_prob, grad):
-    check(lib().rtt_net_grad(h, spins.shape[0], _ptr(spins), _ptr(moves), _ptr(accept_prob), _ptr(grad),
-                             _stream()))
+    B, sp, mv, ap = _train_args(h, spins, moves, accept_prob)
+    check(lib().rtt_net_grad(h, B, sp, mv, ap, _ptr(grad, "grad", F32, N_NET_PARAMS), _stream()))
 
 
 def rtt_net_train(h, spins, moves, accept_prob, lr, beta1=0.9, beta2=0.999, eps=1e-8):
-    check(lib().rtt_net_train(h, spins.shape[0], _ptr(spins), _ptr(moves), _ptr(accept_prob),
-                              float(lr), float(beta1), float(beta2), float(eps), _stream()))
+    B, sp, mv, ap = _train_args(h, spins, moves, accept_prob)
+    check(lib().rtt_net_train(h, B, sp, mv, ap, float(lr), float(beta1), float(beta2), float(eps), _stream()))
 
 
 # ---------------------------------------------------------------- convenience

@@ -77,3 +77,37 @@ def test_other_entry_points_reject_null_handles(lib):
     assert lib.rtt_tfim_create(4, 4, 1, float("nan"), 3.0, C.byref(H)) == -1
     assert lib.rtt_lincomb(0, None, None, C.byref(C.c_void_p())) == -1
     assert lib.rtt_destroy(None) == 0
+
+
+def test_binding_rejects_wrong_buffers_before_any_launch():
+    """The binding refuses device buffers of the wrong dtype, element count
+    or spin-word count instead of passing their pointers on: the kernels
+    would read or write past their ends.  Checked on the host (CPU tensors
+    that pass the dtype and size checks are refused as not on the device)."""
+    import torch
+
+    from paper_2604_22718_amd import rtt as R
+    nw = 2
+    with pytest.raises(ValueError):
+        R._spins_ptr(torch.zeros(5, nw + 1, dtype=torch.int64), nw)         # wrong word count
+    with pytest.raises(ValueError):
+        R._spins_ptr(torch.zeros(5 * nw, dtype=torch.int64), nw)            # not [W][nw]
+    with pytest.raises(ValueError):
+        R._spins_ptr(torch.zeros(0, nw, dtype=torch.int64), nw)             # no walkers
+    with pytest.raises(TypeError):
+        R._spins_ptr(torch.zeros(5, nw, dtype=torch.int32), nw)             # not 64-bit words
+    with pytest.raises(ValueError, match="CUDA"):
+        R._spins_ptr(torch.zeros(5, nw, dtype=torch.int64), nw)             # right, but host memory
+    with pytest.raises(TypeError):
+        R._ptr(torch.zeros(5, dtype=torch.float32), "eloc", R.F64, 5)       # float32 energies
+    with pytest.raises(ValueError):
+        R._ptr(torch.zeros(4, dtype=torch.float64), "eloc", R.F64, 5)       # too short
+    with pytest.raises(TypeError):
+        R._ptr(torch.zeros(5, 3, dtype=torch.int32), "rsign", R.I8, 15)     # int32 signs
+    with pytest.raises(ValueError):
+        R._ptr(torch.zeros(3, dtype=torch.float64), "out", R.F64, 3)        # host memory
+    with pytest.raises(TypeError):
+        R._ptr(np.zeros(3), "out", R.F64, 3)                                # not a tensor
+    with pytest.raises(ValueError):
+        R._net_sites(C.c_void_p(12345))                                     # unknown network
+    assert R._ptr(None) is None

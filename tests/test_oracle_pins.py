@@ -294,6 +294,42 @@ def test_lincomb_pins():
                        rtt.flip_ratios(ds, pi, S[:7]), rtol=1e-10)
 
 
+def test_lincomb_condition_numbers():
+    """Term-wise cancellation measure of a linear combination: the one-term
+    case is condition_numbers; copies of one train give closed forms (same
+    signs: kappa(A); c = (1, -1/2): the terms cancel to half, kappa = 3
+    kappa(A)); it is >= 1, at least the value at the middle bond computed
+    from explicit products, and at most the direct-sum train's kappa."""
+    N, R, chi = 5, 2, 3
+    pi = wl.path_site_plus_perms(N, R, 61)
+    terms = [rand_cores(wl.open_bonds(N * R, chi), 62 + t) for t in range(3)]
+    S = rtt.all_configs(N)
+    kA = rtt.condition_numbers(terms[0], pi, S)
+    assert np.allclose(rtt.lincomb_condition_numbers(terms[:1], [1.0], pi, S), kA, rtol=1e-12)
+    assert np.allclose(rtt.lincomb_condition_numbers(terms[:1], [-2.5], pi, S), kA, rtol=1e-12)
+    A2 = [terms[0], terms[0]]
+    assert np.allclose(rtt.lincomb_condition_numbers(A2, [0.3, 1.2], pi, S), kA, rtol=1e-12)
+    assert np.allclose(rtt.lincomb_condition_numbers(A2, [1.0, -0.5], pi, S), 3.0 * kA, rtol=1e-12)
+    c = np.array([0.7, -1.3, 0.4])
+    k = rtt.lincomb_condition_numbers(terms, c, pi, S)
+    assert np.all(k >= 1.0 - 1e-12)
+    assert np.all(k <= rtt.condition_numbers(tt.direct_sum(terms, c), pi, S) * (1 + 1e-12))
+    s = S[11]
+    num, psi = 0.0, 0.0
+    for ca, cores in zip(c, terms):
+        l = np.ones((1, 1))
+        for q in range(5):
+            l = l @ cores[q][s[pi[q]]]
+        r = np.ones((1, 1))
+        for q in reversed(range(5, 10)):
+            r = cores[q][s[pi[q]]] @ r
+        num += abs(ca) * np.linalg.norm(l) * np.linalg.norm(r)
+        psi += ca * (l @ r)[0, 0]
+    assert k[11] >= num / abs(psi) * (1 - 1e-12)
+    kf = rtt.lincomb_flip_condition_numbers(terms, c, pi, S[:4])
+    assert kf.shape == (4, 5) and np.all(kf >= k[:4, None] * (1 - 1e-12))
+
+
 # ---------------------------------------------------------------- MCMC
 def test_single_flip_sweep_is_stationary():
     """Brute force on 3x3 (512 states): |psi|^2 is left-invariant under the full
