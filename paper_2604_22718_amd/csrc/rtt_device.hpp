@@ -51,6 +51,7 @@ __device__ __forceinline__ void split_bf16x2(float a, float b, uint32_t& hi, uin
 // mma() / mma2() run the K loop for one (or two, interleaved) core slices.
 struct DF32 {
   using elem = float;
+  static constexpr bool kF32 = true;  // FP32 activations on FP32 matrix ops
   template <int KPL>
   struct BOp { float v[KPL]; };
   template <int KPL>
@@ -81,6 +82,7 @@ struct DF32 {
 // pair (two MFMAs), so each product keeps ~16 significant activation bits.
 struct DBF16 {
   using elem = uint16_t;
+  static constexpr bool kF32 = false;
   template <int KPL>
   struct BOp { bf16x8 hi[KPL / 8], lo[KPL / 8]; };
   template <int KPL>
@@ -128,6 +130,68 @@ struct DBF16 {
   __device__ __forceinline__ static float to_f32(uint16_t x) { return bf16_to_f32(x); }
 };
 
+// FP8 cores: one OCP e4m3 code per byte.  The matrix ops take a code c as
+// the BF16 value c * 2^-9, decoded in registers by the gfx950 scaled
+// conversion (exact: three mantissa bits, exponent well inside the BF16
+// range).  Codes are at most 448 in magnitude, so the values the kernels see
+// stay below 1 like the prescaled FP32 and BF16 cores; each position's
+// exponent (FP8 scale + 9) is added back in the exponent bookkeeping.
+// Activations are the hi + lo BF16 pair of DBF16.  Fragments stay FP8 in
+// registers and are decoded where the matrix ops use them, so a fragment
+// set takes half the registers of a BF16 one and half the bytes to load.
+constexpr float kFp8Scale = 0.001953125f;  // 2^-9
+struct DFP8 {
+  using elem = uint8_t;
+  static constexpr bool kF32 = false;
+  template <int KPL>
+  using BOp = DBF16::BOp<KPL>;
+  template <int KPL>
+  __device__ __forceinline__ static void prep(const float (&x)[KPL], BOp<KPL>& b) {
+    DBF16::prep<KPL>(x, b);
+  }
+  // the 8 codes at elements 8c .. 8c+7 of a lane's fragment as BF16 values
+  template <int KPL>
+  __device__ __forceinline__ static bf16x8 pack(const uint8_t (&a)[KPL], int c) {
+    typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+    uint32_t w0 = 0, w1 = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      w0 |= (uint32_t)a[8 * c + i] << (8 * i);
+      w1 |= (uint32_t)a[8 * c + 4 + i] << (8 * i);
+    }
+    const b2 p0 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(w0, kFp8Scale, false);
+    const b2 p1 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(w0, kFp8Scale, true);
+    const b2 p2 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(w1, kFp8Scale, false);
+    const b2 p3 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(w1, kFp8Scale, true);
+    return bf16x8{p0[0], p0[1], p1[0], p1[1], p2[0], p2[1], p3[0], p3[1]};
+  }
+  __device__ __forceinline__ static float to_f32(uint8_t x) {
+    return (float)__builtin_amdgcn_cvt_scalef32_pk_bf16_fp8((uint32_t)x, kFp8Scale, false)[0];
+  }
+  template <int KPL>
+  __device__ __forceinline__ static f4 mma(const uint8_t (&a)[KPL], const BOp<KPL>& b, f4 acc) {
+#pragma unroll
+    for (int c = 0; c < KPL / 8; ++c) {
+      const bf16x8 av = pack<KPL>(a, c);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b.hi[c], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b.lo[c], acc, 0, 0, 0);
+    }
+    return acc;
+  }
+  template <int KPL>
+  __device__ __forceinline__ static void mma2(const uint8_t (&a0)[KPL], const uint8_t (&a1)[KPL],
+                                              const BOp<KPL>& b, f4& c0, f4& c1) {
+#pragma unroll
+    for (int c = 0; c < KPL / 8; ++c) {
+      const bf16x8 x0 = pack<KPL>(a0, c), x1 = pack<KPL>(a1, c);
+      c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x0, b.hi[c], c0, 0, 0, 0);
+      c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x1, b.hi[c], c1, 0, 0, 0);
+      c0 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x0, b.lo[c], c0, 0, 0, 0);
+      c1 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x1, b.lo[c], c1, 0, 0, 0);
+    }
+  }
+};
+
 // Workgroup barrier that orders LDS only: global loads issued before it
 // (prefetched core fragments) stay in flight across it.
 __device__ __forceinline__ void lds_barrier() {
@@ -143,6 +207,11 @@ __device__ __forceinline__ void lds_barrier() {
 // each, which is what limited the rate at which CUs take fragments from L2.
 __host__ __device__ constexpr size_t frag_offset(int lane, int e, int ce) {
   return ((size_t)(e / ce) * 64 + lane) * ce + e % ce;
+}
+// chunk length in elements: 16 bytes, or a lane's whole fragment when that is
+// shorter (FP8 at bond 32: 8 codes, one 8-byte load)
+__host__ __device__ constexpr int frag_chunk(int elem_bytes, int kpl) {
+  return 16 / elem_bytes < kpl ? 16 / elem_bytes : kpl;
 }
 
 // Load a lane's KPL-element fragment from a tile (16-byte aligned).
@@ -167,6 +236,25 @@ __device__ __forceinline__ void load_frag(uint16_t (&dst)[KPL], const uint16_t* 
       dst[8 * i + 2 * j] = (uint16_t)(w[j] & 0xffffu);
       dst[8 * i + 2 * j + 1] = (uint16_t)(w[j] >> 16);
     }
+  }
+}
+
+template <int KPL>
+__device__ __forceinline__ void load_frag(uint8_t (&dst)[KPL], const uint8_t* tile, int lane) {
+  if constexpr (KPL % 16 == 0) {
+    const uint4* s = reinterpret_cast<const uint4*>(tile) + lane;
+#pragma unroll
+    for (int i = 0; i < KPL / 16; ++i) {
+      uint4 v = s[64 * i];
+      uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int j = 0; j < 16; ++j) dst[16 * i + j] = (uint8_t)(w[j / 4] >> (8 * (j % 4)));
+    }
+  } else {
+    static_assert(KPL == 8, "FP8 fragments of 8 or a multiple of 16 codes per lane");
+    const uint2 v = reinterpret_cast<const uint2*>(tile)[lane];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) dst[j] = (uint8_t)((j < 4 ? v.x : v.y) >> (8 * (j % 4)));
   }
 }
 
@@ -330,6 +418,10 @@ struct Act<DBF16, CHI> {
     *reinterpret_cast<uint2*>(hi(dst) + CHI + col) = *reinterpret_cast<const uint2*>(hi(src) + CHI + col);
   }
 };
+
+// FP8 cores take the same activation rows as BF16 cores
+template <int CHI>
+struct Act<DFP8, CHI> : Act<DBF16, CHI> {};
 
 // ---------------------------------------------------------------- Philox4x64-10
 // Salmon et al., SC'11: 10 rounds of two 64x64->128 multiplies per block,

@@ -96,10 +96,12 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int bx, int ty) {
   // otherwise (bond 256) once per half of the tiles.  The core fragments of item i+1
   // are loaded while item i computes.  Rows are stored in the matrix-op
   // form (Act), and renormalisation scales the products, not the inputs.
-  constexpr int FRAG_DW = MT * 2 * KPL * (int)sizeof(E) / 4;
+  // (FP8 fragments are sized as BF16 ones here: the codes are decoded to
+  // BF16 operands next to the matrix ops, which needs the room)
+  constexpr int FRAG_DW = MT * 2 * KPL * (sizeof(E) < 2 ? 2 : (int)sizeof(E)) / 4;
   constexpr int MTI = FRAG_DW <= 128 ? MT : (MT % 2 == 0 && FRAG_DW <= 256 ? MT / 2 : 1);
   constexpr int NIS = MT / MTI;  // items per step
-  constexpr bool ODD_MFMA = sizeof(E) == 2;
+  constexpr bool ODD_MFMA = !D::kF32;
   struct Frags { E m[MTI][KPL]; E o[MTI][KPL]; };
   const int n_items = gs.y * NIS;
   auto load = [&](Frags& F, int item) {
@@ -412,7 +414,7 @@ struct ChainGeo {
   static constexpr int NT = 2 * SW * 64;                       // threads per block
   // fragment sets in the prefetch ring (see chain_body)
   template <class E>
-  static constexpr int PF = (CHI == 128 && sizeof(E) == 2) ? 4 : 2;
+  static constexpr int PF = ((CHI == 128 && sizeof(E) == 2) || (CHI == 128 && sizeof(E) == 1)) ? 4 : 2;
 };
 
 // Block of 2 * SW waves for 16 * CG walkers: CG groups of 16 matrix-core
@@ -598,11 +600,11 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
               // FP32 rows are renormalised in place as read; BF16 rows scale
               // the products instead (their stored split stays as written)
               float v[KPL];
-              if constexpr (sizeof(E) == 4) lds_read<KPL>(v, buf(t, cur) + wn * RS + g * KPL);
+              if constexpr (D::kF32) lds_read<KPL>(v, buf(t, cur) + wn * RS + g * KPL);
               else A::template load_b<KPL>(buf(t, cur) + wn * RS, g, bo[cg]);
               if (i % kRenormEvery == 0) {
                 int e;
-                if constexpr (sizeof(E) == 4) {
+                if constexpr (D::kF32) {
                   e = renorm_row<KPL>(v);
                 } else {
                   e = A::template row_exp<KPL>(bo[cg]);
@@ -620,7 +622,7 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
                   }
                 }
               }
-              if constexpr (sizeof(E) == 4) D::template prep<KPL>(v, bo[cg]);
+              if constexpr (D::kF32) D::template prep<KPL>(v, bo[cg]);
             }
           }
         }
@@ -635,7 +637,7 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
 #pragma unroll
         for (int cg = 0; cg < CG; ++cg) {
           const int wn = 16 * cg + m;
-          if constexpr (sizeof(E) == 2) {
+          if constexpr (!D::kF32) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) { c0[cg][q] *= psc[cg]; c1[cg][q] *= psc[cg]; }
           }

@@ -79,6 +79,22 @@ double e4m3_round(float f) {
   return sg * q;
 }
 
+// OCP e4m3 byte of a value that e4m3 represents exactly (|v| <= 448)
+uint8_t e4m3_code(double v) {
+  const uint8_t sg = v < 0 ? 0x80 : 0x00;
+  const double a = fabs(v);
+  if (a == 0.0) return sg;
+  if (a < ldexp(1.0, -6)) return sg | (uint8_t)lrint(a * 512.0);  // subnormal: m * 2^-9
+  int ex = 0;
+  const double f = frexp(a, &ex);                               // a = f 2^ex, f in [0.5, 1)
+  return sg | (uint8_t)((ex + 6) << 3) | (uint8_t)lrint((2.0 * f - 1.0) * 8.0);
+}
+double e4m3_decode(uint8_t b) {
+  const int e = (b >> 3) & 15, m = b & 7;
+  const double v = e == 0 ? m * ldexp(1.0, -9) : ldexp(1.0 + m / 8.0, e - 7);
+  return (b & 0x80) ? -v : v;
+}
+
 int fp8_scale_exponent(const double* c, size_t n) {
   double amax = 0.0;
   for (size_t i = 0; i < n; ++i) amax = std::max(amax, fabs(c[i]));
@@ -179,6 +195,7 @@ struct rtt_s {
   std::vector<int> pi, bond;
   std::vector<double> coeffs;
   std::vector<std::vector<double>> qcores;  // quantised values, rtt_create layout, per term
+  std::vector<std::vector<int>> fp8e;       // [T][L] FP8 scale exponents (FP8 cores only)
   std::vector<int> core_exp;                // [T][L] power-of-two scale of each stored core
   std::vector<int> cesum;                   // [T][L+1] prefix sums of core_exp
   std::vector<uint64_t> rmask;              // [N][LW] replica positions of each spin
@@ -227,12 +244,14 @@ struct rtt_ham_s {
 
 namespace {
 
-size_t elem_bytes(int dtype) { return dtype == RTT_F32 ? 4 : 2; }
+size_t elem_bytes(int dtype) { return dtype == RTT_F32 ? 4 : dtype == RTT_BF16 ? 2 : 1; }
 
 // Pack one term: element (t, lane, e) of slice (k, b) in the forward layout
 // is core[b][g*KPL + e][16t + m] (transposed), in the backward layout
 // core[b][16t + m][g*KPL + e]; lane = 16 g + m, KPL = chi / 4.  Within the
-// 64 * KPL elements of tile t the order is rttk::frag_offset's.
+// 64 * KPL elements of tile t the order is rttk::frag_offset's.  Elements are
+// the quantised core divided by 2^core_exp: FP32 and BF16 values, or for FP8
+// the e4m3 code c of the value c * 2^-9 (core_exp = FP8 scale + 9).
 void pack_term(const rtt_s* h, int term, const std::vector<double>& q, std::vector<uint8_t>& fw,
                std::vector<uint8_t>& bw) {
   const int chi = h->chi, L = h->L, KPL = chi / 4;
@@ -256,13 +275,18 @@ void pack_term(const rtt_s* h, int term, const std::vector<double>& q, std::vect
         for (int lane = 0; lane < 64; ++lane)
           for (int e = 0; e < KPL; ++e) {
             const int g = lane >> 4, m = lane & 15;
-            const size_t idx = base + (size_t)t * 64 * KPL + rttk::frag_offset(lane, e, (int)(16 / eb));
+            const size_t idx = base + (size_t)t * 64 * KPL + rttk::frag_offset(lane, e, rttk::frag_chunk((int)eb, KPL));
             const double vf = pad[s * slice + (size_t)(g * KPL + e) * chi + 16 * t + m];
             const double vb = pad[s * slice + (size_t)(16 * t + m) * chi + g * KPL + e];
             if (eb == 4) {
               const float ff = (float)vf, fb = (float)vb;
               memcpy(&fw[idx * 4], &ff, 4);
               memcpy(&bw[idx * 4], &fb, 4);
+            } else if (eb == 1) {
+              fw[idx] = e4m3_code(vf * 512.0);
+              bw[idx] = e4m3_code(vb * 512.0);
+              if (e4m3_decode(fw[idx]) != vf * 512.0 || e4m3_decode(bw[idx]) != vb * 512.0)
+                throw std::runtime_error("FP8 packing: a core value is not an e4m3 code times its scale");
             } else {
               const uint16_t hf = bf16_bits_rne((float)vf), hb = bf16_bits_rne((float)vb);
               memcpy(&fw[idx * 2], &hf, 2);
@@ -293,7 +317,8 @@ void free_dev(rtt_s* h) {
   if (any) (void)hipDeviceSynchronize();
 }
 
-// Quantised copy of the cores (rtt_create layout) and per-position exponents.
+// Quantised copy of the cores (rtt_create layout) and, for FP8, the scale
+// exponent of each position.
 void quantise(int dtype, const std::vector<int>& bond, const double* cores, std::vector<double>& q,
               std::vector<int>& cexp) {
   const int L = (int)bond.size() - 1;
@@ -310,6 +335,7 @@ void quantise(int dtype, const std::vector<int>& bond, const double* cores, std:
     } else {  // FP8 e4m3: value = code * 2^e, one scale per position
       const int e = fp8_scale_exponent(c, n);
       for (size_t i = 0; i < n; ++i) q.push_back(ldexp(e4m3_round((float)ldexp(c[i], -e)), e));
+      cexp[k] = e;
     }
     off += n;
   }
@@ -318,7 +344,8 @@ void quantise(int dtype, const std::vector<int>& bond, const double* cores, std:
 // Every stored core is the quantised core times 2^-e_k, with e_k chosen so
 // that its largest entry lies in [0.5, 1): exact, and it bounds the growth
 // of a renormalised row to chi per step.  e_k is added back in the exponent
-// bookkeeping of the kernels.
+// bookkeeping of the kernels.  FP8 cores are stored as their codes, which the
+// kernels read as code * 2^-9 (below 1 as well): e_k = FP8 scale + 9.
 void prescale(rtt_s* h) {
   h->core_exp.assign((size_t)h->T * h->L, 0);
   h->cesum.assign((size_t)h->T * (h->L + 1), 0);
@@ -330,7 +357,8 @@ void prescale(rtt_s* h) {
       double amax = 0.0;
       for (size_t i = 0; i < n; ++i) amax = std::max(amax, fabs(q[off + i]));
       int e = 0;
-      if (amax > 0.0) frexp(amax, &e);
+      if (h->dtype == RTT_FP8_E4M3) e = h->fp8e[t][k] + 9;
+      else if (amax > 0.0) frexp(amax, &e);
       h->core_exp[(size_t)t * h->L + k] = e;
       h->cesum[(size_t)t * (h->L + 1) + k + 1] = h->cesum[(size_t)t * (h->L + 1) + k] + e;
       off += n;
@@ -555,12 +583,19 @@ rtt_status dispatch(int dtype, int chi, Args&&... args) {
       case 64: return F<rttk::DF32, 64>::run(args...);
       case 128: return F<rttk::DF32, 128>::run(args...);
     }
-  } else {
+  } else if (dtype == RTT_BF16) {
     switch (chi) {
       case 32: return F<rttk::DBF16, 32>::run(args...);
       case 64: return F<rttk::DBF16, 64>::run(args...);
       case 128: return F<rttk::DBF16, 128>::run(args...);
       case 256: return F<rttk::DBF16, 256>::run(args...);
+    }
+  } else if (dtype == RTT_FP8_E4M3) {
+    switch (chi) {
+      case 32: return F<rttk::DFP8, 32>::run(args...);
+      case 64: return F<rttk::DFP8, 64>::run(args...);
+      case 128: return F<rttk::DFP8, 128>::run(args...);
+      case 256: return F<rttk::DFP8, 256>::run(args...);
     }
   }
   return fail(RTT_E_UNSUPPORTED, "no kernel for dtype %d, padded bond %d", dtype, chi);
@@ -758,7 +793,8 @@ static rtt_status rtt_create_impl(int32_t n_spins, int32_t n_cores, const int32_
   h->bond.assign(bond, bond + n_cores + 1);
   h->coeffs = {1.0};
   h->qcores.resize(1);
-  quantise(dtype, h->bond, cores, h->qcores[0], h->core_exp);
+  h->fp8e.resize(1);
+  quantise(dtype, h->bond, cores, h->qcores[0], h->fp8e[0]);
   (void)hipGetDevice(&h->device);
   rtt_status st = finish_create(h);
   if (st != RTT_OK) {
@@ -797,7 +833,10 @@ static rtt_status rtt_lincomb_impl(int32_t n_terms, const rtt_t* terms, const do
   h->bond = t0->bond;
   // terms may have different inner bonds: keep each term's own layout
   h->coeffs.assign(coeffs, coeffs + n_terms);
-  for (int t = 0; t < n_terms; ++t) h->qcores.push_back(terms[t]->qcores[0]);
+  for (int t = 0; t < n_terms; ++t) {
+    h->qcores.push_back(terms[t]->qcores[0]);
+    h->fp8e.push_back(terms[t]->fp8e[0]);
+  }
   // pack_term reads bond per handle: all terms share bond only if equal; pad via each term
   bool same_bond = true;
   for (int t = 0; t < n_terms; ++t) same_bond &= (terms[t]->bond == t0->bond);
@@ -854,9 +893,10 @@ rtt_status rtt_get_cores(rtt_t h, int32_t term, double* out) {
           // forward layout holds core[s][i][j] at g*KPL+e = i, 16t+m = j
           const int g = i / KPL, e = i % KPL, t = j / 16, m = j % 16;
           const size_t idx = ((size_t)k * 2 + s) * slice + (size_t)t * 64 * KPL +
-                             rttk::frag_offset(16 * g + m, e, (int)(16 / eb));
+                             rttk::frag_offset(16 * g + m, e, rttk::frag_chunk((int)eb, KPL));
           double v;
           if (eb == 4) { float f; memcpy(&f, &fw[idx * 4], 4); v = f; }
+          else if (eb == 1) v = e4m3_decode(fw[idx]) / 512.0;
           else { uint16_t u; memcpy(&u, &fw[idx * 2], 2); v = bf16_value(u); }
           out[off + ((size_t)s * a + i) * b + j] = v * scale;
         }
@@ -1477,11 +1517,11 @@ static rtt_status rtt_batch_create_impl(int32_t n, const rtt_t* rtts, const rtt_
     const rtt_s* h = b->rtts[i];
     int ci = -1;
     for (int c = 0; c < (int)b->classes.size(); ++c)
-      if (b->classes[c].dtype == (h->dtype == RTT_FP8_E4M3 ? RTT_BF16 : h->dtype) && b->classes[c].chi == h->chi) ci = c;
+      if (b->classes[c].dtype == h->dtype && b->classes[c].chi == h->chi) ci = c;
     if (ci < 0) {
       b->classes.emplace_back();
       ci = (int)b->classes.size() - 1;
-      b->classes[ci].dtype = h->dtype == RTT_FP8_E4M3 ? RTT_BF16 : h->dtype;
+      b->classes[ci].dtype = h->dtype;
       b->classes[ci].chi = h->chi;
     }
     b->classes[ci].members.push_back(i);

@@ -1,4 +1,7 @@
 """Shared test helpers: case construction and error metrics (no method arithmetic)."""
+import json
+import os
+
 import numpy as np
 
 from paper_2604_22718_amd import workloads as wl
@@ -20,30 +23,90 @@ def device_cores(psi, bond, n_terms=1):
     return [split_cores(psi.core_values(bond, t), bond) for t in range(n_terms)]
 
 
-def check_ratios(lr_gpu, sg_gpu, r_ref, kappa, tol, k0=10.0):
+def check_ratios(lr_gpu, sg_gpu, r_ref, kappa, tol, k0=10.0, min_well=1):
     """Per-ratio bound |Delta log|r_j|| <= tol * max(1, kappa_j / k0).
 
     kappa_j = max(kappa(s), kappa(s^j)) is the oracle's cancellation measure
     (condition_numbers); a floating-point evaluation of psi has relative
     error ~ gamma * kappa, so the tolerance holds as stated for
     well-conditioned ratios (kappa <= k0) and grows linearly beyond.  Signs
-    must agree wherever the allowed error is below 1/2.  Returns a summary."""
+    must agree wherever the allowed error is below 1/2.  At least
+    ``min_well`` ratios must be well-conditioned, so that the unscaled bound
+    is tested on some (``assert_ratio_summary`` checks it); pass 0 where the
+    caller asserts the unscaled bound on every ratio instead.  Returns a
+    summary: counts, the fraction of ratios within the unscaled tol, the
+    99.9th percentile and the maximum error, and the number of ratios held
+    to the scaled bound only (kappa > k0)."""
     r_ref = np.asarray(r_ref)
     with np.errstate(divide="ignore", invalid="ignore"):
         dlog = np.abs(np.asarray(lr_gpu) - np.log(np.abs(r_ref)))
-    allow = tol * np.maximum(1.0, np.asarray(kappa) / k0)
+    kappa = np.asarray(kappa)
+    allow = tol * np.maximum(1.0, kappa / k0)
     nz = r_ref != 0
     bad = nz & ~(dlog <= allow)
     sign_bad = nz & (allow < 0.5) & (np.sign(r_ref) != np.asarray(sg_gpu))
-    well = nz & (np.asarray(kappa) <= k0)
+    well = nz & (kappa <= k0)
     return {
-        "n": int(nz.sum()), "n_well": int(well.sum()),
-        "max_well": float(dlog[well].max()) if well.any() else 0.0,
+        "n": int(nz.sum()), "n_well": int(well.sum()), "min_well": int(min_well),
+        "n_scaled_only": int((nz & ~well).sum()),
+        "max_well": float(dlog[well].max()) if well.any() else float("nan"),
+        "frac_within_tol": float(np.mean(dlog[nz] <= tol)),
         "max_all": float(dlog[nz].max()), "p999_all": float(np.quantile(dlog[nz], 0.999)),
-        "median": float(np.median(dlog[nz])),
+        "median": float(np.median(dlog[nz])), "tol": float(tol),
         "n_bad": int(bad.sum()), "n_sign_bad": int(sign_bad.sum()),
         "worst_ratio_to_allow": float((dlog[nz] / allow[nz]).max()),
     }
+
+
+def assert_ratio_summary(st):
+    """The bounds of a check_ratios summary: no ratio beyond its (scaled)
+    bound, no sign error, enough well-conditioned ratios, and those within
+    the unscaled tolerance."""
+    assert st["n_bad"] == 0 and st["n_sign_bad"] == 0, st
+    assert st["n_well"] >= st["min_well"], st
+    if st["n_well"]:
+        assert st["max_well"] <= st["tol"], st
+
+
+# BF16 and FP8 cores run with hi + lo BF16 activations (about 16 significant
+# bits per product): their log-ratio errors stay within HILO_TOL * max(1,
+# kappa / 10), 100 times inside the stated 2e-2.  Parity tests hold them to
+# this bound as well, which a path with single-pass BF16 activations (8 bits,
+# ~4e-3 per product) would not meet.
+HILO_TOL = 2e-4
+
+
+def tie_error(lr_gpu, r_ref):
+    """Per walker, the largest error |Delta (r_j^2)| ~ 2 r_j^2 |Delta log|r_j||
+    over the ratios that can decide a Metropolis step near a tie (r_j^2 <=
+    1.5: u < 1, so a tie needs r^2 close to u).  A decision u < r^2 can only
+    differ from the exact one when |u - r^2| is below this."""
+    r_ref = np.asarray(r_ref)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        dlog = np.abs(np.asarray(lr_gpu) - np.log(np.abs(r_ref)))
+    r2 = r_ref * r_ref
+    e = np.where((r2 <= 1.5) & (r_ref != 0), 2.0 * r2 * dlog, 0.0)
+    return e.max(axis=1)
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def sampled_refs(workload, dtype):
+    """Oracle chain configurations and FP64 values stored by
+    tests/golden/make_sampled_refs.py, as arrays."""
+    with open(os.path.join(GOLDEN, "sampled_refs.json")) as f:
+        cases = json.load(f)["cases"]
+    c = next(x for x in cases if x["workload"] == workload and x["dtype"] == dtype)
+    out = dict(c)
+    for k in ("start", "sampled", "after", "final"):
+        out[k] = np.array([[int(x, 16) for x in row] for row in c[k]], dtype=np.uint64)
+    for k in ("walkers",):
+        out[k] = np.asarray(c[k], dtype=np.int64)
+    for k in ("min_margin", "flip_ratios", "flip_kappa", "eloc_quantised_cores", "eloc_fp64_cores",
+              "eloc_series"):
+        out[k] = np.asarray(c[k], dtype=np.float64)
+    return out
 
 
 def ratio_errors(lr_gpu, sg_gpu, r_ref):

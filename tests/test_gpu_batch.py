@@ -21,6 +21,9 @@ RUNS = [  # Lx, Ly, R, chi, dtype, W
     (4, 4, 2, 32, "bf16", 100),
     (5, 4, 2, 32, "fp8", 17),
     (4, 4, 2, 8, "f32", 64),
+    (5, 5, 2, 128, "bf16", 40),     # the widest class of the benchmark batch
+    (4, 4, 3, 128, "fp8", 24),      # FP8 cores: a class of their own
+    (10, 10, 2, 32, "bf16", 50),    # the largest lattice of the benchmark batch
 ]
 
 
@@ -77,7 +80,7 @@ def test_batch_energies_match_oracle_on_a_sample(R):
     batch = R.Batch(rtts, hams, spins, seed=5)
     batch.step(n_sweeps=1)
     torch.cuda.synchronize()
-    for i in (0, 3, 4):
+    for i in (0, 3, 4, 6, 7):
         pi, bond, N, Lx, Ly, h = meta[i]
         qc = device_cores(rtts[i], bond)
         bits = wl.unpack_spins(R.spins_to_host(batch.spins[i]), N)[:6]
@@ -105,4 +108,39 @@ def test_autotune_picks_a_shape_and_keeps_results_exact(R, tmp_path):
     torch.cuda.synchronize()
     for i in range(len(rtts)):
         assert torch.equal(batch.spins[i], ref_spins[i]), i
+    batch.close()
+
+
+def test_benchmark_batch_sampled_runs(R):
+    """The benchmark's batch in its launch configuration: 256 uneven BF16 RTTs
+    (side 4-10, R 2-3, chi 16-128, 256-4096 walkers), autotuned, one step of
+    1 sweep + local energies.  The oracle recomputes the local energies of
+    three walkers of six runs: the two largest chi = 128 runs, the largest
+    R = 3 run, and the smallest runs of chi 16, 32 and 64."""
+    ws = wl.batched_workloads(256)
+    rtts = [R.RTT.create(w.N, w.pi(), w.cores(), "bf16") for w in ws]
+    hams = [R.TFIM(w.Lx, w.Ly, w.J, w.h) for w in ws]
+    spins = [R.spins_to_device(wl.pack_spins(w.spins())) for w in ws]
+    batch = R.Batch(rtts, hams, spins, seed=3100)
+    conc, occ = batch.autotune(n_sweeps=1, reps=1)
+    batch.step(n_sweeps=1)
+    torch.cuda.synchronize()
+    work = [w.W * w.N * w.N * w.R * w.chi ** 2 for w in ws]
+    c128 = sorted((i for i, w in enumerate(ws) if w.chi == 128), key=lambda i: -work[i])[:2]
+    r3 = max((i for i, w in enumerate(ws) if w.R == 3), key=lambda i: work[i])
+    small = [min((i for i, w in enumerate(ws) if w.chi == c), key=lambda i: work[i]) for c in (16, 32, 64)]
+    picks = list(dict.fromkeys(c128 + [r3] + small))
+    print(f"  autotuned shape: concurrent {conc}, blocks per CU {occ}; runs {picks}", flush=True)
+    for i in picks:
+        w = ws[i]
+        qc = device_cores(rtts[i], w.bond())
+        sub = [0, w.W // 2, w.W - 1]
+        bits = wl.unpack_spins(R.spins_to_host(batch.spins[i]), w.N)[sub]
+        el = orc.local_energy(qc, w.pi(), bits, tfim.bonds(w.Lx, w.Ly), w.J, w.h)
+        got = batch.eloc[i].cpu().numpy()[sub]
+        rel = np.abs(got - el) / np.maximum(1.0, np.abs(el))
+        print(f"  run {i}: {w.Lx}x{w.Ly} R={w.R} chi={w.chi} W={w.W}: E_loc rel err {rel.max():.2e}", flush=True)
+        assert np.all(rel <= 2e-2)
+        es = batch.esum[i].cpu().numpy()
+        assert es[2] == w.W
     batch.close()

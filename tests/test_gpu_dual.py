@@ -8,7 +8,7 @@ import scipy.linalg
 import torch
 
 from helpers import case, device_cores
-from oracle import dual, rtt as orc, stats, tfim, tt
+from oracle import dual, rtt as orc, stats, tfim
 from paper_2604_22718_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
@@ -198,11 +198,21 @@ def test_full_size_dual_step_sampled_walkers(R):
         assert np.all(st == 0)
         def kap(x):   # cancellation measure of a state on the sampled walkers
             if isinstance(x, tuple):
-                return orc.condition_numbers(tt.direct_sum(x[0], x[1]), pi, bits[idx])
+                return orc.lincomb_condition_numbers(x[0], x[1], pi, bits[idx])
             return orc.condition_numbers(x, pi, bits[idx])
+
+        def kap_flip(x):   # ... and of its flipped configurations (its local energy)
+            if isinstance(x, tuple):
+                return orc.lincomb_flip_condition_numbers(x[0], x[1], pi, bits[idx]).max(axis=1)
+            return orc.flip_condition_numbers(x, pi, bits[idx]).max(axis=1)
         for t in range(3):
             o_ref, e_ref = dual.mixed_estimators(ref[2 * sa], ref[t], pi, bits[idx], bonds, w.J, w.h)
             allow = 1e-5 * np.maximum(1.0, np.maximum(kap(ref[2 * sa]), kap(ref[t])) / 10.0)
             assert np.all(np.abs(np.log(np.abs(ratio[t][idx] / o_ref))) <= 2 * allow), (sa, t)
             assert np.all(np.sign(ratio[t][idx]) == np.sign(o_ref))
-            assert np.all(np.abs(mixed[t][idx] - e_ref) <= 1e-3 * np.abs(e_ref).max()), (sa, t)
+            # mixed = ratio * E_loc of the target: the FP32 bound of each factor
+            allow_m = 1e-5 * np.maximum(1.0, np.maximum(kap(ref[2 * sa]), kap_flip(ref[t])) / 10.0)
+            rel_m = np.abs(mixed[t][idx] - e_ref) / np.maximum(1.0, np.abs(e_ref))
+            print(f"  state {2 * sa} target {t}: mixed rel err {rel_m.max():.2e}, allowed {2 * allow_m.min():.2e}..",
+                  flush=True)
+            assert np.all(rel_m <= 2 * allow_m), (sa, t, rel_m, allow_m)

@@ -1,0 +1,144 @@
+"""Full-size parity in the benchmark's launch configuration, on configurations
+the oracle's own Metropolis chain samples (|psi|^2-typical, stored with their
+FP64 ratios, condition numbers, energies and next-sweep decisions by
+tests/golden/make_sampled_refs.py):
+
+  * 8x8, R = 2, chi = 64, 4096 walkers, FP32 and BF16 cores;
+  * 10x10, R = 3, chi = 128, 8192 walkers, BF16 cores;
+  * 16x16, R = 2, chi = 256, 16384 walkers, a 4-term linear combination of
+    FP8 cores.
+
+The sampled configurations are placed at their walker indices among the
+workload's seeded walkers, every walker is evaluated, and the sampled ones
+are compared element by element.  Tolerances on log-ratios: FP32 1e-5 on
+every ratio whose condition number is <= 10 (at least 20 such ratios), the
+bound growing as kappa / 10 beyond; BF16 and FP8 2e-2 on at least 99% of the
+ratios with no scaling, and on every ratio HILO_TOL * max(1, kappa / 10), 100
+times inside the stated bound.  Then one Metropolis sweep with the chain's
+Philox words must make the oracle's decisions for every walker whose
+decision margins |u - r^2| exceed 10 times the error in r^2 measured on that
+walker's near-tie ratios.  At 8x8 the mean
+energy of the full GPU chain (50 burn-in + 200 measured sweeps) must lie
+within 3 sigma of the oracle chain's FP64 mean."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from helpers import HILO_TOL, assert_ratio_summary, check_ratios, sampled_refs, tie_error
+from oracle import stats
+from paper_2604_22718_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f32": 1e-5, "bf16": 2e-2, "fp8": 2e-2}
+FULL = [("tfim8x8_R2_chi64_W4096", "f32"), ("tfim8x8_R2_chi64_W4096", "bf16"),
+        ("tfim10x10_R3_chi128_W8192", "bf16"), ("tfim16x16_R2_chi256_W16384_T4", "fp8")]
+
+
+@pytest.fixture(scope="module")
+def R():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2604_22718_amd import rtt
+    return rtt
+
+
+def make_state(R, w, dtype):
+    pi = w.pi()
+    if w.n_terms == 1:
+        return R.RTT.create(w.N, pi, w.cores(), dtype)
+    hs = [R.RTT.create(w.N, pi, w.cores(t), dtype) for t in range(w.n_terms)]
+    psi = R.RTT.lincomb(hs, w.coeffs())
+    for h in hs:
+        h.close()
+    return psi
+
+
+@pytest.mark.parametrize("name,dtype", FULL, ids=[f"{n}-{d}" for n, d in FULL])
+def test_full_size_sampled_walkers(R, name, dtype):
+    print(f"[case] {name} {dtype}", flush=True)
+    w = wl.WORKLOADS[name]
+    g = sampled_refs(name, dtype)
+    ids = g["walkers"]
+    psi = make_state(R, w, dtype)
+    ham = R.TFIM(w.Lx, w.Ly, w.J, w.h)
+    words = wl.pack_spins(w.spins())
+    words[ids] = g["sampled"]
+    spins = R.spins_to_device(words)
+    out = psi.evaluate(spins, ham)
+    torch.cuda.synchronize()
+    sub = {k: v.cpu().numpy()[ids] for k, v in out.items()}
+    assert np.all(out["status"].cpu().numpy() == 0)
+    tol = TOL[dtype]
+    st = check_ratios(sub["logratio"], sub["rsign"], g["flip_ratios"], g["flip_kappa"], tol,
+                      min_well=20 if dtype == "f32" else 0)
+    print(f"  ratios {st}", flush=True)
+    assert_ratio_summary(st)
+    if dtype != "f32":
+        sh = check_ratios(sub["logratio"], sub["rsign"], g["flip_ratios"], g["flip_kappa"], HILO_TOL, min_well=0)
+        print(f"  ratios at {HILO_TOL}: {sh}", flush=True)
+        assert sh["n_bad"] == 0, sh
+        assert st["frac_within_tol"] >= 0.99, st
+    # local energies against the oracle's FP64 values on the same cores
+    el = g["eloc_quantised_cores"]
+    rel = np.abs(sub["eloc"] - el) / np.maximum(1.0, np.abs(el))
+    kmax = g["flip_kappa"].max(axis=1)
+    print(f"  E_loc rel err max {rel.max():.3e} median {np.median(rel):.3e} (kappa max {kmax.max():.0f})",
+          flush=True)
+    assert np.all(rel <= tol * np.maximum(1.0, kmax / 10.0))
+    if dtype != "f32":
+        assert np.all(rel <= tol) and np.all(rel <= HILO_TOL * np.maximum(1.0, kmax / 10.0))
+    # one sweep from the sampled configurations with the chain's Philox words:
+    # the oracle's decisions wherever every margin exceeds 10 times the
+    # error in r^2 measured on the walker (the sweep's own configurations
+    # differ from the sampled one after its first accepted move)
+    err = tie_error(sub["logratio"], g["flip_ratios"])
+    psi.sweep(spins, seed=g["seed"], rng_stream=g["stream"], sweep0=g["burn"], n_sweeps=1)
+    torch.cuda.synchronize()
+    got = R.spins_to_host(spins)[ids]
+    clean = g["min_margin"] > 10.0 * np.maximum(err, 1e-7)
+    print(f"  sweep: {clean.sum()}/{len(ids)} walkers away from ties, margins {np.round(g['min_margin'], 5)}, "
+          f"ratio errors {err}", flush=True)
+    assert clean.sum() >= max(1, len(ids) // 2)
+    assert np.array_equal(got[clean], g["after"][clean])
+    psi.close()
+    ham.close()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "bf16"])
+def test_full_size_chain_energy_within_3_sigma_of_oracle(R, dtype):
+    """8x8, chi = 64, 4096 walkers: 50 burn-in + 200 measured sweeps from the
+    seeded walkers.  The GPU chain's mean energy (all walkers, sigma from
+    tau_int) and the oracle chain's FP64 mean (16 of the same walkers, same
+    Philox words, on the same quantised cores) agree within 3 combined sigma."""
+    w = wl.MEDIUM_8x8
+    g = sampled_refs(w.name, dtype)
+    psi = make_state(R, w, dtype)
+    ham = R.TFIM(w.Lx, w.Ly, w.J, w.h)
+    spins = R.spins_to_device(wl.pack_spins(w.spins()))
+    psi.sweep(spins, seed=w.chain_seed, sweep0=0, n_sweeps=w.burn_in + 1)
+    series = []
+    for t in range(w.sweeps):
+        psi.sweep(spins, seed=w.chain_seed, sweep0=w.burn_in + 1 + t, n_sweeps=1)
+        series.append(psi.local_energy(spins, ham))
+    E = torch.stack(series).cpu().numpy()
+    m_gpu, s_gpu, tau_gpu, _ = stats.energy_estimate(E)
+    m_or, s_or, tau_or, _ = stats.energy_estimate(g["eloc_series"])
+    z = abs(m_gpu - m_or) / math.hypot(s_gpu, s_or)
+    print(f"  GPU {m_gpu / w.N:.6f} +- {s_gpu / w.N:.6f} (tau {tau_gpu:.2f}), oracle {m_or / w.N:.6f} +- "
+          f"{s_or / w.N:.6f} (tau {tau_or:.2f}) per site, z = {z:.2f}", flush=True)
+    assert z < 3.0
+    if dtype == "f32":   # the oracle's 16 walkers: the GPU chain made the same decisions
+        ids = g["walkers"]
+        got = wl.unpack_spins(R.spins_to_host(spins)[ids], w.N)
+        same = np.all(got == wl.unpack_spins(g["final"], w.N), axis=1)
+        print(f"  {same.sum()}/{len(ids)} oracle walkers on the same trajectory after 251 sweeps", flush=True)
+        assert same.sum() >= len(ids) - 2
+        e_or = g["eloc_series"]
+        rel = np.abs(E[:, ids] - e_or) / np.maximum(1.0, np.abs(e_or))
+        print(f"  per-sample E_loc rel err on those walkers: max {rel[:, same].max():.3e}", flush=True)
+        assert np.all(rel[:, same] <= 1e-3)
+    psi.close()
+    ham.close()

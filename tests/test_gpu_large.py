@@ -1,12 +1,13 @@
 """Shapes that do not fit on chip in one piece: row groups in the flip-ratio
 passes, and the term-sequential sweep of a large linear combination; the
-16x16, chi = 256, 4-term FP8 workload on sampled spins; and the sampler's
-two-column-group blocks (bond 128, at least 32 walkers per compute unit)."""
+sampler's two-column-group blocks (bond 128, at least 32 walkers per compute
+unit); the largest spin count.  (The 16x16, chi = 256, 4-term FP8 workload
+is tested at full size in test_gpu_fullsize.py.)"""
 import numpy as np
 import pytest
 import torch
 
-from helpers import case, check_ratios, device_cores
+from helpers import HILO_TOL, case, check_ratios, device_cores
 from oracle import mcmc, rtt as orc, tt
 from paper_2604_22718_amd import workloads as wl
 
@@ -36,6 +37,7 @@ def test_row_groups_match_oracle(R):
     st = check_ratios(out["logratio"], out["rsign"], r_ref, kap, 2e-2)
     print(psi.info, st)
     assert st["n_bad"] == 0 and st["n_sign_bad"] == 0
+    assert check_ratios(out["logratio"], out["rsign"], r_ref, kap, HILO_TOL)["n_bad"] == 0
     la, sg = orc.log_sign(orc.amplitudes(qc, pi, bits))
     assert np.all(out["sign"] == sg) and np.max(np.abs(out["logabs"] - la)) < 2e-2
 
@@ -88,40 +90,6 @@ def test_sequential_terms_sweep_matches_oracle(R):
     ok = clean
     assert np.all(sg.cpu().numpy()[ok] == sref[ok])
     assert np.max(np.abs(la.cpu().numpy()[ok] - lref[ok])) < 2e-2
-
-
-def test_16x16_chi256_four_term_fp8_sampled(R):
-    """The 16x16 periodic TFIM workload (N = 256, R = 2, L = 512, chi = 256,
-    4-term linear combination, FP8 cores): local energies of a few walkers;
-    the oracle recomputes 12 of the 256 flip ratios of walker 0."""
-    w = wl.HUGE_16x16
-    pi, bond = w.pi(), w.bond()
-    hs = [R.RTT.create(w.N, pi, w.cores(t), "fp8") for t in range(w.n_terms)]
-    comb = R.RTT.lincomb(hs, w.coeffs())
-    for h in hs:
-        h.close()
-    print(comb.info)
-    W = 8
-    bits = w.spins(W)
-    ham = R.TFIM(16, 16, w.J, w.h)
-    out = comb.evaluate(R.spins_to_device(wl.pack_spins(bits)), ham)
-    torch.cuda.synchronize()
-    out = {k: v.cpu().numpy() for k, v in out.items()}
-    assert np.all(out["status"] == 0) and np.all(np.isfinite(out["eloc"]))
-    qts = device_cores(comb, bond, n_terms=w.n_terms)
-    js = [0, 1, 17, 63, 64, 100, 128, 129, 200, 230, 254, 255]
-    r_ref = orc.lincomb_flip_ratios(qts, w.coeffs(), pi, bits[:1], which=js)
-    got = out["rsign"][:1, js] * np.exp(out["logratio"][:1, js])
-    rel = np.abs(np.log(np.abs(got)) - np.log(np.abs(r_ref)))
-    print("dlog", rel)
-    assert np.all(np.sign(got) == np.sign(r_ref))
-    assert np.median(rel) < 2e-2
-    # the sweep on the same workload (term-sequential at chi = 256, 4 terms)
-    spins = R.spins_to_device(wl.pack_spins(bits))
-    st = torch.zeros(W, dtype=torch.int32, device="cuda")
-    comb.sweep(spins, seed=w.chain_seed, n_sweeps=1, status=st)
-    torch.cuda.synchronize()
-    assert torch.all(st == 0)
 
 
 @pytest.mark.parametrize("dtype", ["f32", "bf16"])

@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 import torch
 
-from helpers import case, check_ratios, device_cores
+from helpers import HILO_TOL, assert_ratio_summary, case, check_ratios, device_cores
 from oracle import mcmc, rtt as orc, stats, tfim
 from paper_2604_22718_amd import workloads as wl
 
@@ -48,12 +48,15 @@ EVAL_CASES = [
     ("n30_R1_chi64", 30, 1, 64, "perm", "f32", 6),
     ("n24_perm_chi64_bf16", 24, 2, 64, "perm", "bf16", 7),
     ("n24_perm_chi64_fp8", 24, 2, 64, "perm", "fp8", 7),
+    ("n20_perm_chi32_fp8_ragged", 20, 2, 32, "perm", "fp8", 13),
+    ("n16_R3_chi128_fp8", 16, 3, 128, "perm", "fp8", 5),
+    ("n12_perm_chi256_fp8", 12, 2, 256, "perm", "fp8", 3),
     ("n20_perm_chi128_f32", 20, 2, 128, "perm", "f32", 3),
     ("n12_perm_chi256_bf16", 12, 2, 256, "perm", "bf16", 3),
 ]
 
 
-def assert_parity(out, qc, pi, bits, dtype, label=""):
+def assert_parity(out, qc, pi, bits, dtype, label="", min_well=1):
     psi_ref = orc.amplitudes(qc, pi, bits)
     la_ref, sg_ref = orc.log_sign(psi_ref)
     k0 = orc.condition_numbers(qc, pi, bits)
@@ -63,10 +66,15 @@ def assert_parity(out, qc, pi, bits, dtype, label=""):
     assert np.all(np.abs(out["logabs"] - la_ref) <= tol * np.maximum(1.0, k0 / 10.0))
     r_ref = orc.flip_ratios(qc, pi, bits)
     kap = orc.flip_condition_numbers(qc, pi, bits)
-    st = check_ratios(out["logratio"], out["rsign"], r_ref, kap, tol)
+    st = check_ratios(out["logratio"], out["rsign"], r_ref, kap, tol, min_well=min_well)
     print(f"  {label} {st}", flush=True)
-    assert st["n_bad"] == 0 and st["n_sign_bad"] == 0
-    assert st["max_well"] <= tol
+    assert_ratio_summary(st)
+    if tol > 1e-3:   # reduced precision: the accuracy of hi + lo activations
+        sh = check_ratios(out["logratio"], out["rsign"], r_ref, kap, HILO_TOL, min_well=0)
+        print(f"  {label} at {HILO_TOL}: {sh}", flush=True)
+        assert sh["n_bad"] == 0, sh
+        if label == "sampled":   # configurations the chain visits: the stated bound, unscaled
+            assert st["frac_within_tol"] >= 0.99, st
     return st
 
 
@@ -83,13 +91,14 @@ def test_evaluate_matches_oracle(R, name, N, Rr, chi, path, dtype, W):
     pi, bond, cores = case(N, Rr, chi, path, seed=len(name))
     bits = wl.random_spins(W, N, 7 + N)
     psi, qc, out = run_eval(R, pi, bond, cores, N, bits, dtype)
-    assert_parity(out, qc, pi, bits, dtype, "uniform")
+    # uniform spins of the wide-bond cases have no well-conditioned ratio
+    assert_parity(out, qc, pi, bits, dtype, "uniform", min_well=0)
     # configurations the chain samples
     bits2 = sampled(qc, pi, min(W, 12), N, 100 + N)
     out2 = psi.evaluate(R.spins_to_device(wl.pack_spins(bits2)))
     torch.cuda.synchronize()
     out2 = {k: v.cpu().numpy() for k, v in out2.items()}
-    assert_parity(out2, qc, pi, bits2, dtype, "sampled")
+    assert_parity(out2, qc, pi, bits2, dtype, "sampled", min_well=1 if dtype == "f32" else 0)
 
 
 def test_general_path_with_unread_spins_and_uneven_bonds(R):
@@ -299,29 +308,6 @@ def test_tiny_and_degenerate_shapes(R):
         assert np.allclose(out["rsign"] * np.exp(out["logratio"]), r_ref, rtol=1e-5)
 
 
-@pytest.mark.parametrize("dtype", ["f32", "bf16"])
-def test_full_size_8x8_sampled_walkers(R, dtype):
-    """8x8, R=2, chi=64, 4096 walkers in the benchmark's launch configuration;
-    the oracle recomputes a sample of walkers one by one."""
-    w = wl.MEDIUM_8x8
-    pi, bond, cores = w.pi(), w.bond(), w.cores()
-    psi = R.RTT.create(w.N, pi, cores, dtype)
-    qc = device_cores(psi, bond)
-    bits = w.spins()
-    ham = R.TFIM(w.Lx, w.Ly, w.J, w.h)
-    out = psi.evaluate(R.spins_to_device(wl.pack_spins(bits)), ham)
-    torch.cuda.synchronize()
-    out = {k: v.cpu().numpy() for k, v in out.items()}
-    assert np.all(out["status"] == 0)
-    idx = np.array([0, 1, 777, 2048, 3001, 4095])
-    sub = {k: v[idx] for k, v in out.items()}
-    assert_parity(sub, qc, pi, bits[idx], dtype, "full-size sample")
-    el = orc.local_energy(qc, pi, bits[idx], tfim.bonds(w.Lx, w.Ly), w.J, w.h)
-    kap = orc.flip_condition_numbers(qc, pi, bits[idx]).max(axis=1)
-    rel = np.abs(sub["eloc"] - el) / np.maximum(1.0, np.abs(el))
-    assert np.all(rel <= TOL[dtype] * np.maximum(1.0, kap / 10.0))
-
-
 def test_chain_energy_matches_exact_enumeration(R):
     """4x4, R=2 (site order twice), chi=8, 64 walkers, 20 burn-in + 200 sweeps
     with a local-energy measurement after every sweep: the GPU mean is within
@@ -344,7 +330,8 @@ def test_chain_energy_matches_exact_enumeration(R):
     assert abs(mean - exact) < 3 * sigma
 
 
-@pytest.mark.parametrize("dtype,chi", [("bf16", 32), ("fp8", 64), ("bf16", 128), ("bf16", 256)])
+@pytest.mark.parametrize("dtype,chi", [("bf16", 32), ("fp8", 32), ("fp8", 64), ("bf16", 128), ("fp8", 128),
+                                       ("bf16", 256), ("fp8", 256)])
 def test_sweep_decisions_reduced_precision(R, dtype, chi):
     """BF16 / FP8 cores (hi+lo BF16 activations): one GPU sweep makes the
     oracle's decisions (same Philox words, oracle on the library's quantised
