@@ -147,6 +147,27 @@ rtt_status rtt_evaluate(rtt_t h, rtt_ham_t ham, int32_t W, const uint64_t* spins
                         double* logabs, int8_t* sign, double* logratio, int8_t* rsign,
                         double* eloc, int32_t* status, void* stream);
 
+/*
+ * rtt_evaluate for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * same arguments, outputs and errors as rtt_evaluate, the same kernels and
+ * bit-identical results, but the flip-ratio workspace is a fixed 64 MiB
+ * device array inside the library (one per GPU, held until the process
+ * ends) instead of the handle's own, and no call allocates or frees
+ * anything.  The workspace needed is 2 * T * groups * W * slots * (4 * bond
+ * + 4) bytes (T terms, padded bond, and groups and slots per walker as
+ * rtt_info reports them); a larger W gives RTT_E_ARG with the largest W
+ * this state allows per call (e.g. about 1600 walkers of the 8x8, bond-64
+ * train, 25 of the 16x16 bond-256 four-term combination), checked before
+ * any launch.  Every call on a GPU shares that GPU's array: calls that
+ * overlap on one GPU (different streams, threads or handles) race and must
+ * be ordered by the caller.  Nothing in the array needs to start at zero.
+ * Trains on the narrow-bond path need no workspace.
+ */
+rtt_status rtt_evaluate_noalloc(rtt_t h, rtt_ham_t ham, int32_t W, const uint64_t* spins,
+                                double* logabs, int8_t* sign, double* logratio, int8_t* rsign,
+                                double* eloc, int32_t* status, void* stream);
+
 /* Amplitudes only: log|psi| and sign for W walkers (device pointers). */
 rtt_status rtt_amplitudes(rtt_t h, int32_t W, const uint64_t* spins, double* logabs,
                           int8_t* sign, void* stream);

@@ -26,6 +26,7 @@ SIGNATURES = {
     "rtt_tfim_create": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double, C.POINTER(P)]),
     "rtt_tfim_destroy": (C.c_int, [P]),
     "rtt_evaluate": (C.c_int, [P, P, C.c_int32, P, P, P, P, P, P, P, P]),
+    "rtt_evaluate_noalloc": (C.c_int, [P, P, C.c_int32, P, P, P, P, P, P, P, P]),
     "rtt_amplitudes": (C.c_int, [P, C.c_int32, P, P, P, P]),
     "rtt_flip_ratios": (C.c_int, [P, C.c_int32, P, P, P, P]),
     "rtt_local_energy": (C.c_int, [P, P, C.c_int32, P, P, P]),

@@ -9,6 +9,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -928,16 +929,34 @@ rtt_status rtt_tfim_destroy(rtt_ham_t H) {
   return RTT_OK;
 }
 
-rtt_status rtt_evaluate(rtt_t h, rtt_ham_t ham, int32_t W, const uint64_t* spins, double* logabs,
-                        int8_t* sign, double* logratio, int8_t* rsign, double* eloc, int32_t* status,
-                        void* stream) {
-  g_err.clear();
+}  // extern "C"
+
+namespace {
+
+// Workspace of the flip-ratio passes: forward and backward cut vectors and
+// their exponents, [T][groups][W][slots] each.
+struct EvalWs {
+  float* u; float* v; int* ue; int* ve;
+};
+
+size_t eval_ws_rows(const rtt_s* h, int W) { return (size_t)h->T * h->sched.ng * W * h->sched.nslot; }
+size_t eval_ws_bytes(const rtt_s* h, int W) { return eval_ws_rows(h, W) * 2 * ((size_t)h->chi * 4 + 4); }
+
+rtt_status check_eval_args(const char* who, rtt_t h, rtt_ham_t ham, int32_t W, const uint64_t* spins,
+                           const double* eloc) {
   if (check_handle(h) != RTT_OK) return RTT_E_ARG;
-  if (W < 1) return fail(RTT_E_ARG, "rtt_evaluate: W = %d < 1", W);
-  if (!spins) return fail(RTT_E_ARG, "rtt_evaluate: spins is null");
-  if (eloc && !ham) return fail(RTT_E_ARG, "rtt_evaluate: eloc requested without a Hamiltonian");
-  if (ham && ham->Lx * ham->Ly != h->N) return fail(RTT_E_ARG, "rtt_evaluate: lattice has %d sites, RTT has %d spins", ham->Lx * ham->Ly, h->N);
-  hipStream_t s = (hipStream_t)stream;
+  if (W < 1) return fail(RTT_E_ARG, "%s: W = %d < 1", who, W);
+  if (!spins) return fail(RTT_E_ARG, "%s: spins is null", who);
+  if (eloc && !ham) return fail(RTT_E_ARG, "%s: eloc requested without a Hamiltonian", who);
+  if (ham && ham->Lx * ham->Ly != h->N)
+    return fail(RTT_E_ARG, "%s: lattice has %d sites, RTT has %d spins", who, ham->Lx * ham->Ly, h->N);
+  return RTT_OK;
+}
+
+// The evaluation itself on a given workspace (unused by narrow-bond trains).
+rtt_status evaluate_on(rtt_t h, rtt_ham_t ham, int32_t W, const uint64_t* spins, double* logabs, int8_t* sign,
+                       double* logratio, int8_t* rsign, double* eloc, int32_t* status, const EvalWs& ws,
+                       hipStream_t s) {
   if (h->narrow) {
     rttn::NarrowArgs na = narrow_args(h, W);
     na.spins = const_cast<uint64_t*>(spins);
@@ -949,10 +968,7 @@ rtt_status rtt_evaluate(rtt_t h, rtt_ham_t ham, int32_t W, const uint64_t* spins
     na.status = status;
     return h->narrow == 2 ? launch_narrow_eval<2>(na, s) : launch_narrow_eval<4>(na, s);
   }
-  rtt_status st = ensure_ws(h, W, s);
-  if (st != RTT_OK) return st;
-  const size_t tslice = (size_t)h->L * 2 * h->chi * h->chi * elem_bytes(h->dtype);
-  (void)tslice;
+  rtt_status st;
   rttk::PassArgs pa{};
   pa.core_exp = h->d_cexp;
   pa.nslot = h->sched.nslot;
@@ -965,18 +981,18 @@ rtt_status rtt_evaluate(rtt_t h, rtt_ham_t ham, int32_t W, const uint64_t* spins
   pa.cores = h->d_fwd;
   pa.sched = h->d_sf;
   pa.gsteps = h->d_fgs;
-  pa.out_vec = h->d_u;
-  pa.out_exp = h->d_ue;
+  pa.out_vec = ws.u;
+  pa.out_exp = ws.ue;
   if ((st = dispatch<PassL>(h->dtype, h->chi, pa, h->T * h->sched.ng, s)) != RTT_OK) return st;
   // backward
   pa.cores = h->d_bwd;
   pa.sched = h->d_sb;
   pa.gsteps = h->d_bgs;
-  pa.out_vec = h->d_v;
-  pa.out_exp = h->d_ve;
+  pa.out_vec = ws.v;
+  pa.out_exp = ws.ve;
   if ((st = dispatch<PassL>(h->dtype, h->chi, pa, h->T * h->sched.ng, s)) != RTT_OK) return st;
   rttk::CombineArgs ca{};
-  ca.u = h->d_u; ca.ue = h->d_ue; ca.v = h->d_v; ca.ve = h->d_ve;
+  ca.u = ws.u; ca.ue = ws.ue; ca.v = ws.v; ca.ve = ws.ve;
   ca.nsf = h->sched.nslot; ca.nsb = h->sched.nslot; ca.chi = h->chi; ca.T = h->T; ca.W = W;
   ca.N = h->N; ca.nw = h->nw; ca.fslot = h->d_fslot; ca.bslot = h->d_bslot; ca.coeffs = h->d_coeffs;
   ca.ng = h->sched.ng; ca.grp = h->d_grp;
@@ -989,6 +1005,75 @@ rtt_status rtt_evaluate(rtt_t h, rtt_ham_t ham, int32_t W, const uint64_t* spins
   hipLaunchKernelGGL(rttk::combine_kernel, dim3((W + 3) / 4), dim3(256), 0, s, ca);
   HIPX(hipGetLastError());
   return RTT_OK;
+}
+
+// Workspace of rtt_evaluate_noalloc: a file-scope device array, one copy per
+// GPU, held until the process ends.  In host code `scratch` only names the
+// symbol; its device address comes from hipGetSymbolAddress, once per
+// device, with that device current.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+rtt_status scratch_address(void** out) {
+  int dev = 0;
+  HIPX(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(RTT_E_UNSUPPORTED, "device %d: more devices than the library keeps", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIPX(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(RTT_E_HIP, "hipGetSymbolAddress returned no address for the scratch array");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return RTT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rtt_status rtt_evaluate(rtt_t h, rtt_ham_t ham, int32_t W, const uint64_t* spins, double* logabs,
+                        int8_t* sign, double* logratio, int8_t* rsign, double* eloc, int32_t* status,
+                        void* stream) {
+  g_err.clear();
+  rtt_status st = check_eval_args("rtt_evaluate", h, ham, W, spins, eloc);
+  if (st != RTT_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  if (!h->narrow && (st = ensure_ws(h, W, s)) != RTT_OK) return st;
+  return evaluate_on(h, ham, W, spins, logabs, sign, logratio, rsign, eloc, status,
+                     EvalWs{h->d_u, h->d_v, h->d_ue, h->d_ve}, s);
+}
+
+rtt_status rtt_evaluate_noalloc(rtt_t h, rtt_ham_t ham, int32_t W, const uint64_t* spins, double* logabs,
+                                int8_t* sign, double* logratio, int8_t* rsign, double* eloc,
+                                int32_t* status, void* stream) {
+  g_err.clear();
+  rtt_status st = check_eval_args("rtt_evaluate_noalloc", h, ham, W, spins, eloc);
+  if (st != RTT_OK) return st;
+  hipStream_t s = (hipStream_t)stream;
+  EvalWs ws{nullptr, nullptr, nullptr, nullptr};
+  if (!h->narrow) {
+    const size_t need = eval_ws_bytes(h, W);
+    if (need > kScratchBytes) {
+      const size_t per = eval_ws_bytes(h, 1);
+      return fail(RTT_E_ARG, "rtt_evaluate_noalloc: %d walkers need %zu bytes of workspace, more than the %zu "
+                  "bytes held for it (at most %zu walkers of this state per call)", W, need, kScratchBytes,
+                  kScratchBytes / per);
+    }
+    void* base = nullptr;
+    if ((st = scratch_address(&base)) != RTT_OK) return st;
+    const size_t rows = eval_ws_rows(h, W), vec = rows * h->chi * 4;
+    unsigned char* b = static_cast<unsigned char*>(base);
+    ws.u = reinterpret_cast<float*>(b);
+    ws.v = reinterpret_cast<float*>(b + vec);
+    ws.ue = reinterpret_cast<int*>(b + 2 * vec);
+    ws.ve = reinterpret_cast<int*>(b + 2 * vec + rows * 4);
+  }
+  return evaluate_on(h, ham, W, spins, logabs, sign, logratio, rsign, eloc, status, ws, s);
 }
 
 rtt_status rtt_flip_ratios(rtt_t h, int32_t W, const uint64_t* spins, double* logratio, int8_t* rsign,

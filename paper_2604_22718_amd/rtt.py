@@ -12,7 +12,7 @@ import ctypes as C
 import numpy as np
 import torch
 
-from ._lib import check, lib
+from ._lib import RTTError, check, lib  # noqa: F401  (RTTError: raised by check)
 
 DTYPES = {"f32": 1, "bf16": 2, "fp8": 3}
 
@@ -119,6 +119,15 @@ def rtt_evaluate(h, ham, spins, logabs=None, sign=None, logratio=None, rsign=Non
     check(lib().rtt_evaluate(h, ham, W, sp, _ptr(logabs, "logabs", F64, W), _ptr(sign, "sign", I8, W),
                              _ptr(logratio, "logratio", F64, W * N), _ptr(rsign, "rsign", I8, W * N),
                              _ptr(eloc, "eloc", F64, W), _ptr(status, "status", I32, W), _stream()))
+
+
+def rtt_evaluate_noalloc(h, ham, spins, logabs=None, sign=None, logratio=None, rsign=None, eloc=None,
+                         status=None):
+    N, nw = _words(h)
+    W, sp = _spins_ptr(spins, nw)
+    check(lib().rtt_evaluate_noalloc(h, ham, W, sp, _ptr(logabs, "logabs", F64, W), _ptr(sign, "sign", I8, W),
+                                     _ptr(logratio, "logratio", F64, W * N), _ptr(rsign, "rsign", I8, W * N),
+                                     _ptr(eloc, "eloc", F64, W), _ptr(status, "status", I32, W), _stream()))
 
 
 def rtt_amplitudes(h, spins, logabs, sign):
