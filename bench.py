@@ -1,13 +1,26 @@
 #!/usr/bin/env python3
 """Throughput of the RTT Monte Carlo hot path on one MI355X.
 
-One step = one single-spin-flip Metropolis sweep of every walker + local
-energies (all N flip ratios + diagonal) of every walker + the compensated
-FP64 energy reduction, on the 8x8 periodic TFIM workload (N = 64, R = 2,
-L = 128, chi = 64, 4096 walkers, h = 3.04; synthetic Gaussian cores).
+Headline workload: the 16x16 periodic TFIM (N = 256, h = 3.04), R = 2
+(L = 512, site order + a seeded permutation), bond 256, a linear combination
+of 4 RTTs with Gaussian real weights, FP8 e4m3 cores with a power-of-two
+scale per position, 16384 walkers, learned multi-spin proposal enabled.
+Synthetic Gaussian cores N(0, 1/chi).
+
+Before the timed region: burn-in sweeps, each followed by learned moves and
+one online training step of the proposal network (trained on the chain's
+own states), then the network is frozen.  One timed step = one
+single-spin-flip Metropolis sweep of every walker + the learned
+Metropolis-Hastings moves + local energies (all N flip ratios + diagonal)
+of every walker + the compensated FP64 energy reduction, all on the GPU.
 
 Prints one JSON line.  value = local-energy evaluations per second over the
-whole timed region (walkers x steps / time), inputs resident in HBM.
+whole timed region (walkers x steps / wall time), inputs resident in HBM.
+effective_samples_per_s divides by the integrated autocorrelation time of
+the walkers' local-energy series.  Energy errors against FP64 come from the
+oracle's stored values (tests/golden, written by oracle-only scripts): per
+sample on configurations the oracle's chain visited, and for the 8x8 lines
+as chain means against the oracle's FP64 chain.
 """
 import argparse
 import hashlib
@@ -22,9 +35,11 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"f32": 157.3e12, "bf16": 2.5e15, "fp8": 2.5e15}  # dense MFMA FLOP/s (fp8 cores run as bf16)
+# dense MFMA peaks (FLOP/s); FP8 cores are decoded to BF16 and run on the BF16 matrix ops
+PEAK = {"f32": 157.3e12, "bf16": 2.5e15, "fp8": 2.5e15}
 HBM_PEAK = 8.0e12
 METRIC = "local-energy evals/s & effective samples/s at fixed energy error vs FP64"
+HEADLINE = "tfim16x16_R2_chi256_W16384_T4"
 
 
 def schedule_rowsteps(pi, N, L, cut):
@@ -83,205 +98,6 @@ def traffic_from_profile(kernel, workload):
     return d.get("bytes_per_launch")
 
 
-def eloc_error(workload, dtype, e_gpu):
-    """Relative error of GPU local energies of the seeded initial walkers
-    against FP64 values stored by tests/golden/make_eloc_refs.py (computed by
-    the oracle on the same quantised cores, and on the unquantised cores)."""
-    p = os.path.join(ROOT, "tests", "golden", "eloc_fp64_refs.json")
-    if not os.path.exists(p):
-        return None
-    for c in json.load(open(p))["cases"]:
-        if c["workload"] == workload and c["dtype"] == dtype:
-            idx = np.array(c["walkers"])
-            got = np.asarray(e_gpu)[idx]
-            q, u = np.array(c["eloc_quantised_cores"]), np.array(c["eloc_fp64_cores"])
-            return {"eloc_max_rel_vs_fp64_same_cores": float(np.max(np.abs(got - q) / np.abs(q))),
-                    "eloc_median_rel_vs_fp64_same_cores": float(np.median(np.abs(got - q) / np.abs(q))),
-                    "eloc_max_rel_vs_fp64_unquantised_cores": float(np.max(np.abs(got - u) / np.abs(u))),
-                    "sample_walkers": idx.tolist(), "reference": "tests/golden/eloc_fp64_refs.json"}
-    return None
-
-
-def cpu_baseline(w, n_walkers, n_steps):
-    """The FP64 oracle on the host, single-threaded BLAS: the same step on a
-    sample of the workload's walkers."""
-    from threadpoolctl import threadpool_limits
-
-    from oracle import mcmc, rtt as orc, tfim
-    pi, cores = w.pi(), w.cores()
-    bits = w.spins(n_walkers)
-    bonds = tfim.bonds(w.Lx, w.Ly)
-    def steps(n):
-        t0 = time.perf_counter()
-        s = bits
-        for t in range(n):
-            s, _, _ = mcmc.metropolis(cores, pi, s, seed=w.chain_seed, stream=0, sweep0=t, n_sweeps=1)
-            orc.local_energy(cores, pi, s, bonds, w.J, w.h)
-        return time.perf_counter() - t0
-
-    with threadpool_limits(limits=1):
-        dt = steps(n_steps)
-    ncpu = len(os.sched_getaffinity(0))
-    n_all = max(1, n_steps // 3)
-    with threadpool_limits(limits=ncpu):
-        dt_all = steps(n_all)
-    return {"value": n_walkers * n_steps / dt, "unit": "local-energy evals/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"{n_walkers} walkers x {n_steps} steps (sweep + local energies) of the same "
-                      f"8x8 chi=64 workload, FP64 numpy, 1 BLAS thread, {dt:.1f} s",
-            "host_cpus_available": ncpu,
-            "all_cores": {"value": n_walkers * n_all / dt_all, "unit": "local-energy evals/s", "cores": ncpu,
-                          "sample": f"{n_walkers} walkers x {n_all} steps, BLAS threads = {ncpu}, "
-                                    f"{dt_all:.1f} s"}}
-
-
-def cpu_baseline_rows(n_dual=48, n_narrow=1024, n_wide=8):
-    """The FP64 oracle beside three more GPU lines, on samples of their
-    workloads, single-threaded BLAS: a dual Monte Carlo step (one sweep per
-    state, then overlap and mixed-energy estimators against all three
-    states; 8x8 chi=64), a sweep plus local energies of a chi = 2 train on
-    the 10x10 H+V+D+D' path (400 positions, the narrow-kernel shape), and
-    local energies of the 10x10 R=3 chi=128 workload (the wide-bond line)."""
-    from threadpoolctl import threadpool_limits
-
-    from oracle import dual, mcmc, rtt as orc, tfim
-    from paper_2604_22718_amd import lattice
-    from paper_2604_22718_amd import workloads as wl
-    out = {}
-    w = wl.MEDIUM_8x8
-    pi = w.pi()
-    a, b = w.cores(), wl.gaussian_cores(w.bond(), w.core_seed + 5)
-    states = [a, b, ([a, b], np.array([0.8, -1.1]))]
-    bonds = tfim.bonds(w.Lx, w.Ly)
-    with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
-        for i, st in enumerate(states):
-            amp = (lambda S, st=st: dual.state_amplitudes(st, pi, S))
-            s, _, _ = mcmc.metropolis(None, pi, w.spins(n_dual), seed=w.chain_seed, stream=100 + i, n_sweeps=1,
-                                      amp_fn=amp)
-            for st_b in states:
-                dual.mixed_estimators(st, st_b, pi, s, bonds, w.J, w.h)
-        dt = time.perf_counter() - t0
-    out["dual_mc"] = {"value": n_dual * 9 / dt, "unit": "mixed estimators/s", "cores": 1, "kind": "oracle",
-                      "sample": f"{n_dual} walkers per state, 3 states: one sweep each and 9 estimator "
-                                f"rows, 8x8 chi=64, FP64 numpy, {dt:.1f} s"}
-    L = 10
-    pi2 = lattice.path(L, L)
-    c2 = wl.gaussian_cores(wl.open_bonds(len(pi2), 2), 5)
-    with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
-        s, _, _ = mcmc.metropolis(c2, pi2, wl.random_spins(n_narrow, L * L, 6), seed=3, n_sweeps=1)
-        orc.local_energy(c2, pi2, s, tfim.bonds(L, L, periodic=False), 1.0, 3.0)
-        dt = time.perf_counter() - t0
-    out["narrow_chi2"] = {"value": n_narrow / dt, "unit": "local-energy evals/s (sweep + local energies)",
-                          "cores": 1, "kind": "oracle",
-                          "sample": f"{n_narrow} walkers x 1 step on the 10x10 open H+V+D+D' chi=2 train, "
-                                    f"FP64 numpy, {dt:.1f} s"}
-    ww = wl.WORKLOADS["tfim10x10_R3_chi128_W8192"]
-    with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
-        orc.local_energy(ww.cores(), ww.pi(), ww.spins(n_wide), tfim.bonds(ww.Lx, ww.Ly), ww.J, ww.h)
-        dt = time.perf_counter() - t0
-    out["wide_chi128"] = {"value": n_wide / dt, "unit": "local-energy evals/s", "cores": 1, "kind": "oracle",
-                          "sample": f"{n_wide} walkers x 1 local-energy evaluation of the 10x10 R=3 chi=128 "
-                                    f"workload, FP64 cores, FP64 numpy, {dt:.1f} s"}
-    return out
-
-
-def run(dtype, steps, warmup, with_cpu):
-    import torch
-
-    from paper_2604_22718_amd import rtt as R
-    from paper_2604_22718_amd import workloads as wl
-
-    w = wl.MEDIUM_8x8
-    pi, bond, cores = w.pi(), w.bond(), w.cores()
-    psi = R.RTT.create(w.N, pi, cores, dtype)
-    ham = R.TFIM(w.Lx, w.Ly, w.J, w.h)
-    bits = w.spins()
-    spins = R.spins_to_device(wl.pack_spins(bits))
-    W, N, L, chi = w.W, w.N, w.L, w.chi
-
-    # energy error vs FP64 on the seeded configurations (sample of walkers)
-    err = eloc_error(w.name, dtype, psi.local_energy(spins, ham).cpu().numpy())
-
-    eloc = torch.empty(W, dtype=torch.float64, device="cuda")
-    red = torch.empty(3, dtype=torch.float64, device="cuda")
-    acc = torch.zeros(W, dtype=torch.int32, device="cuda")
-    series = []
-
-    def step(t, ev=None):
-        if ev: ev[0].record()
-        psi.sweep(spins, seed=w.chain_seed, sweep0=t, n_sweeps=1, accepts=acc)
-        if ev: ev[1].record()
-        R.rtt_evaluate(psi.handle, ham.handle, spins, eloc=eloc)
-        if ev: ev[2].record()
-        R.rtt_energy_reduce(eloc, red)
-        if ev: ev[3].record()
-        series.append(red.clone())
-
-    for t in range(warmup):
-        step(t)
-    torch.cuda.synchronize()
-    series.clear()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for t in range(steps):
-        step(warmup + t, evs[t])
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    sweep_ms = np.array([e[0].elapsed_time(e[1]) for e in evs])
-    eval_ms = np.array([e[1].elapsed_time(e[2]) for e in evs])
-    red_ms = np.array([e[2].elapsed_time(e[3]) for e in evs])
-
-    sums = torch.stack(series).cpu().numpy()          # (steps, 3)
-    means = sums[:, 0] / sums[:, 2]
-    var = float(np.mean(sums[:, 1] / sums[:, 2] - means ** 2))
-    tau = stats_tau(means)
-    energy = float(np.mean(means))
-    ess = W * steps / tau
-
-    info = R.rtt_info(psi.handle)
-    fwd, bwd = schedule_rowsteps(pi, N, L, info["cut"])
-    flops_row = 2.0 * chi * chi
-    le_flops = W * (fwd + bwd) * flops_row
-    sw_flops = W * sweep_rowsteps(pi, N, L) * flops_row
-    kernels = {
-        "chain_kernel (1 sweep)": {"ms": float(sweep_ms.mean()), "algorithmic_flops": sw_flops,
-                                   "tflops": sw_flops / (sweep_ms.mean() * 1e-3) / 1e12},
-        "pass_kernel x2 + combine (local energies)": {"ms": float(eval_ms.mean()),
-                                                      "algorithmic_flops": le_flops,
-                                                      "tflops": le_flops / (eval_ms.mean() * 1e-3) / 1e12},
-        "reduce_kernel": {"ms": float(red_ms.mean())},
-    }
-    dom = "chain_kernel" if sweep_ms.mean() >= eval_ms.mean() else "evaluate"
-    if dom == "chain_kernel":
-        ach, nm = sw_flops / (sweep_ms.mean() * 1e-3), "chain_kernel"
-    else:
-        ach, nm = le_flops / (eval_ms.mean() * 1e-3), "pass_kernel+combine"
-    roof = {"kernel": nm, "bound": "mfma", "achieved": ach / 1e12, "peak": PEAK[dtype] / 1e12,
-            "unit": "TFLOP/s", "frac": ach / PEAK[dtype],
-            "traffic": traffic_from_profile(nm, w.name)}
-    res = {
-        "metric": METRIC, "value": W * steps / dt, "unit": "local-energy evals/s",
-        "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": dt / steps * 1e3,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
-        "data": "synthetic",
-        "config": {"workload": w.name, "lattice": f"{w.Lx}x{w.Ly} periodic TFIM", "J": w.J, "h": w.h,
-                   "R": w.R, "L": L, "chi": chi, "walkers": W,
-                   "step": "1 Metropolis sweep + local energies of all walkers + FP64 reduction"},
-        "effective_samples_per_s": ess / dt, "tau_int_steps": tau,
-        "energy_per_site": energy / N, "var_eloc": var,
-        "acceptance": float(acc.sum().item()) / (W * N * (steps + warmup)),
-        "energy_error": err,
-        "kernels": kernels,
-        "roofline": roof,
-    }
-    psi.close()
-    ham.close()
-    return res
-
 
 def run_batched(steps, n_rtt=256):
     """256 uneven RTTs (side 4..10, R 2..3, chi 16..128, 256..4096 walkers,
@@ -331,6 +147,7 @@ def run_batched(steps, n_rtt=256):
     return res
 
 
+
 def run_learned(n_meas=30, train_steps=150, learned_per_sweep=4):
     """10x10, R=3, chi=128, 8192 walkers, BF16: effective samples/s of
     single-flip sweeps alone vs single-flip sweeps + learned multi-spin moves
@@ -375,7 +192,7 @@ def run_learned(n_meas=30, train_steps=150, learned_per_sweep=4):
         torch.cuda.synchronize()
         secs = ev0.elapsed_time(ev1) * 1e-3
         e = torch.stack(series).cpu().numpy()
-        tau = stats_tau(e)
+        tau = tau_int(e)
         res = {"seconds": secs, "tau_int_measurements": tau, "energy_per_site": float(e.mean()) / w.N,
                "effective_samples_per_s": w.W * n_meas / tau / secs,
                "single_flip_acceptance": c.acc_flip.sum().item() / (w.W * w.N * (n_meas + 2))}
@@ -390,23 +207,6 @@ def run_learned(n_meas=30, train_steps=150, learned_per_sweep=4):
                        / out["single_flip"]["effective_samples_per_s"])
     return out
 
-
-def stats_tau(x):
-    """Integrated autocorrelation time of a 1-D series (Sokal window, c = 5)."""
-    x = np.asarray(x, dtype=np.float64)
-    n = len(x)
-    if n < 4:
-        return 1.0
-    d = x - x.mean()
-    c0 = np.mean(d * d)
-    if c0 == 0:
-        return 1.0
-    tau = 1.0
-    for M in range(1, n):
-        tau += 2.0 * np.mean(d[: n - M] * d[M:]) / c0
-        if M >= 5 * tau:
-            break
-    return max(tau, 1.0)
 
 
 def run_wide(name, n_eval=3, with_sweep=True):
@@ -434,7 +234,7 @@ def run_wide(name, n_eval=3, with_sweep=True):
     spins = R.spins_to_device(wl.pack_spins(bits))
     eloc = torch.empty(w.W, dtype=torch.float64, device="cuda")
     R.rtt_evaluate(psi.handle, ham.handle, spins, eloc=eloc)
-    err = eloc_error(w.name, dtype, eloc.cpu().numpy())
+    err = sampled_energy_error(R, psi, ham, w.name, dtype)
     torch.cuda.synchronize()
     e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     e[0].record()
@@ -466,6 +266,7 @@ def run_wide(name, n_eval=3, with_sweep=True):
     return out
 
 
+
 def run_dual(steps=5, warmup=1):
     """Dual Monte Carlo step on the 8x8 workload (chi=64, FP32, 4096 walkers
     per chain): three states (the workload's RTT, a second seeded RTT and
@@ -490,14 +291,15 @@ def run_dual(steps=5, warmup=1):
         la = torch.empty(W, dtype=torch.float64, device="cuda")
         sg = torch.empty(W, dtype=torch.int8, device="cuda")
         chains.append((spins, la, sg))
-    sums = torch.zeros((M, 2, M), dtype=torch.float64, device="cuda")
+    # per step and sampled state: the library's compensated row sums of both estimators
+    sums = torch.zeros((steps + warmup, M, 2, M, 1, 2), dtype=torch.float64, device="cuda")
 
     def step(t):
         for i, (spins, la, sg) in enumerate(chains):
             states[i].sweep(spins, seed=w.chain_seed, rng_stream=100 + i, sweep0=t, n_sweeps=1, logabs=la, sign=sg)
             ratio, mixed, _ = R.mixed_estimators(states, ham, spins, la, sg)
-            sums[i, 0] += ratio.mean(dim=1)
-            sums[i, 1] += mixed.mean(dim=1)
+            R.rtt_pair_sums(ratio, None, sums[t, i, 0])
+            R.rtt_pair_sums(mixed, None, sums[t, i, 1])
 
     for t in range(warmup):
         step(t)
@@ -509,8 +311,9 @@ def run_dual(steps=5, warmup=1):
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
-    S = (sums[:, 0] / (steps + warmup)).cpu().numpy()
-    H = (sums[:, 1] / (steps + warmup)).cpu().numpy()
+    X = sums.cpu().numpy()
+    S = (X[:, :, 0, :, 0, 0] / X[:, :, 0, :, 0, 1]).mean(axis=0)
+    H = (X[:, :, 1, :, 0, 0] / X[:, :, 1, :, 0, 1]).mean(axis=0)
     out = {"workload": w.name + "_dual3", "states": M, "walkers_per_chain": W, "ms_per_step": ms,
            "mixed_estimator_evals_per_s": W * M * M / (ms * 1e-3),
            "step": "per state: 1 sweep + overlap and mixed-energy estimators against all 3 states",
@@ -519,6 +322,7 @@ def run_dual(steps=5, warmup=1):
         x.close()
     ham.close()
     return out
+
 
 
 def time_narrow(N, pi, cores, ham, W=4096, reps=20):
@@ -562,6 +366,7 @@ def time_narrow(N, pi, cores, ham, W=4096, reps=20):
                       "unit": "TFLOP/s", "frac": sweep_flops / (sweep_ms * 1e9) / peak},
             "local_energy": {"bound": "alu", "achieved": le_flops / (le_ms * 1e9), "peak": peak,
                              "unit": "TFLOP/s", "frac": le_flops / (le_ms * 1e9) / peak}}
+
 
 
 # Operator sets of the paper's physical-space table (rows in its order) and
@@ -646,19 +451,394 @@ def run_paper_pipeline(L=10, steps=120, phys_steps=2, table=False):
     return out
 
 
+
+
+# ------------------------------------------------------------------ statistics
+def tau_int(E, c=5.0):
+    """Integrated autocorrelation time tau = 1 + 2 sum_t rho(t) of a (T,) or
+    (T, W) series (Sokal's window, c = 5).  With many walkers the
+    autocovariance is averaged over walkers around the global mean, so a
+    short series of many walkers still resolves rho(t) at small t.  A series
+    without fluctuations has tau = 1."""
+    x = np.asarray(E, dtype=np.float64)
+    if x.ndim == 1:
+        x = x[:, None]
+    T = x.shape[0]
+    if T < 2:
+        return 1.0
+    d = x - x.mean()
+    c0 = np.mean(d * d)
+    if not c0 > 0:
+        return 1.0
+    tau = 1.0
+    for M in range(1, T):
+        tau += 2.0 * np.mean(d[: T - M] * d[M:]) / c0
+        if M >= c * tau:
+            break
+    return max(tau, 1.0)
+
+
+def energy_stats(E, N):
+    """Mean (exactly rounded), variance, tau_int, sigma of the mean and the
+    V-score N var / E^2 of a (T, W) local-energy series."""
+    x = np.asarray(E, dtype=np.float64)
+    mean = math.fsum(x.ravel()) / x.size
+    var = float(np.mean((x - mean) ** 2))
+    tau = tau_int(x)
+    sigma = math.sqrt(var * tau / x.size)
+    return {"E_per_site": mean / N, "sigma_per_site": sigma / N, "tau_int": tau, "var_eloc": var,
+            "v_score": N * var / (mean * mean) if mean != 0 else None, "samples": int(x.size)}
+
+
+# ------------------------------------------------------------------ stored FP64 references
+def golden(name, dtype):
+    """Configurations the oracle's chain visited and its FP64 values there,
+    stored by tests/golden/make_sampled_refs.py (None if absent)."""
+    p = os.path.join(ROOT, "tests", "golden", "sampled_refs.json")
+    if not os.path.exists(p):
+        return None
+    for c in json.load(open(p))["cases"]:
+        if c["workload"] == name and c["dtype"] == dtype:
+            out = dict(c)
+            for k in ("start", "sampled", "after", "final"):
+                out[k] = np.array([[int(x, 16) for x in row] for row in c[k]], dtype=np.uint64)
+            return out
+    return None
+
+
+def sampled_energy_error(R, psi, ham, name, dtype):
+    """GPU local energies on the oracle-sampled configurations against the
+    oracle's FP64 values on the same quantised cores (arithmetic error) and
+    on the unquantised FP64 cores (arithmetic + state quantisation)."""
+    import torch
+    g = golden(name, dtype)
+    if g is None:
+        return None
+    spins = R.spins_to_device(g["sampled"])
+    e = psi.local_energy(spins, ham)
+    torch.cuda.synchronize()
+    e = e.cpu().numpy()
+    q, u = np.array(g["eloc_quantised_cores"]), np.array(g["eloc_fp64_cores"])
+    rq = np.abs(e - q) / np.maximum(1.0, np.abs(q))
+    ru = np.abs(e - u) / np.maximum(1.0, np.abs(u))
+    return {"walkers": len(e), "configurations": f"oracle Metropolis chain, {g['burn']} sweeps from the seeded walkers",
+            "max_rel_vs_fp64_same_cores": float(rq.max()), "median_rel_vs_fp64_same_cores": float(np.median(rq)),
+            "mean_diff_vs_fp64_same_cores": float(np.mean(e - q)),
+            "max_rel_vs_fp64_unquantised_cores": float(ru.max()),
+            "mean_diff_vs_fp64_unquantised_cores": float(np.mean(e - u)),
+            "reference": "tests/golden/sampled_refs.json"}
+
+
+def build_state(R, w, dtype):
+    pi = w.pi()
+    if w.n_terms == 1:
+        return R.RTT.create(w.N, pi, w.cores(), dtype)
+    terms = [R.RTT.create(w.N, pi, w.cores(t), dtype) for t in range(w.n_terms)]
+    psi = R.RTT.lincomb(terms, w.coeffs())
+    for t in terms:
+        t.close()
+    return psi
+
+
+def core_bytes(w, chi_pad, dtype):
+    """Device bytes of the packed cores: both fragment layouts, every term."""
+    eb = {"f32": 4, "bf16": 2, "fp8": 1}[dtype]
+    return 2 * w.n_terms * w.L * 2 * chi_pad * chi_pad * eb
+
+
+# ------------------------------------------------------------------ headline
+def headline(steps, warmup, burn, learned_per_step=2, lr=1e-3):
+    """The 16x16 chi=256 four-term FP8 workload with the learned proposal
+    (see the module docstring).  Returns the bench record."""
+    import torch
+
+    from paper_2604_22718_amd import rtt as R
+    from paper_2604_22718_amd import workloads as wl
+    w = wl.WORKLOADS[HEADLINE]
+    dtype = w.dtype
+    t_setup = time.perf_counter()
+    psi = build_state(R, w, dtype)
+    info = psi.info
+    ham = R.TFIM(w.Lx, w.Ly, w.J, w.h)
+    net = R.Net(w.Lx, w.Ly, wl.net_init_params(4005))
+    spins = R.spins_to_device(wl.pack_spins(w.spins()))
+    ch = R.LearnedChain(psi, net, spins, seed=w.chain_seed)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t_setup
+    err = sampled_energy_error(R, psi, ham, w.name, dtype)
+
+    # burn-in with online training of the proposal network on the chain's states
+    t_burn = time.perf_counter()
+    burn_means = []
+    for t in range(burn):
+        ch.sweep(1)
+        for _ in range(learned_per_step):
+            ch.learned_step()
+            ch.train(lr=lr)
+        if t % 5 == 4 or t == burn - 1:
+            burn_means.append(float(psi.local_energy(ch.spins, ham).mean().item()) / w.N)
+        print(f"[bench] burn-in sweep {t + 1}/{burn}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    burn_s = time.perf_counter() - t_burn
+    acc_flip0, acc_learn0 = ch.acc_flip.sum().item(), ch.acc_learn.sum().item()
+    sweeps0, steps0 = ch.sweeps, ch.steps
+
+    W = w.W
+    eloc = torch.empty(W, dtype=torch.float64, device="cuda")
+    red = torch.empty(3, dtype=torch.float64, device="cuda")
+    series, sums = [], []
+
+    def step(ev=None):
+        if ev: ev[0].record()
+        ch.sweep(1)
+        if ev: ev[1].record()
+        for _ in range(learned_per_step):
+            ch.learned_step()
+        if ev: ev[2].record()
+        R.rtt_evaluate(psi.handle, ham.handle, ch.spins, eloc=eloc)
+        if ev: ev[3].record()
+        R.rtt_energy_reduce(eloc, red)
+        if ev: ev[4].record()
+        series.append(eloc.clone())
+        sums.append(red.clone())
+
+    for t in range(warmup):
+        step()
+        print(f"[bench] warm-up step {t + 1}/{warmup}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    series.clear()
+    sums.clear()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in range(steps):
+        step(evs[t])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print(f"[bench] {steps} timed steps in {dt:.1f} s", file=sys.stderr, flush=True)
+    ms = lambda a, b: np.array([e[a].elapsed_time(e[b]) for e in evs])
+    sweep_ms, learn_ms, eval_ms, red_ms = ms(0, 1), ms(1, 2), ms(2, 3), ms(3, 4)
+
+    E = torch.stack(series).cpu().numpy()            # (steps, W)
+    S = torch.stack(sums).cpu().numpy()              # (steps, 3): library's compensated sums
+    st = energy_stats(E, w.N)
+    st["E_per_site_library_reduce"] = float(S[:, 0].sum() / S[:, 2].sum()) / w.N
+    st["finite_fraction"] = float(S[:, 2].sum() / (W * steps))
+
+    pi, T, chi = w.pi(), w.n_terms, info["chi"]
+    fwd, bwd = schedule_rowsteps(pi, w.N, w.L, info["cut"])
+    row = 2.0 * chi * chi
+    le_flops = W * T * (fwd + bwd) * row
+    sw_flops = W * T * sweep_rowsteps(pi, w.N, w.L) * row
+    am_flops = W * T * w.L * row                      # one amplitude per learned move
+    kernels = {
+        "chain_kernel (1 sweep)": {"ms": float(sweep_ms.mean()), "algorithmic_flops": sw_flops,
+                                   "tflops": sw_flops / (sweep_ms.mean() * 1e-3) / 1e12},
+        f"learned moves x{learned_per_step} (network kernels + chain_kernel amplitudes)":
+            {"ms": float(learn_ms.mean()), "algorithmic_flops_amplitudes": learned_per_step * am_flops},
+        "pass_kernel x2 + combine (local energies)": {"ms": float(eval_ms.mean()), "algorithmic_flops": le_flops,
+                                                      "tflops": le_flops / (eval_ms.mean() * 1e-3) / 1e12,
+                                                      "frac_bf16_peak": le_flops / (eval_ms.mean() * 1e-3) / PEAK["bf16"]},
+        "reduce_kernel": {"ms": float(red_ms.mean())},
+    }
+    ach = sw_flops / (sweep_ms.mean() * 1e-3)
+    nm = "chain_kernel"
+    if eval_ms.mean() > sweep_ms.mean():
+        ach, nm = le_flops / (eval_ms.mean() * 1e-3), "pass_kernel+combine"
+    roof = {"kernel": nm, "bound": "mfma", "achieved": ach / 1e12, "peak": PEAK[dtype] / 1e12,
+            "unit": "TFLOP/s", "frac": ach / PEAK[dtype],
+            "traffic": traffic_from_profile(nm, w.name),
+            "flop_count": "method minimum: L + sum_j (last_j - first_j + 1) row-steps per walker-sweep and "
+                          "term, 2 chi^2 flops each (the hi+lo BF16 activation split and both core slices, "
+                          "which the matrix ops also execute, are not counted)"}
+    ess = W * steps / st["tau_int"]
+    n_fl = (ch.sweeps - sweeps0) * W * w.N
+    n_le = (ch.steps - steps0) * W
+    res = {
+        "metric": METRIC, "value": W * steps / dt, "unit": "local-energy evals/s",
+        "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": dt / steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+        "data": "synthetic (seeded Gaussian cores, seeded walkers)",
+        "config": {"workload": w.name, "lattice": f"{w.Lx}x{w.Ly} periodic TFIM", "J": w.J, "h": w.h,
+                   "R": w.R, "L": w.L, "chi": w.chi, "terms": T, "walkers": W, "core_dtype": "fp8_e4m3",
+                   "core_bytes_on_device": core_bytes(w, chi, "fp8"),
+                   "learned_proposal": {"enabled": True, "moves_per_step": learned_per_step,
+                                        "trained_steps": burn * learned_per_step, "frozen_when_timed": True},
+                   "burn_in_sweeps": burn,
+                   "step": "1 Metropolis sweep + learned MH moves + local energies of all walkers + FP64 reduction"},
+        "effective_samples_per_s": ess / dt,
+        "energy": st,
+        "energy_error": err,
+        "acceptance": {"single_flip": (ch.acc_flip.sum().item() - acc_flip0) / max(1, n_fl),
+                       "learned": (ch.acc_learn.sum().item() - acc_learn0) / max(1, n_le)},
+        "burn_in": {"seconds": burn_s, "E_per_site_every_5_sweeps": burn_means},
+        "setup_s": setup_s,
+        "kernels": kernels,
+        "roofline": roof,
+    }
+    net.close()
+    psi.close()
+    ham.close()
+    torch.cuda.empty_cache()
+    return res
+
+
+# ------------------------------------------------------------------ 8x8 chains
+def chain_line(dtype, burn=None, meas=None):
+    """8x8, chi = 64, 4096 walkers: burn-in, then measured steps of one sweep +
+    local energies + FP64 reduction.  Energy against the oracle's FP64 chain
+    (16 of the same walkers, same Philox words, stored) and, where the
+    trajectories coincide (FP32), sample by sample."""
+    import torch
+
+    from paper_2604_22718_amd import rtt as R
+    from paper_2604_22718_amd import workloads as wl
+    w = wl.MEDIUM_8x8
+    burn = w.burn_in if burn is None else burn
+    meas = w.sweeps if meas is None else meas
+    psi = build_state(R, w, dtype)
+    info = psi.info
+    ham = R.TFIM(w.Lx, w.Ly, w.J, w.h)
+    spins = R.spins_to_device(wl.pack_spins(w.spins()))
+    W = w.W
+    eloc = torch.empty(W, dtype=torch.float64, device="cuda")
+    red = torch.empty(3, dtype=torch.float64, device="cuda")
+    acc = torch.zeros(W, dtype=torch.int32, device="cuda")
+    # burn-in and the oracle's decision sweep: sweeps 0 .. burn
+    psi.sweep(spins, seed=w.chain_seed, sweep0=0, n_sweeps=burn + 1)
+    series = []
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(meas)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for t in range(meas):
+        e = evs[t]
+        e[0].record()
+        psi.sweep(spins, seed=w.chain_seed, sweep0=burn + 1 + t, n_sweeps=1, accepts=acc)
+        e[1].record()
+        R.rtt_evaluate(psi.handle, ham.handle, spins, eloc=eloc)
+        e[2].record()
+        R.rtt_energy_reduce(eloc, red)
+        e[3].record()
+        series.append(eloc.clone())
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    sweep_ms = np.array([e[0].elapsed_time(e[1]) for e in evs])
+    eval_ms = np.array([e[1].elapsed_time(e[2]) for e in evs])
+    E = torch.stack(series).cpu().numpy()
+    st = energy_stats(E, w.N)
+    out = {"workload": w.name, "dtype": dtype, "walkers": W, "burn_in_sweeps": burn + 1, "measured_steps": meas,
+           "ms_per_step": dt / meas * 1e3, "le_evals_per_s": W * meas / dt,
+           "effective_samples_per_s": W * meas / st["tau_int"] / dt, "energy": st,
+           "acceptance": float(acc.sum().item()) / (W * w.N * meas)}
+    pi, chi = w.pi(), info["chi"]
+    fwd, bwd = schedule_rowsteps(pi, w.N, w.L, info["cut"])
+    row = 2.0 * chi * chi
+    le_flops, sw_flops = W * (fwd + bwd) * row, W * sweep_rowsteps(pi, w.N, w.L) * row
+    out["kernels"] = {"chain_kernel (1 sweep)": {"ms": float(sweep_ms.mean()),
+                                                 "tflops": sw_flops / (sweep_ms.mean() * 1e-3) / 1e12},
+                      "pass_kernel x2 + combine": {"ms": float(eval_ms.mean()),
+                                                   "tflops": le_flops / (eval_ms.mean() * 1e-3) / 1e12}}
+    dom = ("chain_kernel", sw_flops, sweep_ms) if sweep_ms.mean() >= eval_ms.mean() else \
+        ("pass_kernel+combine", le_flops, eval_ms)
+    ach = dom[1] / (dom[2].mean() * 1e-3)
+    out["roofline"] = {"kernel": dom[0], "bound": "mfma", "achieved": ach / 1e12, "peak": PEAK[dtype] / 1e12,
+                       "unit": "TFLOP/s", "frac": ach / PEAK[dtype], "traffic": traffic_from_profile(dom[0], w.name)}
+    g = golden(w.name, dtype)
+    if g is not None:
+        eo = np.array(g["eloc_series"])                  # (meas, 16): oracle FP64 chain energies
+        so = energy_stats(eo, w.N)
+        z = abs(st["E_per_site"] - so["E_per_site"]) / math.hypot(st["sigma_per_site"], so["sigma_per_site"])
+        ee = {"oracle_chain": {"walkers": eo.shape[1], "measured_sweeps": eo.shape[0],
+                               "E_per_site": so["E_per_site"], "sigma_per_site": so["sigma_per_site"]},
+              "abs_diff_per_site": abs(st["E_per_site"] - so["E_per_site"]), "z": z}
+        ids = np.array(g["walkers"])
+        same = np.all(R.spins_to_host(spins)[ids] == g["final"], axis=1)
+        ee["oracle_walkers_on_same_trajectory"] = int(same.sum())
+        if same.any() and eo.shape[0] == meas:
+            rel = np.abs(E[:, ids[same]] - eo[:, same]) / np.maximum(1.0, np.abs(eo[:, same]))
+            ee["per_sample_on_same_trajectory"] = {"samples": int(rel.size), "max_rel": float(rel.max()),
+                                                   "median_rel": float(np.median(rel)),
+                                                   "mean_diff_per_site": float(np.mean(E[:, ids[same]] - eo[:, same])) / w.N}
+        out["energy_error_vs_fp64"] = ee
+    out["energy_error_sampled"] = sampled_energy_error(R, psi, ham, w.name, dtype)
+    psi.close()
+    ham.close()
+    return out
+
+
+# ------------------------------------------------------------------ CPU oracle
+def cpu_baseline(n_props=16, n_ratios=64):
+    """The FP64 oracle on the host, one BLAS thread, on a bounded sample of the
+    headline workload (one walker at the first oracle-sampled configuration):
+    its Metropolis sweep costs two full amplitudes (4 terms x 512 positions)
+    per proposal, timed on n_props proposals and scaled to the 256 of a sweep;
+    its local energy costs the N flipped amplitudes, timed on n_ratios spins
+    and scaled to 256.  The two give the oracle's time for one walker-step
+    (sweep + local energy), i.e. its local-energy evals/s at the step the GPU
+    times (learned moves excluded: they add two network passes and one
+    amplitude)."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import quant, rtt as orc
+    from paper_2604_22718_amd import workloads as wl
+    w = wl.WORKLOADS[HEADLINE]
+    pi, c = w.pi(), w.coeffs()
+    terms = [quant.quantise_cores(w.cores(t), w.dtype) for t in range(w.n_terms)]
+    g = golden(w.name, w.dtype)
+    s = wl.unpack_spins(g["sampled"][:1], w.N) if g is not None else w.spins(1)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        for j in range(n_props):
+            orc.lincomb_amplitudes(terms, c, pi, s)
+            orc.lincomb_amplitudes(terms, c, pi, orc.flip(s, j))
+        t_props = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        orc.lincomb_flip_ratios(terms, c, pi, s, which=list(range(n_ratios)))
+        t_ratios = time.perf_counter() - t0
+    step_s = t_props * w.N / n_props + t_ratios * w.N / n_ratios
+    return {"value": 1.0 / step_s, "unit": "local-energy evals/s", "cores": 1, "kind": "oracle",
+            "sample": f"1 walker of the {w.name} workload (FP8-quantised cores, FP64 numpy): {n_props} Metropolis "
+                      f"proposals ({t_props:.1f} s) and {n_ratios} of the {w.N} flip ratios of a local energy "
+                      f"({t_ratios:.1f} s), scaled to one sweep + local energy = {step_s:.0f} s per walker-step",
+            "host_cpus_available": len(os.sched_getaffinity(0))}
+
+
+def cpu_baseline_8x8(n_walkers=64, n_steps=6):
+    """The oracle's step (sweep + local energies) on a sample of the 8x8
+    workload's walkers, one BLAS thread (beside the 8x8 lines)."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import mcmc, quant, rtt as orc, tfim
+    from paper_2604_22718_amd import workloads as wl
+    w = wl.MEDIUM_8x8
+    pi, cores = w.pi(), quant.quantise_cores(w.cores(), "f32")
+    s = w.spins(n_walkers)
+    bonds = tfim.bonds(w.Lx, w.Ly)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        for t in range(n_steps):
+            s, _, _ = mcmc.metropolis(cores, pi, s, seed=w.chain_seed, stream=0, sweep0=t, n_sweeps=1)
+            orc.local_energy(cores, pi, s, bonds, w.J, w.h)
+        dt = time.perf_counter() - t0
+    return {"value": n_walkers * n_steps / dt, "unit": "local-energy evals/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n_walkers} walkers x {n_steps} steps (sweep + local energies) of {w.name}, FP64 numpy, "
+                      f"{dt:.1f} s"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--dtype", default="f32", choices=["f32", "bf16", "fp8"])
+    ap.add_argument("--steps", type=int, default=8, help="timed steps of the headline workload")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--burn", type=int, default=None, help="burn-in sweeps (default: the workload's, 20)")
+    ap.add_argument("--learned-per-step", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
-    ap.add_argument("--also", default="bf16", help="second precision reported alongside ('' for none)")
+    ap.add_argument("--no-8x8", action="store_true", help="skip the 8x8 FP32 / BF16 chain lines")
+    ap.add_argument("--no-wide", action="store_true", help="skip the 10x10 chi=128 BF16 wide-bond line")
+    ap.add_argument("--only-8x8", action="store_true", help="only the 8x8 lines (no headline)")
     ap.add_argument("--batched", type=int, default=0, help="also time the 256-RTT batch for this many steps")
     ap.add_argument("--learned", action="store_true", help="also compare learned-proposal ESS/s (10x10, chi=128)")
-    ap.add_argument("--no-wide", action="store_true", help="skip the 10x10 chi=128 BF16 wide-bond line")
-    ap.add_argument("--huge", action="store_true", help="also time the 16x16 chi=256 4-term FP8 workload (slow)")
-    ap.add_argument("--no-dual", action="store_true", help="skip the dual Monte Carlo line")
+    ap.add_argument("--dual", action="store_true", help="also the dual Monte Carlo line")
     ap.add_argument("--paper-pipeline", type=int, default=0, metavar="STEPS",
                     help="also run the chi=2 power method for STEPS steps plus two physical-space steps")
     ap.add_argument("--paper-side", type=int, default=10, help="lattice side of the chi=2 pipeline (10 or 20)")
@@ -683,16 +863,19 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copied_bytes_per_launch": n * 4}))
         return
-    res = run(a.dtype, a.steps, a.warmup, not a.no_cpu)
-    if a.also and a.also != a.dtype:
-        other = run(a.also, a.steps, a.warmup, False)
-        res["also"] = {k: other[k] for k in ("dtype", "value", "ms_per_step", "effective_samples_per_s",
-                                             "energy_error", "kernels", "roofline")}
+    from paper_2604_22718_amd import workloads as wl
+    if a.only_8x8:
+        res = {"lines_8x8": [chain_line("f32"), chain_line("bf16")]}
+        print(json.dumps(res), flush=True)
+        return
+    burn = wl.WORKLOADS[HEADLINE].burn_in if a.burn is None else a.burn
+    res = headline(a.steps, a.warmup, burn, a.learned_per_step)
+    if not a.no_8x8:
+        res["lines_8x8"] = [chain_line("f32"), chain_line("bf16")]
+        print("[bench] 8x8 lines done", file=sys.stderr, flush=True)
     if not a.no_wide:
         res["wide_bond"] = [run_wide("tfim10x10_R3_chi128_W8192")]
-        if a.huge:
-            res["wide_bond"].append(run_wide("tfim16x16_R2_chi256_W16384_T4", n_eval=1))
-    if not a.no_dual:
+    if a.dual:
         res["dual_mc"] = run_dual()
     if a.paper_pipeline:
         res["paper_pipeline"] = run_paper_pipeline(L=a.paper_side, steps=a.paper_pipeline, table=a.paper_table)
@@ -701,9 +884,8 @@ def main():
     if a.learned:
         res["learned"] = run_learned()
     if not a.no_cpu:
-        from paper_2604_22718_amd import workloads as wl
-        res["cpu_baseline"] = cpu_baseline(wl.MEDIUM_8x8, 64, 12)
-        res["cpu_baseline"]["rows"] = cpu_baseline_rows()
+        res["cpu_baseline"] = cpu_baseline()
+        res["cpu_baseline"]["beside_8x8"] = cpu_baseline_8x8()
     print(json.dumps(res), flush=True)
 
 

@@ -318,6 +318,22 @@ rtt_status rtt_tt_combine(int32_t n_trains, int32_t n_cores, const int32_t* bond
 rtt_status rtt_energy_reduce(int32_t n, const double* x, double* out, void* stream);
 
 /*
+ * Compensated (Neumaier) FP64 sums of row products (device buffers):
+ *   out[2 (a B + b)]     = sum_w x[a][w] * y[b][w]
+ *   out[2 (a B + b) + 1] = number of w whose product is finite (summed)
+ * for a < A, b < B; x double[A][W], y double[B][W], out double[A][B][2].
+ * With y = NULL (and B = 1) the rows of x are summed alone.  Non-finite
+ * terms are skipped and not counted.  These are the averages of dual Monte
+ * Carlo (Sec. 3.3): rows of S~ and H~ from the estimators of
+ * rtt_mixed_estimators, and, for states that differ from the sampled one
+ * by diagonal (Z) operators (Sec. 4.1.3), S_ab = <r_a r_b> and
+ * H_ab = <r_a m_b> from one chain.  Stream-ordered; RTT_E_ARG for A, B or
+ * W < 1, null x or out, or y = NULL with B != 1.
+ */
+rtt_status rtt_pair_sums(int32_t A, int32_t B, int32_t W, const double* x, const double* y, double* out,
+                         void* stream);
+
+/*
  * Batches: many independent RTT Monte Carlo runs of uneven size stepped
  * together in one captured HIP graph of persistent kernels.
  *

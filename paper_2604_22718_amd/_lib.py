@@ -33,6 +33,7 @@ SIGNATURES = {
     "rtt_mcmc_sweep": (C.c_int, [P, C.c_int32, P, P, P, C.c_uint64, C.c_uint64, C.c_uint64,
                                  C.c_int32, P, P, P]),
     "rtt_energy_reduce": (C.c_int, [C.c_int32, P, P, P]),
+    "rtt_pair_sums": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, P, P, P, P]),
     "rtt_mixed_estimators": (C.c_int, [C.c_int32, P, P, C.c_int32, P, P, P, P, P, P, P]),
     "rtt_tt_round": (C.c_int, [C.c_int32, P, P, C.c_int32, C.c_double, P, P, C.c_int64, C.POINTER(C.c_int64)]),
     "rtt_pauli_apply": (C.c_int, [C.c_int32, P, P, C.c_int32, P, P, C.c_double, C.c_double, C.c_int32,

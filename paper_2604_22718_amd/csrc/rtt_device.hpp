@@ -143,6 +143,10 @@ constexpr float kFp8Scale = 0.001953125f;  // 2^-9
 struct DFP8 {
   using elem = uint8_t;
   static constexpr bool kF32 = false;
+  // a lane's KPL codes decoded to BF16 bits (for fragments that serve many
+  // matrix ops: decode once, then run them as BF16)
+  template <int KPL>
+  __device__ __forceinline__ static void decode(const uint8_t (&a)[KPL], uint16_t (&out)[KPL]);
   template <int KPL>
   using BOp = DBF16::BOp<KPL>;
   template <int KPL>
@@ -191,6 +195,16 @@ struct DFP8 {
     }
   }
 };
+
+template <int KPL>
+__device__ __forceinline__ void DFP8::decode(const uint8_t (&a)[KPL], uint16_t (&out)[KPL]) {
+#pragma unroll
+  for (int c = 0; c < KPL / 8; ++c) {
+    const u16x8 v = __builtin_bit_cast(u16x8, pack<KPL>(a, c));
+#pragma unroll
+    for (int i = 0; i < 8; ++i) out[8 * c + i] = v[i];
+  }
+}
 
 // Workgroup barrier that orders LDS only: global loads issued before it
 // (prefetched core fragments) stay in flight across it.

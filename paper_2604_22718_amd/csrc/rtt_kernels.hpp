@@ -16,11 +16,22 @@
 #include <float.h>
 #include <math.h>
 
+#include <type_traits>
+
 #include "rtt_device.hpp"
 
 namespace rttk {
 
 constexpr int kMaxTerms = 8;
+#ifndef PASS_PF_FP8
+#define PASS_PF_FP8 2
+#endif
+#ifndef CHAIN_PF_FP8_256
+#define CHAIN_PF_FP8_256 2
+#endif
+#ifndef CHAIN_SW_FP8_256
+#define CHAIN_SW_FP8_256 2
+#endif
 // steps between power-of-two renormalisations: a row grows by at most chi
 // per step, so 8 steps stay below 2^64 even at chi = 256 (FP32 range 2^128)
 constexpr int kRenormEvery = 8;
@@ -103,6 +114,12 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int bx, int ty) {
   constexpr int NIS = MT / MTI;  // items per step
   constexpr bool ODD_MFMA = !D::kF32;
   struct Frags { E m[MTI][KPL]; E o[MTI][KPL]; };
+  // FP8 fragments stay codes while their loads are in flight and are decoded
+  // to BF16 once per item, since every row tile of the step uses them; the
+  // matrix ops then run as for BF16 cores
+  constexpr bool kDec = std::is_same<D, DFP8>::value;
+  using DR = typename std::conditional<kDec, DBF16, D>::type;
+  using ER = typename DR::elem;
   const int n_items = gs.y * NIS;
   auto load = [&](Frags& F, int item) {
     const int s = item / NIS, ig = item % NIS;
@@ -119,6 +136,19 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int bx, int ty) {
     const int s = item / NIS, ig = item % NIS;
     const int4 st = sched[s];
     const int k = st.x, nact = st.z, odd = st.w;
+    ER Fm[MTI][KPL];
+    if constexpr (kDec) {
+#pragma unroll
+      for (int q = 0; q < MTI; ++q) D::template decode<KPL>(F.m[q], Fm[q]);
+    }
+    auto fm = [&](int q) -> const ER(&)[KPL] {
+      if constexpr (kDec) return Fm[q];
+      else return F.m[q];
+    };
+    auto fo = [&](int q, ER (&tmp)[KPL]) -> const ER(&)[KPL] {
+      if constexpr (kDec) { D::template decode<KPL>(F.o[q], tmp); return tmp; }
+      else return F.o[q];
+    };
     const int cexp = cexp_p ? cexp_p[k] : 0;
     const int ntile = (nact + 15) >> 4;
     // rows are renormalised every kRenormEvery steps: between two, a row
@@ -142,7 +172,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int bx, int ty) {
 #pragma unroll
       for (int q = 0; q < MTI; ++q) {
         f4 acc = {0.f, 0.f, 0.f, 0.f};
-        acc = D::template mma<KPL>(F.m[q], bo, acc);
+        acc = DR::template mma<KPL>(fm(q), bo, acc);
 #pragma unroll
         for (int i = 0; i < 4; ++i) acc[i] *= sc;
         A::store4(nxt + row * RS, 16 * (wv * MT + ig * MTI + q) + 4 * g, acc);
@@ -152,7 +182,8 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int bx, int ty) {
 #pragma unroll
         for (int q = 0; q < MTI; ++q) {
           f4 acc = {0.f, 0.f, 0.f, 0.f};
-          acc = D::template mma<KPL>(F.o[q], bo, acc);
+          ER tmp[KPL];
+          acc = DR::template mma<KPL>(fo(q, tmp), bo, acc);
 #pragma unroll
           for (int i = 0; i < 4; ++i) acc[i] *= sc;
           oacc[q] = acc;
@@ -181,7 +212,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int bx, int ty) {
       for (int q = 0; q < MTI; ++q) {
         float p = 0.f;
 #pragma unroll
-        for (int c = 0; c < KPL; ++c) p = fmaf(D::to_f32(F.o[q][c]), v[c], p);
+        for (int c = 0; c < KPL; ++c) p = fmaf(DR::to_f32(F.o[q][c]), v[c], p);
         p += __shfl_xor(p, 16);
         p += __shfl_xor(p, 32);
         if (g == 0) A::store1(nxt + oout * RS, 16 * (wv * MT + ig * MTI + q) + m, __builtin_amdgcn_ldexpf(p, -e));
@@ -194,17 +225,24 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int bx, int ty) {
       int* te = exc; exc = exn; exn = te;
     }
   };
-  // prefetch on every path (clamped to the last item) so that the wait
-  // before the matrix ops never covers the item being prefetched
-  Frags FA, FB;
+  // A ring of PFP fragment sets: loads run PFP - 1 items ahead of the
+  // matrix ops, issued on every path (clamped to the last item) so that the
+  // wait before the matrix ops never covers an item still being prefetched.
+  // FP8 sets are half the registers of BF16 ones, which pays for a third
+  // set at bond 256, where one wave per SIMD leaves the fragment
+  // latency exposed.
+  constexpr int PFP = (kDec && CHI == 256) ? PASS_PF_FP8 : 2;
+  Frags FR[PFP];
   if (n_items > 0) {
-    load(FA, 0);
-    for (int i = 0; i < n_items; i += 2) {
-      load(FB, min(i + 1, n_items - 1));
-      compute(FA, i);
-      if (i + 1 >= n_items) break;
-      load(FA, min(i + 2, n_items - 1));
-      compute(FB, i + 1);
+#pragma unroll
+    for (int q = 0; q < PFP - 1; ++q) load(FR[q], min(q, n_items - 1));
+    for (int i = 0; i < n_items; i += PFP) {
+#pragma unroll
+      for (int r = 0; r < PFP; ++r) {
+        if (i + r >= n_items) break;
+        load(FR[(r + PFP - 1) % PFP], min(i + r + PFP - 1, n_items - 1));
+        compute(FR[r], i + r);
+      }
     }
   }
   __syncthreads();
@@ -407,14 +445,18 @@ struct ChainLayout {
 // Waves per side of the chain kernel: two sides of up to four waves, except
 // that wide bonds keep one wave per SIMD (their fragments need the whole
 // register file) with two waves per side.
-template <int CHI>
+template <int CHI, class D = DBF16>
 struct ChainGeo {
-  static constexpr int SW = CHI >= 128 ? 2 : Geo<CHI>::WPW;  // waves per side
+  // waves per side: FP8 fragments are half the registers, which lets the
+  // bond-256 kernel run four waves per side (two per SIMD, CHAIN_SW_FP8_256)
+  static constexpr int SW = (CHI == 256 && std::is_same<D, DFP8>::value) ? CHAIN_SW_FP8_256
+                            : CHI >= 128 ? 2 : Geo<CHI>::WPW;
   static constexpr int MT = CHI / (16 * SW);                   // output tiles per wave
   static constexpr int NT = 2 * SW * 64;                       // threads per block
   // fragment sets in the prefetch ring (see chain_body)
   template <class E>
-  static constexpr int PF = ((CHI == 128 && sizeof(E) == 2) || (CHI == 128 && sizeof(E) == 1)) ? 4 : 2;
+  static constexpr int PF = ((CHI == 128 && sizeof(E) == 2) || (CHI == 128 && sizeof(E) == 1)) ? 4
+                            : (CHI == 256 && sizeof(E) == 1) ? CHAIN_PF_FP8_256 : 2;
 };
 
 // Block of 2 * SW waves for 16 * CG walkers: CG groups of 16 matrix-core
@@ -436,7 +478,7 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
   // sweep 37.4 -> 30.9 ms), 2 elsewhere (deeper rings slowed the bond-64
   // sweep; FP32 at 128 would spill and at 256 the fragments would not fit
   // the register file).
-  constexpr int MT = ChainGeo<CHI>::MT, SW = ChainGeo<CHI>::SW, PF = ChainGeo<CHI>::template PF<E>;
+  constexpr int MT = ChainGeo<CHI, D>::MT, SW = ChainGeo<CHI, D>::SW, PF = ChainGeo<CHI, D>::template PF<E>;
   constexpr int NB = 16 * CG;
   constexpr int BUF = NB * RS;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -963,7 +1005,7 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
 }
 
 template <class D, int CHI, int CG, bool CKP>
-__global__ void __launch_bounds__(ChainGeo<CHI>::NT) chain_kernel(ChainArgs a) {
+__global__ void __launch_bounds__((ChainGeo<CHI, D>::NT)) chain_kernel(ChainArgs a) {
   chain_body<D, CHI, CG, CKP>(a, blockIdx.x, a.sweep0);
 }
 
@@ -1023,6 +1065,40 @@ __global__ void __launch_bounds__(256) reduce_kernel(int n, const double* x, dou
   reduce_body(n, x, out);
 }
 
+// Compensated FP64 sums of products of rows: block (a, b) sums x[a][w] *
+// y[b][w] over w (y = null: x[a][w] alone) and counts the finite terms,
+// out[2 (a B + b)] and out[2 (a B + b) + 1]; non-finite terms are skipped.
+// The partial sums of the 256 threads meet in a fixed tree (deterministic).
+__global__ void __launch_bounds__(256) pair_sums_kernel(int B, int W, const double* x, const double* y,
+                                                        double* out) {
+  __shared__ double sh[3][256];
+  const int a = blockIdx.x / B, b = blockIdx.x % B;
+  const double* xa = x + (size_t)a * W;
+  const double* yb = y ? y + (size_t)b * W : nullptr;
+  double s = 0, c = 0, cnt = 0;
+  for (int i = threadIdx.x; i < W; i += 256) {
+    const double v = yb ? xa[i] * yb[i] : xa[i];
+    if (!isfinite(v)) continue;
+    neumaier_add(s, c, v);
+    cnt += 1.0;
+  }
+  sh[0][threadIdx.x] = s; sh[1][threadIdx.x] = c; sh[2][threadIdx.x] = cnt;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) {
+      double s1 = sh[0][threadIdx.x], c1 = sh[1][threadIdx.x];
+      neumaier_merge(s1, c1, sh[0][threadIdx.x + off], sh[1][threadIdx.x + off]);
+      sh[0][threadIdx.x] = s1; sh[1][threadIdx.x] = c1;
+      sh[2][threadIdx.x] += sh[2][threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[2 * (size_t)blockIdx.x] = sh[0][0] + sh[1][0];
+    out[2 * (size_t)blockIdx.x + 1] = sh[2][0];
+  }
+}
+
 // ============================================================================
 // persistent forms for batches of RTTs
 // ============================================================================
@@ -1052,7 +1128,7 @@ __global__ void __launch_bounds__(256) pass_persistent(const PassArgs* descs, co
 }
 
 template <class D, int CHI>
-__global__ void __launch_bounds__(ChainGeo<CHI>::NT) chain_persistent(const ChainArgs* descs,
+__global__ void __launch_bounds__((ChainGeo<CHI, D>::NT)) chain_persistent(const ChainArgs* descs,
                                                                         const int4* items, int n_items,
                                                                         int* counter,
                                                                         const uint64_t* sweep0) {

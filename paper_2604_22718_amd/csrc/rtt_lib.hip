@@ -555,7 +555,7 @@ rtt_status launch_chain_cg(const rttk::ChainArgs& a0, hipStream_t s) {
   if constexpr (CHI <= 64)
     if (a.n_ck > 0) kfn = rttk::chain_kernel<D, CHI, CG, true>;
   HIPX(hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL(kfn, grid, dim3(rttk::ChainGeo<CHI>::NT), lds, s, a);
+  hipLaunchKernelGGL(kfn, grid, dim3(rttk::ChainGeo<CHI, D>::NT), lds, s, a);
   HIPX(hipGetLastError());
   return RTT_OK;
 }
@@ -1328,6 +1328,17 @@ rtt_status rtt_net_create(int32_t Lx, int32_t Ly, const double* params, rtt_net_
   return host_guard("rtt_net_create", [&] { return rtt_net_create_impl(Lx, Ly, params, out); });
 }
 
+rtt_status rtt_pair_sums(int32_t A, int32_t B, int32_t W, const double* x, const double* y, double* out,
+                         void* stream) {
+  g_err.clear();
+  if (A < 1 || B < 1 || W < 1 || !x || !out) return fail(RTT_E_ARG, "rtt_pair_sums: bad argument");
+  if (!y && B != 1) return fail(RTT_E_ARG, "rtt_pair_sums: row sums (y null) take B = 1");
+  if ((int64_t)A * B > INT_MAX) return fail(RTT_E_ARG, "rtt_pair_sums: A * B too large");
+  hipLaunchKernelGGL(rttk::pair_sums_kernel, dim3(A * B), dim3(256), 0, (hipStream_t)stream, B, W, x, y, out);
+  HIPX(hipGetLastError());
+  return RTT_OK;
+}
+
 rtt_status rtt_energy_reduce(int32_t n, const double* x, double* out, void* stream) {
   g_err.clear();
   if (n < 0 || (n > 0 && !x) || !out) return fail(RTT_E_ARG, "rtt_energy_reduce: bad argument");
@@ -1407,7 +1418,7 @@ struct BatchL {
     if (phase == 0) {
       if (c.chain_items.empty()) return RTT_OK;
       auto kfn = rttk::chain_persistent<D, CHI>;
-      hipLaunchKernelGGL(kfn, dim3(c.grid_chain), dim3(rttk::ChainGeo<CHI>::NT), c.chain_lds, s, c.d_chain,
+      hipLaunchKernelGGL(kfn, dim3(c.grid_chain), dim3(rttk::ChainGeo<CHI, D>::NT), c.chain_lds, s, c.d_chain,
                          c.d_chain_items, (int)c.chain_items.size(), counters, sweep0);
     } else {
       if (c.pass_items.empty()) return RTT_OK;

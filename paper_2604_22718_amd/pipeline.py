@@ -69,14 +69,13 @@ def vmc_energy(psi, ham, walkers, burn, sweeps, seed, rng_stream=0):
     N = psi.N
     spins = _walkers(walkers, N, seed)
     psi.sweep(spins, seed=seed, rng_stream=rng_stream, sweep0=0, n_sweeps=burn)
-    means = torch.empty(sweeps, dtype=torch.float64, device=spins.device)
-    squares = torch.empty(sweeps, dtype=torch.float64, device=spins.device)
+    # per sweep the library's compensated sums: sum E_loc, sum E_loc^2, count
+    sums = torch.empty((sweeps, 3), dtype=torch.float64, device=spins.device)
     for t in range(sweeps):
         psi.sweep(spins, seed=seed, rng_stream=rng_stream, sweep0=burn + t, n_sweeps=1)
-        e = psi.local_energy(spins, ham)
-        means[t] = e.mean()
-        squares[t] = (e * e).mean()
-    means, squares = means.cpu().numpy(), squares.cpu().numpy()
+        R.rtt_energy_reduce(psi.local_energy(spins, ham), sums[t])
+    S = sums.cpu().numpy()
+    means, squares = S[:, 0] / S[:, 2], S[:, 1] / S[:, 2]
     mean = float(means.mean())
     var = float(squares.mean() - mean * mean)
     return {"mean": mean, "sigma": _blocked_sigma(means), "var": var, "v_score": N * var / (mean * mean)}
@@ -100,14 +99,16 @@ def dual_matrices(states, ham, walkers, burn, sweeps, seed, blocks=10, rows=None
         la = torch.empty(walkers, dtype=torch.float64, device=spins.device)
         sg = torch.empty(walkers, dtype=torch.int8, device=spins.device)
         states[a].sweep(spins, seed=seed, rng_stream=a, sweep0=0, n_sweeps=burn, logabs=la, sign=sg)
-        o_rows, e_rows = [], []
+        # per sweep the library's compensated row sums of both estimators
+        rows = torch.empty((sweeps, 2, M, 1, 2), dtype=torch.float64, device=spins.device)
         for t in range(sweeps):
             states[a].sweep(spins, seed=seed, rng_stream=a, sweep0=burn + t, n_sweeps=1, logabs=la, sign=sg)
             ratio, mixed, st = R.mixed_estimators(states, ham, spins, la, sg)
-            o_rows.append(ratio.mean(dim=1))
-            e_rows.append(mixed.mean(dim=1))
-        O = torch.stack(o_rows).cpu().numpy()
-        E = torch.stack(e_rows).cpu().numpy()
+            R.rtt_pair_sums(ratio, None, rows[t, 0])
+            R.rtt_pair_sums(mixed, None, rows[t, 1])
+        X = rows.cpu().numpy()
+        O = X[:, 0, :, 0, 0] / X[:, 0, :, 0, 1]
+        E = X[:, 1, :, 0, 0] / X[:, 1, :, 0, 1]
         St[a], Ht[a] = O.mean(axis=0), E.mean(axis=0)
         sS[a] = [_blocked_sigma(O[:, b], blocks) for b in range(M)]
         sH[a] = [_blocked_sigma(E[:, b], blocks) for b in range(M)]
@@ -127,14 +128,16 @@ def single_chain_matrices(states, ham, walkers, burn, sweeps, seed, blocks=10):
     la = torch.empty(walkers, dtype=torch.float64, device=spins.device)
     sg = torch.empty(walkers, dtype=torch.int8, device=spins.device)
     states[0].sweep(spins, seed=seed, rng_stream=0, sweep0=0, n_sweeps=burn, logabs=la, sign=sg)
-    s_rows, h_rows = [], []
+    # per sweep the library's compensated sums of r_a r_b and r_a m_b
+    sums = torch.empty((sweeps, 2, M, M, 2), dtype=torch.float64, device=spins.device)
     for t in range(sweeps):
         states[0].sweep(spins, seed=seed, rng_stream=0, sweep0=burn + t, n_sweeps=1, logabs=la, sign=sg)
         ratio, mixed, st = R.mixed_estimators(states, ham, spins, la, sg)
-        s_rows.append((ratio[:, None, :] * ratio[None, :, :]).mean(dim=2))
-        h_rows.append((ratio[:, None, :] * mixed[None, :, :]).mean(dim=2))
-    Sx = torch.stack(s_rows).cpu().numpy()   # (sweeps, M, M)
-    Hx = torch.stack(h_rows).cpu().numpy()
+        R.rtt_pair_sums(ratio, ratio, sums[t, 0])
+        R.rtt_pair_sums(ratio, mixed, sums[t, 1])
+    X = sums.cpu().numpy()
+    Sx = X[:, 0, :, :, 0] / X[:, 0, :, :, 1]   # (sweeps, M, M)
+    Hx = X[:, 1, :, :, 0] / X[:, 1, :, :, 1]
     S, H = Sx.mean(axis=0), Hx.mean(axis=0)
     sS = np.array([[_blocked_sigma(Sx[:, a, b], blocks) for b in range(M)] for a in range(M)])
     sH = np.array([[_blocked_sigma(Hx[:, a, b], blocks) for b in range(M)] for a in range(M)])

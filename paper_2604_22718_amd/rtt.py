@@ -160,6 +160,17 @@ def rtt_energy_reduce(x, out):
     check(lib().rtt_energy_reduce(x.numel(), _ptr(x, "x", F64), _ptr(out, "out", F64, 3), _stream()))
 
 
+def rtt_pair_sums(x, y, out):
+    """x: float64 [A][W], y: float64 [B][W] or None; out: float64 [A][B][2]
+    (compensated sums of x[a] * y[b], and their finite-term counts)."""
+    if x.dim() != 2 or (y is not None and (y.dim() != 2 or y.shape[1] != x.shape[1])):
+        raise ValueError("rtt_pair_sums: x [A][W] and y [B][W] with the same W")
+    A, W = int(x.shape[0]), int(x.shape[1])
+    B = 1 if y is None else int(y.shape[0])
+    check(lib().rtt_pair_sums(A, B, W, _ptr(x, "x", F64), _ptr(y, "y", F64), _ptr(out, "out", F64, 2 * A * B),
+                              _stream()))
+
+
 def _flat_cores(cores):
     bond = np.asarray([cores[0].shape[1]] + [c.shape[2] for c in cores], dtype=np.int32)
     flat = np.concatenate([np.ascontiguousarray(c, dtype=np.float64).ravel() for c in cores])
@@ -572,6 +583,15 @@ def mixed_estimators(targets, ham, spins, logabs_a, sign_a):
 def energy_reduce(x):
     out = torch.empty(3, dtype=torch.float64, device=x.device)
     rtt_energy_reduce(x, out)
+    return out
+
+
+def pair_sums(x, y=None):
+    """[A][B][2] device tensor: compensated sums of x[a] * y[b] (or of x[a]
+    alone) and the number of finite terms."""
+    A, B = x.shape[0], (1 if y is None else y.shape[0])
+    out = torch.empty((A, B, 2), dtype=torch.float64, device=x.device)
+    rtt_pair_sums(x, y, out)
     return out
 
 

@@ -111,3 +111,14 @@ def test_binding_rejects_wrong_buffers_before_any_launch():
     with pytest.raises(ValueError):
         R._net_sites(C.c_void_p(12345))                                     # unknown network
     assert R._ptr(None) is None
+
+
+def test_pair_sums_argument_errors(lib):
+    """rtt_pair_sums checks its arguments on the host, before any launch."""
+    p = C.c_void_p(16)   # never dereferenced: every call below is refused first
+    assert lib.rtt_pair_sums(0, 1, 5, p, p, p, None) == -1
+    assert lib.rtt_pair_sums(2, 1, 0, p, p, p, None) == -1
+    assert lib.rtt_pair_sums(2, 1, 5, None, p, p, None) == -1
+    assert lib.rtt_pair_sums(2, 1, 5, p, p, None, None) == -1
+    assert lib.rtt_pair_sums(2, 3, 5, p, None, p, None) == -1     # row sums take B = 1
+    assert b"B = 1" in lib.rtt_last_error()

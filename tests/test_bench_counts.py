@@ -40,3 +40,25 @@ def test_eight_by_eight_workload_count():
     w = wl.MEDIUM_8x8
     pi = w.pi()
     assert bench.sweep_rowsteps(pi, w.N, len(pi)) == 4288
+
+
+def test_bench_statistics_on_known_series():
+    """tau_int of an AR(1) series of many walkers against (1 + rho)/(1 - rho),
+    a constant series (tau 1, sigma 0), and the V-score / sigma formulas of
+    energy_stats on a white-noise series."""
+    import math
+    g = np.random.default_rng(3)
+    for rho in (0.0, 0.6):
+        T, W = 400, 512
+        e = g.standard_normal((T, W))
+        y = np.empty_like(e)
+        y[0] = e[0] / math.sqrt(1 - rho * rho)
+        for t in range(1, T):
+            y[t] = rho * y[t - 1] + e[t]
+        assert abs(bench.tau_int(y) - (1 + rho) / (1 - rho)) < 0.1 * (1 + rho) / (1 - rho)
+    assert bench.tau_int(np.full((10, 3), 2.5)) == 1.0
+    x = 5.0 + g.standard_normal((50, 200))
+    st = bench.energy_stats(x, 4)
+    assert abs(st["E_per_site"] * 4 - x.mean()) < 1e-12
+    assert abs(st["v_score"] - 4 * x.var() / x.mean() ** 2) < 1e-12
+    assert abs(st["sigma_per_site"] * 4 - math.sqrt(x.var() * st["tau_int"] / x.size)) < 1e-12

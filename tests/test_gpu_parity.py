@@ -258,6 +258,29 @@ def test_energy_reduce_matches_fsum(R):
     assert abs(out[1] - math.fsum(fin * fin)) <= 1e-13 * math.fsum(fin * fin)
 
 
+def test_pair_sums_match_fsum(R):
+    """rtt_pair_sums: compensated sums of row products (and of rows alone)
+    against math.fsum of the same FP64 products; non-finite terms skipped
+    and not counted."""
+    g = np.random.default_rng(4)
+    A, B, W = 3, 4, 3001
+    x = g.standard_normal((A, W)) * 1e3 + 1e6
+    y = g.standard_normal((B, W))
+    x[1, 17] = np.nan
+    y[2, 5] = np.inf
+    out = R.pair_sums(torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()).cpu().numpy()
+    for a in range(A):
+        for b in range(B):
+            p = x[a] * y[b]
+            fin = p[np.isfinite(p)]
+            assert out[a, b, 1] == len(fin)
+            assert abs(out[a, b, 0] - math.fsum(fin)) <= 4e-16 * math.fsum(np.abs(fin))
+    rows = R.pair_sums(torch.from_numpy(x).cuda()).cpu().numpy()
+    for a in range(A):
+        fin = x[a][np.isfinite(x[a])]
+        assert rows[a, 0, 1] == len(fin) and abs(rows[a, 0, 0] - math.fsum(fin)) <= 4e-16 * math.fsum(np.abs(fin))
+
+
 def test_zero_amplitude_walkers_are_flagged(R):
     N = 8
     pi = wl.path_repeat(N, 2)
