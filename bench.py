@@ -103,7 +103,9 @@ def run_batched(steps, n_rtt=256):
     """256 uneven RTTs (side 4..10, R 2..3, chi 16..128, 256..4096 walkers,
     BF16) stepped together: each step = 1 sweep + local energies of every
     walker of every RTT, one captured graph of persistent kernels whose
-    launch shape the autotuner picks."""
+    launch shape and per-class sampler tiles the autotuner picks."""
+    import tempfile
+
     import torch
 
     from paper_2604_22718_amd import rtt as R
@@ -112,6 +114,7 @@ def run_batched(steps, n_rtt=256):
     ws = wl.batched_workloads(n_rtt)
     rtts, hams, spins = [], [], []
     flops_le = flops_sw = 0.0
+    per_class = {}
     for w in ws:
         pi = w.pi()
         rtts.append(R.RTT.create(w.N, pi, w.cores(), "bf16"))
@@ -119,13 +122,25 @@ def run_batched(steps, n_rtt=256):
         spins.append(R.spins_to_device(wl.pack_spins(w.spins())))
         info = R.rtt_info(rtts[-1].handle)
         f, b = schedule_rowsteps(pi, w.N, w.L, info["cut"])
-        flops_le += w.W * (f + b) * 2.0 * w.chi * w.chi
-        flops_sw += w.W * sweep_rowsteps(pi, w.N, w.L) * 2.0 * w.chi * w.chi
+        le = w.W * (f + b) * 2.0 * info["chi"] ** 2
+        sw = w.W * sweep_rowsteps(pi, w.N, w.L) * 2.0 * info["chi"] ** 2
+        flops_le += le
+        flops_sw += sw
+        c = per_class.setdefault(info["chi"], {"runs": 0, "walkers": 0, "algorithmic_flops": 0.0})
+        c["runs"] += 1
+        c["walkers"] += w.W
+        c["algorithmic_flops"] += le + sw
     batch = R.Batch(rtts, hams, spins, seed=3100)
+    torch.cuda.synchronize()
     setup = time.perf_counter() - t0
     t1 = time.perf_counter()
-    choice = batch.autotune(n_sweeps=1, reps=1, cache_path=os.environ.get("RTT_TUNE_CACHE"))
+    cache = os.path.join(tempfile.mkdtemp(), "tune.jsonl")
+    choice = batch.autotune(n_sweeps=1, reps=1, cache_path=cache)
     tune = time.perf_counter() - t1
+    rec = json.loads(open(cache).read().splitlines()[-1])
+    for c in rec["classes"]:
+        if c["bond"] in per_class:
+            per_class[c["bond"]]["sampler_walkers_per_block"] = c["sampler_walkers_per_block"]
     batch.step(1)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -136,16 +151,19 @@ def run_batched(steps, n_rtt=256):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
     walkers = sum(w.W for w in ws)
+    tot = flops_le + flops_sw
+    for c in per_class.values():
+        c["share_of_work"] = c["algorithmic_flops"] / tot
     res = {"workload": f"{n_rtt} uneven RTTs (side 4-10, R 2-3, chi 16-128, 256-4096 walkers), bf16",
            "walkers": walkers, "steps": steps, "ms_per_step": ms,
            "local_energy_evals_per_s": walkers / (ms * 1e-3),
-           "algorithmic_tflops": (flops_le + flops_sw) / (ms * 1e-3) / 1e12,
-           "frac_of_bf16_peak": (flops_le + flops_sw) / (ms * 1e-3) / PEAK["bf16"],
-           "autotuned_shape": {"concurrent_classes": choice[0], "blocks_per_cu": choice[1]},
+           "algorithmic_tflops": tot / (ms * 1e-3) / 1e12,
+           "frac_of_bf16_peak": tot / (ms * 1e-3) / PEAK["bf16"],
+           "autotuned": {"concurrent_classes": choice[0], "blocks_per_cu": choice[1], "trials": rec["trials"]},
+           "classes_by_bond": {str(k): v for k, v in sorted(per_class.items())},
            "setup_s": setup, "autotune_s": tune}
     batch.close()
     return res
-
 
 
 def run_learned(n_meas=30, train_steps=150, learned_per_sweep=4):
@@ -836,7 +854,7 @@ def main():
     ap.add_argument("--no-8x8", action="store_true", help="skip the 8x8 FP32 / BF16 chain lines")
     ap.add_argument("--no-wide", action="store_true", help="skip the 10x10 chi=128 BF16 wide-bond line")
     ap.add_argument("--only-8x8", action="store_true", help="only the 8x8 lines (no headline)")
-    ap.add_argument("--batched", type=int, default=0, help="also time the 256-RTT batch for this many steps")
+    ap.add_argument("--batched", type=int, default=3, help="time the 256-RTT batch for this many steps (0: skip)")
     ap.add_argument("--learned", action="store_true", help="also compare learned-proposal ESS/s (10x10, chi=128)")
     ap.add_argument("--dual", action="store_true", help="also the dual Monte Carlo line")
     ap.add_argument("--paper-pipeline", type=int, default=0, metavar="STEPS",

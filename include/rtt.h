@@ -355,10 +355,19 @@ rtt_status rtt_pair_sums(int32_t A, int32_t B, int32_t W, const double* x, const
  * rtt_batch_autotune: times every launch shape (bond classes one after the
  *   other on the whole GPU, or concurrently on graph branches with compute
  *   units shared in proportion to their work; 1..4 persistent blocks per
- *   compute unit) with `reps` steps each, keeps the fastest, and records it in
- *   the JSON file cache_path (NULL: no file).  The timed steps advance the
- *   chains.  choice (host int32[2], may be NULL) receives (concurrent, blocks
- *   per compute unit).  Synchronises.
+ *   compute unit) with `reps` steps each and keeps the fastest; then, class
+ *   by class, the sampler's tile: 16 walkers per block, or 32 walkers (two
+ *   matrix-core column groups sharing every core fragment a wave loads)
+ *   where every member's sampling state fits on chip in the same layout
+ *   (padded bonds 32 and 128).  Results do not depend on these choices, bit
+ *   for bit.  The choice is appended as one JSON line to cache_path (NULL:
+ *   no file): batch signature, shape, per-class walkers per block, number
+ *   of trials (each = one capture, one warm-up step and `reps` timed steps),
+ *   time per step.  The timed steps advance the chains.  choice (host
+ *   int32[2], may be NULL) receives (concurrent, blocks per compute unit).
+ *   Synchronises.  The environment variable RTT_BATCH_TILE=32 at
+ *   rtt_batch_create starts the eligible classes at 32 walkers per block
+ *   (16 otherwise), the tile used until an autotune changes it.
  */
 typedef struct rtt_batch_s* rtt_batch_t;
 

@@ -1127,7 +1127,8 @@ __global__ void __launch_bounds__(256) pass_persistent(const PassArgs* descs, co
   }
 }
 
-template <class D, int CHI>
+// CG column groups of 16 walkers per item (the batch autotuner's tile choice)
+template <class D, int CHI, int CG>
 __global__ void __launch_bounds__((ChainGeo<CHI, D>::NT)) chain_persistent(const ChainArgs* descs,
                                                                         const int4* items, int n_items,
                                                                         int* counter,
@@ -1138,7 +1139,7 @@ __global__ void __launch_bounds__((ChainGeo<CHI, D>::NT)) chain_persistent(const
     const int it = __builtin_amdgcn_readfirstlane(next_item(counter, &s_item));
     if (it >= n_items) break;
     const int4 w = items[it];
-    chain_body<D, CHI, 1>(descs[w.x], w.y, *sweep0);
+    chain_body<D, CHI, CG>(descs[w.x], w.y, *sweep0);
     __syncthreads();
   }
 }

@@ -1357,6 +1357,7 @@ namespace {
 // one bond class (dtype, padded bond) of a batch
 struct BatchClass {
   int dtype = 0, chi = 0;
+  int cg = 1, cg_max = 1;              // sampler walkers per block = 16 cg (autotuned)
   std::vector<int> members;
   std::vector<rttk::ChainArgs> chain;  // one descriptor per member
   std::vector<rttk::PassArgs> pass;    // forward and backward per member
@@ -1405,20 +1406,28 @@ struct rtt_batch_s {
 
 namespace {
 
+// Sampler tile of a class: 16 walkers per block, or 32 (two column groups
+// sharing every core fragment) at the bonds where that kernel fits in
+// registers (at 64 and 256 the second group's operands spill).
+constexpr bool batch_cg2(int chi) { return chi == 32 || chi == 128; }
+template <class D, int CHI>
+constexpr bool kBatchCG2 = batch_cg2(CHI);
+
 template <class D, int CHI>
 struct BatchL {
   static rtt_status run(BatchClass& c, int* counters, const uint64_t* sweep0, int phase, hipStream_t s) {
+    auto kchain = rttk::chain_persistent<D, CHI, 1>;
+    if constexpr (kBatchCG2<D, CHI>)
+      if (c.cg == 2) kchain = rttk::chain_persistent<D, CHI, 2>;
     if (phase == 2) {  // before capture: allow the dynamic LDS sizes
-      HIPX(hipFuncSetAttribute((const void*)rttk::chain_persistent<D, CHI>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)c.chain_lds));
+      HIPX(hipFuncSetAttribute((const void*)kchain, hipFuncAttributeMaxDynamicSharedMemorySize, (int)c.chain_lds));
       HIPX(hipFuncSetAttribute((const void*)rttk::pass_persistent<D, CHI>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)c.pass_lds));
       return RTT_OK;
     }
     if (phase == 0) {
       if (c.chain_items.empty()) return RTT_OK;
-      auto kfn = rttk::chain_persistent<D, CHI>;
-      hipLaunchKernelGGL(kfn, dim3(c.grid_chain), dim3(rttk::ChainGeo<CHI, D>::NT), c.chain_lds, s, c.d_chain,
+      hipLaunchKernelGGL(kchain, dim3(c.grid_chain), dim3(rttk::ChainGeo<CHI, D>::NT), c.chain_lds, s, c.d_chain,
                          c.d_chain_items, (int)c.chain_items.size(), counters, sweep0);
     } else {
       if (c.pass_items.empty()) return RTT_OK;
@@ -1433,6 +1442,28 @@ struct BatchL {
 
 // persistent blocks per compute unit that the class's LDS allows
 int lds_occupancy(size_t lds) { return std::max(1, std::min(4, (int)(kLdsLimit / std::max<size_t>(lds, 1)))); }
+
+// Sampler work items of a class for cg column groups of 16 walkers per
+// block: (member, block) pairs, members largest first; and the LDS the
+// widest member needs.
+void build_chain_items(const rtt_batch_s* b, BatchClass& c, int cg) {
+  c.cg = cg;
+  c.chain_items.clear();
+  c.chain_lds = 0;
+  for (int mi = 0; mi < (int)c.members.size(); ++mi) {
+    const rtt_s* h = b->rtts[c.members[mi]];
+    const int W = b->W[c.members[mi]];
+    c.chain_lds = std::max(c.chain_lds, chain_lds_bytes(c.chi, h->T, h->L, h->nw, h->N, cg));
+    for (int t = 0; t < (W + 16 * cg - 1) / (16 * cg); ++t) c.chain_items.push_back(make_int4(mi, t, 0, 0));
+  }
+}
+
+rtt_status set_class_cg(rtt_batch_s* b, BatchClass& c, int cg) {
+  build_chain_items(b, c, cg);
+  if (c.d_chain_items) HIPX(hipFree(c.d_chain_items));
+  c.d_chain_items = nullptr;
+  return upload((void**)&c.d_chain_items, c.chain_items.data(), c.chain_items.size() * sizeof(int4));
+}
 
 void size_grids(rtt_batch_s* b) {
   double tot_c = 0, tot_p = 0;
@@ -1643,7 +1674,7 @@ static rtt_status rtt_batch_create_impl(int32_t n, const rtt_t* rtts, const rtt_
       ca.T = h->T; ca.L = h->L; ca.N = h->N; ca.nw = h->nw; ca.LW = (h->L + 63) / 64; ca.W = W;
       ca.spins = b->spins[i]; ca.seed = seed; ca.rstream = (uint64_t)i; ca.mode = 1;
       c.chain.push_back(ca);
-      c.chain_lds = std::max(c.chain_lds, chain_lds_bytes(c.chi, h->T, h->L, h->nw, h->N));
+
       rttk::PassArgs pa{};
       pa.core_exp = h->d_cexp; pa.nslot = h->sched.nslot; pa.L = h->L; pa.nw = h->nw; pa.W = W;
       pa.spins = b->spins[i];
@@ -1661,11 +1692,22 @@ static rtt_status rtt_batch_create_impl(int32_t n, const rtt_t* rtts, const rtt_
       c.chain_cost += sweep_rows * h->T * ((W + 15) / 16) * 16 * (double)c.chi * c.chi;
       const int wpb = 4 / rttk_wpw(c.chi);
       c.pass_cost += (double)h->sched.cost * 16 * h->T * W * (double)c.chi * c.chi;
-      for (int t = 0; t < (W + 15) / 16; ++t) c.chain_items.push_back(make_int4(mi, t, 0, 0));
+
       for (int dir = 0; dir < 2; ++dir)
         for (int ty = 0; ty < h->T * h->sched.ng; ++ty)
           for (int bx = 0; bx < (W + wpb - 1) / wpb; ++bx) c.pass_items.push_back(make_int4(2 * mi + dir, bx, ty, 0));
     }
+    // sampler tiles: 16 walkers per block; 32 allowed where every member's
+    // state fits on chip in the same layout (same results, bit for bit)
+    c.cg_max = batch_cg2(c.chi) ? 2 : 1;
+    for (int i : c.members) {
+      const rtt_s* h = b->rtts[i];
+      const int LW = (h->L + 63) / 64;
+      const rttk::ChainLayout l1(c.chi, h->T, LW, h->nw, 1, 0, h->N), l2(c.chi, h->T, LW, h->nw, 2, 0, h->N);
+      if (l2.seq != l1.seq || (size_t)l2.total > kLdsLimit) c.cg_max = 1;
+    }
+    const char* tile = getenv("RTT_BATCH_TILE");
+    build_chain_items(b, c, (tile && atoi(tile) == 32 && c.cg_max == 2) ? 2 : 1);
     rtt_status st;
     if ((st = upload((void**)&c.d_chain, c.chain.data(), c.chain.size() * sizeof(rttk::ChainArgs))) != RTT_OK) return cleanup(st);
     if ((st = upload((void**)&c.d_pass, c.pass.data(), c.pass.size() * sizeof(rttk::PassArgs))) != RTT_OK) return cleanup(st);
@@ -1731,37 +1773,68 @@ static rtt_status rtt_batch_autotune_impl(rtt_batch_t b, int32_t n_sweeps, int32
   hipEvent_t e0, e1;
   HIPX(hipEventCreate(&e0));
   HIPX(hipEventCreate(&e1));
+  // one timed trial of the current shape and tiles: a capture, one warm-up
+  // step, reps timed steps
+  auto trial = [&](float& ms) -> rtt_status {
+    HIPX(hipDeviceSynchronize());
+    rtt_status st = capture(b, n_sweeps, nullptr);
+    if (st != RTT_OK) return st;
+    HIPX(hipGraphLaunch(b->exec, s));
+    HIPX(hipEventRecord(e0, s));
+    for (int r = 0; r < reps; ++r) HIPX(hipGraphLaunch(b->exec, s));
+    HIPX(hipEventRecord(e1, s));
+    HIPX(hipEventSynchronize(e1));
+    HIPX(hipEventElapsedTime(&ms, e0, e1));
+    return RTT_OK;
+  };
+  // launch shape: concurrency of the classes and persistent blocks per CU
   float best = 1e30f;
   int best_conc = 0, best_occ = 1;
   for (int conc = 0; conc < 2; ++conc)
     for (int occ = 1; occ <= 4; ++occ) {
       b->concurrent = conc;
       b->occ = occ;
-      HIPX(hipDeviceSynchronize());
-      rtt_status st = capture(b, n_sweeps, nullptr);
-      if (st != RTT_OK) return st;
-      HIPX(hipGraphLaunch(b->exec, s));  // warm-up
-      HIPX(hipEventRecord(e0, s));
-      for (int r = 0; r < reps; ++r) HIPX(hipGraphLaunch(b->exec, s));
-      HIPX(hipEventRecord(e1, s));
-      HIPX(hipEventSynchronize(e1));
       float ms = 0.f;
-      HIPX(hipEventElapsedTime(&ms, e0, e1));
+      rtt_status st = trial(ms);
+      if (st != RTT_OK) return st;
       if (ms < best) { best = ms; best_conc = conc; best_occ = occ; }
     }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   b->concurrent = best_conc;
   b->occ = best_occ;
+  // tiles: per class, the sampler's walkers per block (16, or 32 sharing
+  // every core fragment), one class at a time with the others as chosen
+  int trials = 8;
+  for (auto& c : b->classes) {
+    if (c.cg_max < 2) continue;
+    const int other = c.cg == 2 ? 1 : 2;
+    const int keep = c.cg;
+    rtt_status st = set_class_cg(b, c, other);
+    if (st != RTT_OK) return st;
+    float ms = 0.f;
+    if ((st = trial(ms)) != RTT_OK) return st;
+    ++trials;
+    if (ms < best) best = ms;
+    else if ((st = set_class_cg(b, c, keep)) != RTT_OK) return st;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
   if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
   if (choice) { choice[0] = best_conc; choice[1] = best_occ; }
   if (cache_path) {
     // append one JSON object per line: signature, choice, time per step
+    std::string tiles;
+    char buf[96];
+    for (size_t ci = 0; ci < b->classes.size(); ++ci) {
+      snprintf(buf, sizeof buf, "%s{\"dtype\": %d, \"bond\": %d, \"sampler_walkers_per_block\": %d}", ci ? ", " : "",
+               b->classes[ci].dtype, b->classes[ci].chi, 16 * b->classes[ci].cg);
+      tiles += buf;
+    }
     FILE* f = fopen(cache_path, "a");
     if (f) {
-      fprintf(f, "{\"batch\": \"%s\", \"runs\": %d, \"sweeps\": %d, \"concurrent\": %d, \"blocks_per_cu\": %d, \"ms_per_step\": %.4f}\n",
-              batch_signature(b).c_str(), b->n, n_sweeps, best_conc, best_occ, best / reps);
+      fprintf(f, "{\"batch\": \"%s\", \"runs\": %d, \"sweeps\": %d, \"concurrent\": %d, \"blocks_per_cu\": %d, "
+              "\"classes\": [%s], \"trials\": %d, \"ms_per_step\": %.4f}\n",
+              batch_signature(b).c_str(), b->n, n_sweeps, best_conc, best_occ, tiles.c_str(), trials, best / reps);
       fclose(f);
     }
   }

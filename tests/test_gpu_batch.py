@@ -1,6 +1,7 @@
 """Batched persistent launch: many uneven RTT chains in one captured graph give
 bit-identical results to stepping each RTT on its own through the C ABI
 (which is itself parity-tested against the oracle), on every graph replay."""
+import json
 import math
 import os
 
@@ -38,7 +39,9 @@ def R():
 def build(R):
     """The runs, created without column checkpoints: the persistent batch
     kernels contract every proposal's columns from the right boundary, and
-    the eager reference must do the same to agree bit for bit."""
+    the eager reference must do the same to agree bit for bit (the eager
+    sampler runs 16 walkers per block at these sizes, whatever tile the
+    batch uses)."""
     rtts, hams, spins, meta = [], [], [], []
     for i, (Lx, Ly, Rr, chi, dtype, W) in enumerate(RUNS):
         N = Lx * Ly
@@ -54,10 +57,15 @@ def build(R):
     return rtts, hams, spins, meta
 
 
-def test_batch_equals_individual_runs(R):
+@pytest.mark.parametrize("tile", ["16", "32"])
+def test_batch_equals_individual_runs(R, tile):
     rtts, hams, spins, meta = build(R)
     ref_spins = [s.clone() for s in spins]
-    batch = R.Batch(rtts, hams, spins, seed=777)
+    os.environ["RTT_BATCH_TILE"] = tile      # sampler walkers per block (bonds 32, 128)
+    try:
+        batch = R.Batch(rtts, hams, spins, seed=777)
+    finally:
+        del os.environ["RTT_BATCH_TILE"]
     for rep in range(3):
         batch.step(n_sweeps=2)
         torch.cuda.synchronize()
@@ -98,9 +106,16 @@ def test_autotune_picks_a_shape_and_keeps_results_exact(R, tmp_path):
     batch = R.Batch(rtts, hams, spins, seed=11)
     conc, occ = batch.autotune(n_sweeps=1, reps=1, cache_path=str(tmp_path / "tune.jsonl"))
     assert conc in (0, 1) and 1 <= occ <= 4
-    assert (tmp_path / "tune.jsonl").read_text().count("blocks_per_cu") == 1
-    # autotuning ran 8 shapes x (1 warm-up + 1 timed) steps of 1 sweep
-    n_done = 16
+    lines = (tmp_path / "tune.jsonl").read_text().splitlines()
+    assert len(lines) == 1
+    rec = json.loads(lines[0])
+    tiles = {(c["dtype"], c["bond"]): c["sampler_walkers_per_block"] for c in rec["classes"]}
+    print(f"  autotuned: {rec}", flush=True)
+    assert set(tiles.values()) <= {16, 32} and tiles[(2, 64)] == 16
+    # 8 launch shapes, then one trial per class with a second tile (BF16 and
+    # FP8 at bonds 32 and 128), each 1 warm-up + 1 timed step of 1 sweep
+    assert rec["trials"] == 8 + 4
+    n_done = 2 * rec["trials"]
     batch.step(n_sweeps=1)
     torch.cuda.synchronize()
     for i, r in enumerate(rtts):
