@@ -403,10 +403,16 @@ struct ChainArgs {
   uint64_t seed, rstream, sweep0;
   int n_sweeps;
   int mode;                  // 0: amplitudes only, 1: sweeps
-  // Column checkpoints (sweeps, all terms together): the right environments
-  // of bonds ck_first + i * ck_step, i < n_ck, for the current configuration,
-  // kept in LDS with a per-walker validity mask (0: none).
+  // Column checkpoints (sweeps): the right environments of bonds
+  // ck_first + i * ck_step, i < n_ck, for the current configuration, with a
+  // per-walker validity mask (0: none); kept in LDS, or in global memory
+  // (ckg) with the sequential layout.
   int n_ck, ck_first, ck_step;
+  // With the term-by-term ("sequential") layout the checkpoint vectors live
+  // in global memory: [block][saved, candidate][n_ck][T][16 cg walkers][bond + 4],
+  // room for ck_cap checkpoints
+  float* ckg;
+  int ck_cap;
 };
 
 // Layout of one block's walkers' state in LDS (offsets in bytes), for
@@ -417,8 +423,9 @@ struct ChainArgs {
 // at a time, the prefix being advanced after the decision.  Vectors are
 // stored buffer-major ([buffer][term]); with all terms together nck column
 // checkpoints per term and as many candidates follow as buffers 7 ...
-// 6 + 2 nck, their exponents after the spins, and last the replica bitmasks
-// of the n_spins spins when they fit (else they are read from global memory).
+// 6 + 2 nck (with the sequential layout those vectors are in global memory),
+// their exponents after the spins, and last the replica bitmasks of the
+// n_spins spins when they fit (else they are read from global memory).
 struct ChainLayout {
   int nb, rows, exps, vals, pm, sp, ckexp, rm, total;
   bool seq, rml;
@@ -426,8 +433,7 @@ struct ChainLayout {
     nb = 16 * cg;
     const int bufb = nb * (chi + 4) * 4;
     const int tail = 4 * T * nb * 4 + T * nb * 12 + 8 + nb * LW * 8 + nb * nw * 8;
-    seq = (T * 7 * bufb + tail) > 160 * 1024;
-    if (seq) nck = 0;
+    seq = (T * 7 * bufb + tail) > 160 * 1024;   // (seq: checkpoint vectors in global memory)
     rows = 0;                                                 // float vectors
     exps = rows + (seq ? T + 5 : (7 + 2 * nck) * T) * bufb;  // int [4][T][nb]: prefix, first step, row, column
     vals = exps + 4 * T * nb * 4;                  // double [T][nb] end values, int [T][nb] exponents
@@ -469,7 +475,7 @@ struct ChainGeo {
 // amplitude is halved and each SIMD runs two independent chains.  CKP
 // compiles the column checkpoints in (bonds up to 64: wider bonds leave LDS
 // for too few of them, and their register-bound kernels stay as they are).
-template <class D, int CHI, int CG, bool CKP = false>
+template <class D, int CHI, int CG, bool CKP = false, bool CKG = false>
 __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t sweep0) {
   using E = typename D::elem;
   using G = Geo<CHI>;
@@ -500,7 +506,7 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
   uint64_t* sp = reinterpret_cast<uint64_t*>(lds_raw + lay.sp);
   const bool seq = lay.seq;
   const int nbuf = seq ? T + 5 : 7 * T;
-  const int NCK = (CKP && !seq) ? a.n_ck : 0;
+  const int NCK = CKP ? a.n_ck : 0;
   int* cke = reinterpret_cast<int*>(lds_raw + lay.ckexp);
 
   // Buffer ids: the seven vectors of a term, then CK + i for the saved
@@ -511,6 +517,12 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
     if (!seq) return rows + (b * T + t) * BUF;
     return b == P ? rows + t * BUF : rows + (T + b - F) * BUF;  // U is not used then
   };
+  // CKG (sequential layout only): the checkpoint vectors are in global
+  // memory, addressed by gbuf; a segment starting from one first copies it
+  // into the spare column buffer, so that every vector access of the steps
+  // stays an LDS access.
+  float* ckg = (CKG && NCK > 0) ? a.ckg + (size_t)bx * 2 * NCK * T * BUF : nullptr;
+  auto gbuf = [&](int t, int b) { return ckg + ((size_t)(b - CK) * T + t) * BUF; };
   auto ckexp = [&](int b, int t, int wn) -> int& { return cke[((b - CK) * T + t) * NB + wn]; };
   // index of the first checkpoint whose bond is >= b (NCK if none)
   auto ck_ceil = [&](int b) {
@@ -583,10 +595,23 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
   auto segment = [&](int k0, int k1, int kc, int ks, int lj, int jflip, bool split, int t0, int tn) {
     const int nr = k1 > k0 ? k1 - k0 : 0, nc = ks - kc;
     const int cks = (CKP && ks < L) ? CK + (ks - a.ck_first) / a.ck_step : -1;
+    // the buffer the columns start from: the checkpoint itself, or with
+    // CKG its copy in the spare column buffer CY (the steps write CX first)
+    int ck_src = cks;
+    if constexpr (CKG) {
+      if (cks >= 0) {
+        for (int i = threadIdx.x; i < tn * (BUF / 4); i += nthr) {
+          const int t = t0 + i / (BUF / 4), r = i % (BUF / 4);
+          reinterpret_cast<float4*>(buf(t, CY))[r] = reinterpret_cast<const float4*>(gbuf(t, cks))[r];
+        }
+        lds_barrier();
+        ck_src = CY;
+      }
+    }
     if (nr == 0) rb = P;
     else if (split) rb = nr == 1 ? F : (((nr - 1) & 1) ? X : Y);
     else rb = (nr & 1) ? X : Y;
-    cb = nc == 0 ? cks : ((nc & 1) ? CX : CY);
+    cb = nc == 0 ? ck_src : ((nc & 1) ? CX : CY);
     const int S = nr > nc ? nr : nc;
     const int n = side == 0 ? nr : nc;
     if (CKP && side == 1 && n == 0 && cks >= 0 && wv == 0 && g == 0)
@@ -595,7 +620,7 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
         for (int cg = 0; cg < CG; ++cg) Ec[t * NB + 16 * cg + m] = ckexp(cks, t, 16 * cg + m);
     if (n > 0) {
 
-      int cur = side == 0 ? P : cks;
+      int cur = side == 0 ? P : ck_src;
       int out = side == 0 ? (split ? F : X) : CX;
       const int tend = t0 + tn;
       int i = 0, t = t0, mt = 0;
@@ -654,7 +679,7 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
                 }
                 if (wv == 0 && g == 0) {
                   if (side == 1) {
-                    Ec[t * NB + wn] = ((CKP && i == 0) ? ckexp(cur, t, wn) : Ec[t * NB + wn]) + e;
+                    Ec[t * NB + wn] = ((CKP && i == 0) ? ckexp(cks, t, wn) : Ec[t * NB + wn]) + e;
                   } else if (split && i == 0) {
                     const int ne = Ep[t * NB + wn] + e;
                     Ef[t * NB + wn] = ne;
@@ -696,7 +721,8 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
           for (int cg = 0; cg < CG; ++cg) {
             const int wn = 16 * cg + m;
             const f4 sel = bit[cg] ? c1[cg] : c0[cg];
-            A::store4(buf(t, slot) + wn * RS, 16 * tt + 4 * g, sel);
+            if constexpr (CKG) A::store4(gbuf(t, slot) + wn * RS, 16 * tt + 4 * g, sel);
+            else A::store4(buf(t, slot) + wn * RS, 16 * tt + 4 * g, sel);
             if (wv == 0 && g == 0 && mt == 0) ckexp(slot, t, wn) = Ec[t * NB + wn];
           }
         }
@@ -904,7 +930,7 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
           record(0, T);
         } else {
           for (int t = 0; t < T; ++t) {
-            segment(f, c, c, L, lj, j, false, t, 1);
+            segment(f, c, c, ks, lj, j, false, t, 1);
             record(t, 1);
           }
         }
@@ -958,9 +984,14 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
               const int wn = 16 * cg + m;
               for (int i = ic0; i < icand; ++i)
                 for (int t = 0; t < T; ++t) {
-                  for (int q = r; q < CHI / 4; q += 4 * nwave)
-                    reinterpret_cast<float4*>(buf(t, CK + i) + wn * RS)[q] =
-                        reinterpret_cast<const float4*>(buf(t, CD + i) + wn * RS)[q];
+                  for (int q = r; q < CHI / 4; q += 4 * nwave) {
+                    if constexpr (CKG)
+                      reinterpret_cast<float4*>(gbuf(t, CK + i) + wn * RS)[q] =
+                          reinterpret_cast<const float4*>(gbuf(t, CD + i) + wn * RS)[q];
+                    else
+                      reinterpret_cast<float4*>(buf(t, CK + i) + wn * RS)[q] =
+                          reinterpret_cast<const float4*>(buf(t, CD + i) + wn * RS)[q];
+                  }
                   if (r == 0) ckexp(CK + i, t, wn) = ckexp(CD + i, t, wn);
                 }
             }
@@ -1004,9 +1035,9 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
   }
 }
 
-template <class D, int CHI, int CG, bool CKP>
+template <class D, int CHI, int CG, bool CKP, bool CKG = false>
 __global__ void __launch_bounds__((ChainGeo<CHI, D>::NT)) chain_kernel(ChainArgs a) {
-  chain_body<D, CHI, CG, CKP>(a, blockIdx.x, a.sweep0);
+  chain_body<D, CHI, CG, CKP, CKG>(a, blockIdx.x, a.sweep0);
 }
 
 // ============================================================================

@@ -12,6 +12,7 @@
 #include <mutex>
 #include <stdexcept>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/rtt.h"
@@ -229,6 +230,8 @@ struct rtt_s {
   float* d_v = nullptr;
   int* d_ue = nullptr;
   int* d_ve = nullptr;
+  float* d_ck = nullptr;      // global column checkpoints of the sequential sampler layout
+  size_t ck_bytes = 0;
   // this state's amplitudes and local energies as a dual Monte Carlo target
   size_t mix_W = 0;
   double* d_mla = nullptr;
@@ -311,7 +314,7 @@ void free_dev(rtt_s* h) {
                   h->d_pi, h->d_order, h->d_first, h->d_coeffs, h->d_ncores};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
-  void* ws[] = {h->d_u, h->d_v, h->d_ue, h->d_ve, h->d_mla, h->d_msg, h->d_mel, h->d_mst};
+  void* ws[] = {h->d_u, h->d_v, h->d_ue, h->d_ve, h->d_mla, h->d_msg, h->d_mel, h->d_mst, h->d_ck};
   bool any = false;
   for (void* p : ws)
     if (p) { (void)hipFreeAsync(p, nullptr); any = true; }
@@ -524,19 +527,27 @@ int device_cus() {
 void chain_checkpoints(rttk::ChainArgs& a, int chi, int cg, int blocks) {
   const int lo = a.ck_first, LW = (a.L + 63) / 64;
   a.n_ck = 0; a.ck_first = 0; a.ck_step = 1;
-  if (a.mode != 1 || lo >= a.L || lo < 1 || chi > 64) return;
+  if (a.mode != 1 || lo >= a.L || lo < 1) return;
   const rttk::ChainLayout l0(chi, a.T, LW, a.nw, cg, 0, a.N);
-  if (l0.seq) return;
-  const size_t budget = kLdsLimit / (blocks > device_cus() ? 2 : 1);
-  // the largest count whose layout fits, preferring counts that keep the
-  // replica bitmasks in LDS as they are without checkpoints (each layout is
-  // sized in full: the masks may stop fitting as checkpoints are added)
   int nmax = 0;
-  for (int pass = 0; pass < 2 && nmax == 0; ++pass)
-    for (int n = 16; n >= 1; --n) {
-      const rttk::ChainLayout ln(chi, a.T, LW, a.nw, cg, n, a.N);
-      if ((size_t)ln.total <= budget && (pass == 1 || ln.rml == l0.rml)) { nmax = n; break; }
-    }
+  if (l0.seq) {
+    // sequential layout (bond 256, one block per CU): the vectors go to the
+    // global buffer, only their exponents take LDS
+    if (chi != 256 || cg != 1 || !a.ckg) return;
+    for (int n = std::min(16, a.ck_cap); n >= 1 && nmax == 0; --n)
+      if ((size_t)rttk::ChainLayout(chi, a.T, LW, a.nw, cg, n, a.N).total <= kLdsLimit) nmax = n;
+  } else {
+    if (chi > 64) return;
+    const size_t budget = kLdsLimit / (blocks > device_cus() ? 2 : 1);
+    // the largest count whose layout fits, preferring counts that keep the
+    // replica bitmasks in LDS as they are without checkpoints (each layout is
+    // sized in full: the masks may stop fitting as checkpoints are added)
+    for (int pass = 0; pass < 2 && nmax == 0; ++pass)
+      for (int n = 16; n >= 1; --n) {
+        const rttk::ChainLayout ln(chi, a.T, LW, a.nw, cg, n, a.N);
+        if ((size_t)ln.total <= budget && (pass == 1 || ln.rml == l0.rml)) { nmax = n; break; }
+      }
+  }
   if (nmax < 1) return;
   const int span = a.L - lo;
   const int step = (span + nmax - 1) / nmax;
@@ -552,8 +563,12 @@ rtt_status launch_chain_cg(const rttk::ChainArgs& a0, hipStream_t s) {
   chain_checkpoints(a, CHI, CG, (int)grid.x);
   const size_t lds = (size_t)rttk::ChainLayout(CHI, a.T, (a.L + 63) / 64, a.nw, CG, a.n_ck, a.N).total;
   auto kfn = rttk::chain_kernel<D, CHI, CG, false>;
+  // (at bond 256 only the FP8 kernel fits the checkpoint code in registers;
+  // the BF16 one would spill)
   if constexpr (CHI <= 64)
     if (a.n_ck > 0) kfn = rttk::chain_kernel<D, CHI, CG, true>;
+  if constexpr (CHI == 256 && CG == 1 && std::is_same<D, rttk::DFP8>::value)
+    if (a.n_ck > 0) kfn = rttk::chain_kernel<D, CHI, CG, true, true>;   // sequential layout: vectors in global memory
   HIPX(hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   hipLaunchKernelGGL(kfn, grid, dim3(rttk::ChainGeo<CHI, D>::NT), lds, s, a);
   HIPX(hipGetLastError());
@@ -1116,6 +1131,27 @@ static rtt_status chain_common(rtt_t h, int32_t W, uint64_t* spins, double* loga
   ca.T = h->T; ca.L = h->L; ca.N = h->N; ca.nw = h->nw; ca.LW = (h->L + 63) / 64; ca.W = W;
   ca.spins = spins; ca.logabs = logabs; ca.sign = sign; ca.accepts = accepts; ca.status = status;
   ca.seed = seed; ca.rstream = rstream; ca.sweep0 = sweep0; ca.n_sweeps = n_sweeps; ca.mode = mode;
+  // Sequential sampler layout at bond 256 with FP8 cores (the terms of a
+  // combination take turns): room for 8 column checkpoints per block in
+  // global memory, grown
+  // in stream order (8 checkpoints keep 0.72 of the dependent steps of
+  // contracting every proposal's columns from the right boundary on the
+  // 16x16 two-replica path; 16 would keep 0.70 at twice the memory)
+  ca.ckg = nullptr;
+  ca.ck_cap = 0;
+  if (mode == 1 && h->chain_ck && h->chi == 256 && h->dtype == RTT_FP8_E4M3 &&
+      rttk::ChainLayout(h->chi, h->T, (h->L + 63) / 64, h->nw, 1, 0, h->N).seq) {
+    const int cap = 8;
+    const size_t need = (size_t)((W + 15) / 16) * 2 * cap * h->T * 16 * (h->chi + 4) * 4;
+    if (need > h->ck_bytes) {
+      h->ck_bytes = 0;
+      rtt_status st = grow_async((void**)&h->d_ck, need, (hipStream_t)stream);
+      if (st != RTT_OK) return st;
+      h->ck_bytes = need;
+    }
+    ca.ckg = h->d_ck;
+    ca.ck_cap = cap;
+  }
   // the lowest bond a proposal's columns can start from: one past the
   // smallest last position over the spins
   {

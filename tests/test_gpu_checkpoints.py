@@ -143,3 +143,35 @@ def test_full_size_8x8_sweeps_sampled(R, dtype, margin, sweeps):
     err = run_and_compare(R, psi, amp, pi, bits, seed=w.chain_seed, stream=7, n_sweeps=sweeps, margin=margin,
                           walker_ids=ids, min_clean=0.5)
     assert err < (1e-4 if dtype == "f32" else 2e-2)
+
+
+@pytest.mark.parametrize("checkpoints", ["1", "0"])
+def test_sequential_fp8_bond256_checkpoints(R, checkpoints):
+    """A four-term FP8 combination at bond 256 samples with the terms taking
+    turns (their rows do not fit on chip together); its column checkpoints
+    then live in global memory.  Three sweeps in one call and in three calls
+    (checkpoints carried across sweeps, then rebuilt) make the oracle's
+    decisions on the summed amplitudes away from near-ties, with and
+    without checkpoints (RTT_CHAIN_CHECKPOINTS=0)."""
+    N, Rr, chi, T, W = 16, 2, 256, 4, 48
+    pi = wl.path_site_plus_perms(N, Rr, 81)
+    bond = wl.open_bonds(N * Rr, chi)
+    terms = [wl.gaussian_cores(bond, 82 + t) for t in range(T)]
+    c = np.array([0.9, -1.2, 0.5, 0.7])
+    os.environ["RTT_CHAIN_CHECKPOINTS"] = checkpoints
+    try:
+        hs = [R.RTT.create(N, pi, t, "fp8") for t in terms]
+        comb = R.RTT.lincomb(hs, c)
+    finally:
+        del os.environ["RTT_CHAIN_CHECKPOINTS"]
+    for h in hs:
+        h.close()
+    qts = device_cores(comb, bond, n_terms=T)
+    amp = lambda S: orc.lincomb_amplitudes(qts, c, pi, S)
+    bits = wl.random_spins(W, N, 83)
+    for calls in (1, 3):
+        print(f"[case] checkpoints={checkpoints} calls={calls}", flush=True)
+        err = run_and_compare(R, comb, amp, pi, bits, seed=84, stream=1, n_sweeps=3, margin=1e-3,
+                              calls=calls, min_clean=0.5)
+        assert err < 2e-2
+    comb.close()
