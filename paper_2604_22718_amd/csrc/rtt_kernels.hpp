@@ -136,17 +136,24 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int bx, int ty) {
     const int s = item / NIS, ig = item % NIS;
     const int4 st = sched[s];
     const int k = st.x, nact = st.z, odd = st.w;
-    ER Fm[MTI][KPL];
+    // the other slice only serves the odd row, which most steps of a row
+    // group do not have: its codes are decoded only when it does
+    const int oin = odd >= 0 ? (odd & 0xffff) : -1, oout = odd >> 16;
+    ER Fm[MTI][KPL], Fo[MTI][KPL];
     if constexpr (kDec) {
 #pragma unroll
       for (int q = 0; q < MTI; ++q) D::template decode<KPL>(F.m[q], Fm[q]);
+      if (oin >= 0) {
+#pragma unroll
+        for (int q = 0; q < MTI; ++q) D::template decode<KPL>(F.o[q], Fo[q]);
+      }
     }
     auto fm = [&](int q) -> const ER(&)[KPL] {
       if constexpr (kDec) return Fm[q];
       else return F.m[q];
     };
-    auto fo = [&](int q, ER (&tmp)[KPL]) -> const ER(&)[KPL] {
-      if constexpr (kDec) { D::template decode<KPL>(F.o[q], tmp); return tmp; }
+    auto fo = [&](int q) -> const ER(&)[KPL] {
+      if constexpr (kDec) return Fo[q];
       else return F.o[q];
     };
     const int cexp = cexp_p ? cexp_p[k] : 0;
@@ -159,7 +166,6 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int bx, int ty) {
     // same B operand and the column of that row kept (stored after the loop,
     // since the main loop may also write its output slot).  FP32 matrix ops
     // are 8x slower, so there it stays a vector-ALU dot product.
-    const int oin = odd >= 0 ? (odd & 0xffff) : -1, oout = odd >> 16;
     f4 oacc[MTI];
     int oe = 0;
     for (int r = 0; r < ntile; ++r) {
@@ -182,8 +188,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int bx, int ty) {
 #pragma unroll
         for (int q = 0; q < MTI; ++q) {
           f4 acc = {0.f, 0.f, 0.f, 0.f};
-          ER tmp[KPL];
-          acc = DR::template mma<KPL>(fo(q, tmp), bo, acc);
+          acc = DR::template mma<KPL>(fo(q), bo, acc);
 #pragma unroll
           for (int i = 0; i < 4; ++i) acc[i] *= sc;
           oacc[q] = acc;
