@@ -227,6 +227,95 @@ def run_learned(n_meas=30, train_steps=150, learned_per_sweep=4):
 
 
 
+def run_learned_chi2(n_meas=300, train_steps=300, learned_per_sweep=2, burn=50, W=4096, power_steps=120):
+    """The bond-2 state of the paper's pipeline (10x10 open lattice, h = 3,
+    H+V+D+D' path, replica-space power method with H-bar_HV from the
+    constant train), where single-flip sweeps decorrelate slowly: effective
+    samples/s of single-flip sweeps alone against single-flip sweeps plus
+    learned multi-spin moves (network trained online on the chain's own
+    states, then frozen), same GPU, same walkers.  Both chains sample
+    |psi|^2 exactly, so at equal per-sample spread sigma_E the one with more
+    effective samples per second reaches a given energy error sooner."""
+    import torch
+
+    from paper_2604_22718_amd import pipeline
+    from paper_2604_22718_amd import rtt as R
+    from paper_2604_22718_amd import workloads as wl
+    L, hx = 10, 3.0
+    N = L * L
+    t0 = time.perf_counter()
+    pi, phi = pipeline.power_method(L, L, "HV", hx, 0.1, power_steps, chi=2, chi_sum=8, periodic=False)
+    out = {"workload": f"tfim{L}x{L}_open_h3_path_HVDDp_chi2_HV", "walkers": W, "power_steps": power_steps,
+           "power_method_s": time.perf_counter() - t0}
+    psi = R.RTT.create(N, pi, phi, "f32")
+    ham = R.TFIM(L, L, 1.0, hx, periodic=False)
+    net = R.Net(L, L, wl.net_init_params(4006))
+    out["narrow_kernels"] = bool(psi.info.get("narrow", 0))
+    ch = R.LearnedChain(psi, net, R.spins_to_device(wl.pack_spins(wl.random_spins(W, N, 4007))), seed=4008)
+    ch.sweep(burn)
+    t0 = time.perf_counter()
+    for it in range(train_steps):
+        ch.learned_step()
+        ch.train(lr=2e-3)
+        if it % 4 == 3:
+            ch.sweep(1)
+    torch.cuda.synchronize()
+    out["train_s"] = time.perf_counter() - t0
+    out["train_steps"] = train_steps
+    eloc = torch.empty(W, dtype=torch.float64, device="cuda")
+
+    def measure(learned):
+        c = R.LearnedChain(psi, net, ch.spins.clone(), seed=4009, rng_stream=1 + int(learned))
+        c.sweep(5)
+        torch.cuda.synchronize()
+        series, means = [], []
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        t_sw = t_le = 0.0
+        ev[0].record()
+        for t in range(n_meas):
+            c.sweep(1)
+            if learned:
+                for _ in range(learned_per_sweep):
+                    c.learned_step()
+            R.rtt_evaluate(psi.handle, ham.handle, c.spins, eloc=eloc)
+            series.append(eloc.clone())
+        ev[1].record()
+        torch.cuda.synchronize()
+        secs = ev[0].elapsed_time(ev[1]) * 1e-3
+        # cost of one sweep and of one learned move, timed apart
+        ev[2].record()
+        c.sweep(1)
+        ev[3].record()
+        torch.cuda.synchronize()
+        sweep_ms = ev[2].elapsed_time(ev[3])
+        E = torch.stack(series).cpu().numpy()
+        st = energy_stats(E, N)
+        res = {"seconds": secs, "measurements": n_meas, "tau_int": st["tau_int"],
+               "E_per_site": st["E_per_site"], "sigma_of_mean_per_site": st["sigma_per_site"],
+               "sigma_E_per_sample_per_site": float(E.std()) / N,
+               "effective_samples_per_s": W * n_meas / st["tau_int"] / secs, "sweep_ms": sweep_ms,
+               "single_flip_acceptance": c.acc_flip.sum().item() / (W * N * (n_meas + 6))}
+        if learned:
+            ev[2].record()
+            c.learned_step()
+            ev[3].record()
+            torch.cuda.synchronize()
+            res["learned_move_ms"] = ev[2].elapsed_time(ev[3])
+            res["learned_acceptance"] = c.acc_learn.sum().item() / (W * learned_per_sweep * n_meas + W)
+        return res
+
+    out["single_flip"] = measure(False)
+    out["single_flip_plus_learned"] = measure(True)
+    out["learned_moves_per_sweep"] = learned_per_sweep
+    out["ess_gain"] = (out["single_flip_plus_learned"]["effective_samples_per_s"]
+                       / out["single_flip"]["effective_samples_per_s"])
+    out["tau_ratio"] = out["single_flip"]["tau_int"] / out["single_flip_plus_learned"]["tau_int"]
+    net.close()
+    psi.close()
+    ham.close()
+    return out
+
+
 def run_wide(name, n_eval=3, with_sweep=True):
     """Local energies (and one sweep) of a wide-bond workload: 10x10, R=3,
     chi=128, 8192 walkers, BF16 (or 16x16, R=2, chi=256, 16384 walkers,
@@ -856,6 +945,8 @@ def main():
     ap.add_argument("--only-8x8", action="store_true", help="only the 8x8 lines (no headline)")
     ap.add_argument("--batched", type=int, default=3, help="time the 256-RTT batch for this many steps (0: skip)")
     ap.add_argument("--learned", action="store_true", help="also compare learned-proposal ESS/s (10x10, chi=128)")
+    ap.add_argument("--learned-chi2", action="store_true",
+                    help="also compare learned-proposal ESS/s on the bond-2 H-bar_HV state (10x10 open)")
     ap.add_argument("--dual", action="store_true", help="also the dual Monte Carlo line")
     ap.add_argument("--paper-pipeline", type=int, default=0, metavar="STEPS",
                     help="also run the chi=2 power method for STEPS steps plus two physical-space steps")
@@ -901,6 +992,8 @@ def main():
         res["batched"] = run_batched(a.batched)
     if a.learned:
         res["learned"] = run_learned()
+    if a.learned_chi2:
+        res["learned_chi2"] = run_learned_chi2()
     if not a.no_cpu:
         res["cpu_baseline"] = cpu_baseline()
         res["cpu_baseline"]["beside_8x8"] = cpu_baseline_8x8()

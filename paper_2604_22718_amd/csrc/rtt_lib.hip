@@ -1894,6 +1894,7 @@ struct rtt_net_s {
   int Lx = 0, Ly = 0, N = 0, nw = 0;
   float* d_master = nullptr;
   float* d_infer = nullptr;
+  uint16_t* d_wpk = nullptr;  // middle layers packed for the matrix cores
   float* d_m = nullptr;
   float* d_v = nullptr;
   float* d_grad = nullptr;
@@ -1913,8 +1914,8 @@ struct rtt_net_s {
 namespace {
 
 void free_net(rtt_net_s* n) {
-  for (void* p : {(void*)n->d_master, (void*)n->d_infer, (void*)n->d_m, (void*)n->d_v, (void*)n->d_grad,
-                  (void*)n->d_baseline})
+  for (void* p : {(void*)n->d_master, (void*)n->d_infer, (void*)n->d_wpk, (void*)n->d_m, (void*)n->d_v,
+                  (void*)n->d_grad, (void*)n->d_baseline})
     if (p) (void)hipFree(p);
   bool any = false;
   for (void* p : {(void*)n->d_prop, (void*)n->d_moves, (void*)n->d_lqf, (void*)n->d_lqr, (void*)n->d_la,
@@ -1985,10 +1986,18 @@ static rtt_status rtt_net_create_impl(int32_t Lx, int32_t Ly, const double* para
   rtt_net_s* n = new rtt_net_s;
   n->Lx = Lx; n->Ly = Ly; n->N = Lx * Ly; n->nw = (n->N + 63) / 64;
   std::vector<float> zeros(rttk::kNetParams, 0.f);
+  // the middle layers' weights as [layer][tap][co][ci] BF16 bits
+  std::vector<uint16_t> pk(rttk::kNetPacked);
+  for (int p = 0; p < rttk::kNetPacked; ++p) {
+    const int layer = p / (9 * rttk::kNetC * rttk::kNetC), r = p % (9 * rttk::kNetC * rttk::kNetC);
+    const int t = r / (rttk::kNetC * rttk::kNetC), co = (r / rttk::kNetC) % rttk::kNetC, ci = r % rttk::kNetC;
+    pk[p] = bf16_bits_rne(inf[(layer == 0 ? rttk::oW2 : rttk::oW3) + (co * rttk::kNetC + ci) * 9 + t]);
+  }
   double zb = 0.0;
   rtt_status st;
   if ((st = upload((void**)&n->d_master, m.data(), m.size() * 4)) != RTT_OK ||
       (st = upload((void**)&n->d_infer, inf.data(), inf.size() * 4)) != RTT_OK ||
+      (st = upload((void**)&n->d_wpk, pk.data(), pk.size() * 2)) != RTT_OK ||
       (st = upload((void**)&n->d_m, zeros.data(), zeros.size() * 4)) != RTT_OK ||
       (st = upload((void**)&n->d_v, zeros.data(), zeros.size() * 4)) != RTT_OK ||
       (st = upload((void**)&n->d_grad, zeros.data(), zeros.size() * 4)) != RTT_OK ||
@@ -2023,8 +2032,9 @@ rtt_status rtt_net_forward(rtt_net_t n, int32_t W, const uint64_t* spins, float*
   g_err.clear();
   if (!n || W < 1 || !spins || !out) return fail(RTT_E_ARG, "rtt_net_forward: bad argument");
   rttk::NetMoveArgs a{};
-  a.P = n->d_infer; a.Lx = n->Lx; a.Ly = n->Ly; a.nw = n->nw; a.W = W; a.spins = spins; a.out = out;
-  const size_t lds = rttk::net_lds_bytes(n->N);
+  a.P = n->d_infer; a.wpk = n->d_wpk; a.Lx = n->Lx; a.Ly = n->Ly; a.nw = n->nw; a.W = W; a.spins = spins;
+  a.out = out;
+  const size_t lds = rttk::net_fwd_lds_bytes(n->N);
   rtt_status st = net_set_lds((const void*)rttk::net_forward_kernel, lds);
   if (st != RTT_OK) return st;
   hipLaunchKernelGGL(rttk::net_forward_kernel, dim3(W), dim3(256), lds, (hipStream_t)stream, a);
@@ -2044,10 +2054,10 @@ rtt_status rtt_mh_learned_step(rtt_t h, rtt_net_t n, int32_t W, uint64_t* spins,
   rtt_status st = net_ws(n, W, s);
   if (st != RTT_OK) return st;
   rttk::NetMoveArgs a{};
-  a.P = n->d_infer; a.Lx = n->Lx; a.Ly = n->Ly; a.nw = n->nw; a.W = W; a.spins = spins;
+  a.P = n->d_infer; a.wpk = n->d_wpk; a.Lx = n->Lx; a.Ly = n->Ly; a.nw = n->nw; a.W = W; a.spins = spins;
   a.prop = n->d_prop; a.moves = moves ? moves : n->d_moves; a.lqf = n->d_lqf; a.lqr = n->d_lqr;
   a.seed = seed; a.rstream = rng_stream; a.step = step; a.before = before;
-  const size_t lds = rttk::net_lds_bytes(n->N);
+  const size_t lds = rttk::net_fwd_lds_bytes(n->N);
   if ((st = net_set_lds((const void*)rttk::net_propose_kernel, lds)) != RTT_OK) return st;
   if ((st = net_set_lds((const void*)rttk::net_reverse_kernel, lds)) != RTT_OK) return st;
   hipLaunchKernelGGL(rttk::net_propose_kernel, dim3(W), dim3(256), lds, s, a);
@@ -2088,6 +2098,9 @@ rtt_status rtt_net_train(rtt_net_t n, int32_t B, const uint64_t* spins, const in
   n->t += 1;
   hipLaunchKernelGGL(rttk::net_adam_kernel, dim3((rttk::kNetParams + 255) / 256), dim3(256), 0, s, n->d_master,
                      n->d_infer, n->d_m, n->d_v, n->d_grad, lr, beta1, beta2, eps, n->t);
+  HIPX(hipGetLastError());
+  hipLaunchKernelGGL(rttk::net_pack_kernel, dim3((rttk::kNetPacked + 255) / 256), dim3(256), 0, s, n->d_infer,
+                     n->d_wpk);
   HIPX(hipGetLastError());
   return RTT_OK;
 }

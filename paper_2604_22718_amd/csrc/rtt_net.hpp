@@ -109,8 +109,156 @@ __device__ inline float* net_forward_block(const float* __restrict__ P, const ui
   return o;
 }
 
-// LDS of the forward / propose / reverse kernels: z, A1..A3, o, log-probs, scratch
+// LDS of the scalar forward (training kernel): z, A1..A3, o, log-probs, scratch
 __host__ __device__ inline size_t net_lds_bytes(int N) { return (size_t)(280 + 115 * N) * 4; }
+
+// ---------------------------------------------------------------- matrix-core forward
+// The two 32 -> 32 channel 3x3 layers as implicit GEMMs on the BF16 matrix
+// cores: out^T[co][site] = sum over taps t and input channels ci of
+// W[co][ci][t] h[ci][nb(site, t)], one 16 (channels) x 16 (sites) tile per
+// matrix op sequence, K = 32 input channels per tap.  The weights are BF16
+// values already; each activation enters as three BF16 parts hi + mid + lo
+// (their sum equals it to about 2^-26 relative, finer than FP32 rounding),
+// so with FP32 accumulation the layer keeps FP32 accuracy.  Activations are
+// kept in LDS site-major, [site][channel], one plane per part.
+// Packed weights: [layer 2, 3][tap][co][ci] BF16, written from the
+// inference copy by net_pack_kernel.
+constexpr int kNetPacked = 2 * 9 * kNetC * kNetC;
+
+__global__ void net_pack_kernel(const float* infer, uint16_t* wpk) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= kNetPacked) return;
+  const int layer = p / (9 * kNetC * kNetC), r = p % (9 * kNetC * kNetC);
+  const int t = r / (kNetC * kNetC), co = (r / kNetC) % kNetC, ci = r % kNetC;
+  const float w = infer[(layer == 0 ? oW2 : oW3) + (co * kNetC + ci) * 9 + t];
+  wpk[p] = f32_to_bf16_rne(w);  // exact: the inference weights are BF16 values
+}
+
+__device__ __forceinline__ void split3_bf16(float x, uint16_t& h, uint16_t& m, uint16_t& l) {
+  const __bf16 xh = (__bf16)x;
+  const float r1 = x - (float)xh;
+  const __bf16 xm = (__bf16)r1;
+  const __bf16 xl = (__bf16)(r1 - (float)xm);
+  h = __builtin_bit_cast(uint16_t, xh);
+  m = __builtin_bit_cast(uint16_t, xm);
+  l = __builtin_bit_cast(uint16_t, xl);
+}
+
+// sites padded to whole 16-site tiles
+__host__ __device__ inline int net_padded(int N) { return (N + 15) / 16 * 16; }
+// LDS (floats) of the matrix-core forward kernels: z[256], two activation
+// buffers of three [NP][32] BF16 planes (the first later holds SiLU(a3) as
+// [32][N] floats), o[9][N], then the log-probability area of the proposal
+// kernels (lc[N] doubles, lk[8][N], reduction scratch, move, flip set)
+__host__ __device__ inline size_t net_fwd_lds_bytes(int N) {
+  return (size_t)(280 + 96 * net_padded(N) + 19 * N) * 4;
+}
+
+// One 32 -> 32 layer: input planes in (SiLU'd activations, split), output
+// SiLU(a) either split into the planes out, or as FP32 [32][N] into h3.
+__device__ __forceinline__ void net_conv_mfma(const uint16_t* __restrict__ wl, const float* __restrict__ bias,
+                                              const uint16_t* in, uint16_t* out, float* h3, const NetGeo& g,
+                                              int NP) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int gq = lane >> 4, m = lane & 15;
+  const int ct = wave >> 1;  // output channel tile of this wave
+  const int N = g.N;
+  bf16x8 wa[9];
+#pragma unroll
+  for (int t = 0; t < 9; ++t)
+    wa[t] = *reinterpret_cast<const bf16x8*>(wl + ((size_t)t * kNetC + ct * 16 + m) * kNetC + 8 * gq);
+  float bv[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) bv[i] = bias[ct * 16 + 4 * gq + i];
+  const size_t plane = (size_t)NP * kNetC;
+  for (int st = wave & 1; st < NP / 16; st += 2) {
+    const int site = st * 16 + m;
+    const int sc = site < N ? site : 0;
+    const int x = sc % g.Lx, y = sc / g.Lx;
+    f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
+      yy += yy < 0 ? g.Ly : 0;
+      yy -= yy >= g.Ly ? g.Ly : 0;
+      xx += xx < 0 ? g.Lx : 0;
+      xx -= xx >= g.Lx ? g.Lx : 0;
+      const uint16_t* row = in + (size_t)(yy * g.Lx + xx) * kNetC + 8 * gq;
+      const bf16x8 bl = *reinterpret_cast<const bf16x8*>(row + 2 * plane);
+      const bf16x8 bm = *reinterpret_cast<const bf16x8*>(row + plane);
+      const bf16x8 bh = *reinterpret_cast<const bf16x8*>(row);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[t], bl, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[t], bm, acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[t], bh, acc, 0, 0, 0);
+    }
+    if (site < N) {  // lane holds channels ct*16 + 4gq .. +3 of this site
+      const int c0 = ct * 16 + 4 * gq;
+      if (h3) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) h3[(c0 + i) * N + site] = silu_f(acc[i] + bv[i]);
+      } else {
+        uint16_t ph[4], pm[4], pl[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) split3_bf16(silu_f(acc[i] + bv[i]), ph[i], pm[i], pl[i]);
+        uint16_t* o = out + (size_t)site * kNetC + c0;
+        *reinterpret_cast<uint2*>(o) = make_uint2(ph[0] | (uint32_t)ph[1] << 16, ph[2] | (uint32_t)ph[3] << 16);
+        *reinterpret_cast<uint2*>(o + plane) =
+            make_uint2(pm[0] | (uint32_t)pm[1] << 16, pm[2] | (uint32_t)pm[3] << 16);
+        *reinterpret_cast<uint2*>(o + 2 * plane) =
+            make_uint2(pl[0] | (uint32_t)pl[1] << 16, pl[2] | (uint32_t)pl[3] << 16);
+      }
+    }
+  }
+}
+
+// Forward pass of one configuration with the layers above (256 threads:
+// layer 1 and the head one thread per site, the two middle layers on the
+// matrix cores).  Returns o[9][N] in LDS.
+__device__ inline float* net_forward_mfma(const float* __restrict__ P, const uint16_t* __restrict__ wpk,
+                                          const uint64_t* spins, const NetGeo& g, float* lds) {
+  const int N = g.N, i = threadIdx.x, NP = net_padded(N);
+  const bool act = i < N;
+  float* z = lds;
+  uint16_t* S0 = reinterpret_cast<uint16_t*>(lds + 256);
+  uint16_t* S1 = S0 + 3 * NP * kNetC;
+  float* H3 = reinterpret_cast<float*>(S0);  // S0 is free once layer 2 has run
+  float* o = reinterpret_cast<float*>(S1 + 3 * NP * kNetC);
+  if (act) z[i] = 1.f - 2.f * (float)spin_bit(spins, i);
+  __syncthreads();
+  if (act) {
+    float acc[kNetC];
+    conv_site<1>(P + oW1, P + ob1, z, false, g, acc);
+    const size_t plane = (size_t)NP * kNetC;
+#pragma unroll
+    for (int c = 0; c < kNetC; c += 2) {
+      uint16_t h0, m0, l0, h1, m1, l1;
+      split3_bf16(silu_f(acc[c]), h0, m0, l0);
+      split3_bf16(silu_f(acc[c + 1]), h1, m1, l1);
+      uint32_t* row = reinterpret_cast<uint32_t*>(S0 + (size_t)i * kNetC + c);
+      row[0] = h0 | (uint32_t)h1 << 16;
+      row[plane / 2] = m0 | (uint32_t)m1 << 16;
+      row[plane] = l0 | (uint32_t)l1 << 16;
+    }
+  }
+  __syncthreads();
+  net_conv_mfma(wpk, P + ob2, S0, S1, nullptr, g, NP);
+  __syncthreads();
+  net_conv_mfma(wpk + 9 * kNetC * kNetC, P + ob3, S1, nullptr, H3, g, NP);
+  __syncthreads();
+  if (act) {
+    float h[kNetC];
+#pragma unroll
+    for (int c = 0; c < kNetC; ++c) h[c] = H3[c * N + i];
+    for (int k = 0; k < 9; ++k) {
+      float s = P[obh + k];
+#pragma unroll
+      for (int c = 0; c < kNetC; ++c) s = fmaf(P[oWh + k * kNetC + c], h[c], s);
+      o[k * N + i] = s;
+    }
+  }
+  __syncthreads();
+  return o;
+}
 
 // block-wide reductions (256 threads)
 __device__ inline double block_sum_d(double x, double* sh) {
@@ -177,6 +325,7 @@ __device__ inline double net_set_prob(const double* lc, const float* lk, const N
 
 struct NetMoveArgs {
   const float* P;          // inference weights
+  const uint16_t* wpk;     // the middle layers' weights packed for the matrix cores
   int Lx, Ly, nw, W;
   const uint64_t* spins;   // [W][nw] current
   uint64_t* prop;          // [W][nw] proposed (written by propose)
@@ -195,7 +344,7 @@ __global__ void __launch_bounds__(256) net_propose_kernel(NetMoveArgs a) {
   g.init(a.Lx, a.Ly);
   const int w = blockIdx.x, N = g.N;
   const uint64_t* sw = a.spins + (size_t)w * a.nw;
-  float* o = net_forward_block(a.P, sw, g, lds);
+  float* o = net_forward_mfma(a.P, a.wpk, sw, g, lds);
   double* lc = reinterpret_cast<double*>(o + 9 * N + (N & 1));
   float* lk = reinterpret_cast<float*>(lc + N);
   double* shd = reinterpret_cast<double*>(lk + 8 * N + ((8 * N) & 1));
@@ -245,7 +394,7 @@ __global__ void __launch_bounds__(256) net_reverse_kernel(NetMoveArgs a) {
   NetGeo g;
   g.init(a.Lx, a.Ly);
   const int w = blockIdx.x, N = g.N;
-  float* o = net_forward_block(a.P, a.prop + (size_t)w * a.nw, g, lds);
+  float* o = net_forward_mfma(a.P, a.wpk, a.prop + (size_t)w * a.nw, g, lds);
   double* lc = reinterpret_cast<double*>(o + 9 * N + (N & 1));
   float* lk = reinterpret_cast<float*>(lc + N);
   double* shd = reinterpret_cast<double*>(lk + 8 * N + ((8 * N) & 1));
@@ -272,7 +421,7 @@ __global__ void __launch_bounds__(256) net_forward_kernel(NetMoveArgs a) {
   NetGeo g;
   g.init(a.Lx, a.Ly);
   const int w = blockIdx.x, N = g.N;
-  const float* o = net_forward_block(a.P, a.spins + (size_t)w * a.nw, g, lds);
+  const float* o = net_forward_mfma(a.P, a.wpk, a.spins + (size_t)w * a.nw, g, lds);
   for (int i = threadIdx.x; i < 9 * N; i += 256) a.out[(size_t)w * 9 * N + i] = o[i];
 }
 
