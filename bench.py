@@ -945,8 +945,8 @@ def main():
     ap.add_argument("--only-8x8", action="store_true", help="only the 8x8 lines (no headline)")
     ap.add_argument("--batched", type=int, default=3, help="time the 256-RTT batch for this many steps (0: skip)")
     ap.add_argument("--learned", action="store_true", help="also compare learned-proposal ESS/s (10x10, chi=128)")
-    ap.add_argument("--learned-chi2", action="store_true",
-                    help="also compare learned-proposal ESS/s on the bond-2 H-bar_HV state (10x10 open)")
+    ap.add_argument("--no-learned-chi2", action="store_true",
+                    help="skip the learned-proposal ESS/s comparison on the bond-2 H-bar_HV state (10x10 open)")
     ap.add_argument("--dual", action="store_true", help="also the dual Monte Carlo line")
     ap.add_argument("--paper-pipeline", type=int, default=0, metavar="STEPS",
                     help="also run the chi=2 power method for STEPS steps plus two physical-space steps")
@@ -992,8 +992,9 @@ def main():
         res["batched"] = run_batched(a.batched)
     if a.learned:
         res["learned"] = run_learned()
-    if a.learned_chi2:
+    if not a.no_learned_chi2:
         res["learned_chi2"] = run_learned_chi2()
+        print("[bench] learned-proposal comparison done", file=sys.stderr, flush=True)
     if not a.no_cpu:
         res["cpu_baseline"] = cpu_baseline()
         res["cpu_baseline"]["beside_8x8"] = cpu_baseline_8x8()

@@ -1944,11 +1944,14 @@ rtt_status net_set_lds(const void* f, size_t bytes) {
   return RTT_OK;
 }
 
+constexpr int kNetSlices = 32;  // first-stage slices of the gradient sum over samples
+
 rtt_status net_grad_launch(rtt_net_s* n, int B, const uint64_t* spins, const int32_t* moves,
                            const float* accept_prob, float* grad, hipStream_t s) {
   if (B > n->B_ws) {
     n->B_ws = 0;
-    rtt_status st = grow_async((void**)&n->d_partial, (size_t)B * rttk::kNetParams * 4, s);
+    // per-sample gradients, then room for the slice sums of the reduction
+    rtt_status st = grow_async((void**)&n->d_partial, (size_t)(B + kNetSlices) * rttk::kNetParams * 4, s);
     if (st != RTT_OK) return st;
     n->B_ws = B;
   }
@@ -1961,8 +1964,13 @@ rtt_status net_grad_launch(rtt_net_s* n, int B, const uint64_t* spins, const int
   if (st != RTT_OK) return st;
   hipLaunchKernelGGL(rttk::net_grad_kernel, dim3(B), dim3(256), lds, s, ga);
   HIPX(hipGetLastError());
+  const int S = std::min(B, kNetSlices);
+  float* slices = n->d_partial + (size_t)B * rttk::kNetParams;
+  hipLaunchKernelGGL(rttk::net_reduce_slices_kernel, dim3((rttk::kNetParams + 255) / 256, S), dim3(256), 0, s,
+                     n->d_partial, B, S, slices);
+  HIPX(hipGetLastError());
   hipLaunchKernelGGL(rttk::net_reduce_kernel, dim3((rttk::kNetParams + 255) / 256), dim3(256), 0, s,
-                     n->d_partial, B, grad);
+                     slices, S, grad);
   HIPX(hipGetLastError());
   return RTT_OK;
 }

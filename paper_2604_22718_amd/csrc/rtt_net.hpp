@@ -352,16 +352,35 @@ __global__ void __launch_bounds__(256) net_propose_kernel(NetMoveArgs a) {
   int* mv = reinterpret_cast<int*>(shf + 4);
   uint64_t* tgt = reinterpret_cast<uint64_t*>(mv + 2);
   net_logprobs(o, g, lc, lk, shd, shf);
-  if (threadIdx.x == 0) {
+  // inverse-CDF draw of the centre: inclusive prefix sums of p(c = i) over
+  // the sites (FP64 block scan in site order), c = the first site whose sum
+  // exceeds uc (the last site if none does)
+  {
+    const int i = threadIdx.x, lane = i & 63, wv = i >> 6;
     const double uc = philox_uniform(a.seed, a.rstream, (uint64_t)w, a.step, (1ull << 32) + 0);
-    const double uk = philox_uniform(a.seed, a.rstream, (uint64_t)w, a.step, (1ull << 32) + 1);
-    double cum = 0.0;
-    int c = N - 1;
-    for (int i = 0; i < N; ++i) {
-      cum += exp(lc[i]);
-      if (cum > uc) { c = i; break; }
+    double cum = i < N ? exp(lc[i]) : 0.0;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const double y = __shfl_up(cum, o);
+      if (lane >= o) cum += y;
     }
-    cum = 0.0;
+    if (lane == 63) shd[wv] = cum;
+    __syncthreads();
+    for (int q = 0; q < wv; ++q) cum += shd[q];
+    int cand = (i < N && cum > uc) ? i : N - 1;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) cand = min(cand, __shfl_xor(cand, o));
+    int* shi = reinterpret_cast<int*>(shf);
+    __syncthreads();
+    if (lane == 0) shi[wv] = cand;
+    __syncthreads();
+    if (i == 0) mv[0] = min(min(shi[0], shi[1]), min(shi[2], shi[3]));
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double uk = philox_uniform(a.seed, a.rstream, (uint64_t)w, a.step, (1ull << 32) + 1);
+    const int c = mv[0];
+    double cum = 0.0;
     int k = 8;
     for (int m = 0; m < 8; ++m) {
       cum += exp((double)lk[m * N + c]);
@@ -580,6 +599,17 @@ __global__ void __launch_bounds__(256) net_grad_kernel(NetGradArgs a) {
 }
 
 __host__ __device__ inline size_t net_grad_lds_bytes(int N) { return (size_t)(280 + 147 * N) * 4; }
+
+// Sum over samples in two fixed-order stages: slice y of S adds its share
+// of the samples, then net_reduce_kernel adds the S slices.
+__global__ void net_reduce_slices_kernel(const float* partial, int B, int S, float* out) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x, y = blockIdx.y;
+  if (p >= kNetParams) return;
+  const int b0 = (int)((long long)B * y / S), b1 = (int)((long long)B * (y + 1) / S);
+  float s = 0.f;
+  for (int b = b0; b < b1; ++b) s += partial[(size_t)b * kNetParams + p];
+  out[(size_t)y * kNetParams + p] = s;
+}
 
 // grad[p] = sum_b partial[b][p] (fixed order); baseline <- 0.9 baseline + 0.1 mean(a k)
 __global__ void net_reduce_kernel(const float* partial, int B, float* grad) {
