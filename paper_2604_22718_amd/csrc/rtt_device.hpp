@@ -414,6 +414,16 @@ struct Act<DBF16, CHI> {
     *reinterpret_cast<uint2*>(p) = make_uint2(h01, h23);
     *reinterpret_cast<uint2*>(p + CHI) = make_uint2(l01, l23);
   }
+  // store4 through non-temporal stores (rows in global memory)
+  __device__ __forceinline__ static void store4_nt(float* row, int col, f4 v) {
+    typedef uint32_t u2 __attribute__((ext_vector_type(2)));
+    uint32_t h01, l01, h23, l23;
+    split_bf16x2(v[0], v[1], h01, l01);
+    split_bf16x2(v[2], v[3], h23, l23);
+    uint16_t* p = hi(row) + col;
+    __builtin_nontemporal_store(u2{h01, h23}, reinterpret_cast<u2*>(p));
+    __builtin_nontemporal_store(u2{l01, l23}, reinterpret_cast<u2*>(p + CHI));
+  }
   __device__ __forceinline__ static void store1(float* row, int col, float x) {
     uint16_t h, l;
     split(x, h, l);

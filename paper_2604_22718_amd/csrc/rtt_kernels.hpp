@@ -523,7 +523,8 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
     return b == P ? rows + t * BUF : rows + (T + b - F) * BUF;  // U is not used then
   };
   // CKG (sequential layout only): the checkpoint vectors are in global
-  // memory, addressed by gbuf; a segment starting from one first copies it
+  // memory, addressed by gbuf and accessed non-temporally (they must not
+  // push the core fragments out of L2); a segment starting from one first copies it
   // into the spare column buffer, so that every vector access of the steps
   // stays an LDS access.
   float* ckg = (CKG && NCK > 0) ? a.ckg + (size_t)bx * 2 * NCK * T * BUF : nullptr;
@@ -607,7 +608,7 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
       if (cks >= 0) {
         for (int i = threadIdx.x; i < tn * (BUF / 4); i += nthr) {
           const int t = t0 + i / (BUF / 4), r = i % (BUF / 4);
-          reinterpret_cast<float4*>(buf(t, CY))[r] = reinterpret_cast<const float4*>(gbuf(t, cks))[r];
+          reinterpret_cast<f4*>(buf(t, CY))[r] = __builtin_nontemporal_load(reinterpret_cast<const f4*>(gbuf(t, cks)) + r);
         }
         lds_barrier();
         ck_src = CY;
@@ -726,7 +727,7 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
           for (int cg = 0; cg < CG; ++cg) {
             const int wn = 16 * cg + m;
             const f4 sel = bit[cg] ? c1[cg] : c0[cg];
-            if constexpr (CKG) A::store4(gbuf(t, slot) + wn * RS, 16 * tt + 4 * g, sel);
+            if constexpr (CKG) A::store4_nt(gbuf(t, slot) + wn * RS, 16 * tt + 4 * g, sel);
             else A::store4(buf(t, slot) + wn * RS, 16 * tt + 4 * g, sel);
             if (wv == 0 && g == 0 && mt == 0) ckexp(slot, t, wn) = Ec[t * NB + wn];
           }
@@ -991,8 +992,9 @@ __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t 
                 for (int t = 0; t < T; ++t) {
                   for (int q = r; q < CHI / 4; q += 4 * nwave) {
                     if constexpr (CKG)
-                      reinterpret_cast<float4*>(gbuf(t, CK + i) + wn * RS)[q] =
-                          reinterpret_cast<const float4*>(gbuf(t, CD + i) + wn * RS)[q];
+                      __builtin_nontemporal_store(
+                          __builtin_nontemporal_load(reinterpret_cast<const f4*>(gbuf(t, CD + i) + wn * RS) + q),
+                          reinterpret_cast<f4*>(gbuf(t, CK + i) + wn * RS) + q);
                     else
                       reinterpret_cast<float4*>(buf(t, CK + i) + wn * RS)[q] =
                           reinterpret_cast<const float4*>(buf(t, CD + i) + wn * RS)[q];
