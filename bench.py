@@ -220,6 +220,16 @@ def run_learned(n_meas=30, train_steps=150, learned_per_sweep=4):
 
     out["single_flip"] = measure(False)
     out["single_flip_plus_learned"] = measure(True)
+    # the network's forward pass alone over every walker (head outputs to HBM)
+    net.forward(ch.spins)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(10):
+        net.forward(ch.spins)
+    ev[1].record()
+    torch.cuda.synchronize()
+    out["network_forward_ms"] = ev[0].elapsed_time(ev[1]) / 10
+    out["network_forward_over_sweep"] = out["network_forward_ms"] / out["single_flip"]["sweep_ms"]
     out["learned_moves_per_sweep"] = learned_per_sweep
     out["ess_gain"] = (out["single_flip_plus_learned"]["effective_samples_per_s"]
                        / out["single_flip"]["effective_samples_per_s"])
@@ -306,6 +316,16 @@ def run_learned_chi2(n_meas=300, train_steps=300, learned_per_sweep=2, burn=50, 
 
     out["single_flip"] = measure(False)
     out["single_flip_plus_learned"] = measure(True)
+    # the network's forward pass alone over every walker (head outputs to HBM)
+    net.forward(ch.spins)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(10):
+        net.forward(ch.spins)
+    ev[1].record()
+    torch.cuda.synchronize()
+    out["network_forward_ms"] = ev[0].elapsed_time(ev[1]) / 10
+    out["network_forward_over_sweep"] = out["network_forward_ms"] / out["single_flip"]["sweep_ms"]
     out["learned_moves_per_sweep"] = learned_per_sweep
     out["ess_gain"] = (out["single_flip_plus_learned"]["effective_samples_per_s"]
                        / out["single_flip"]["effective_samples_per_s"])
