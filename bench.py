@@ -166,121 +166,39 @@ def run_batched(steps, n_rtt=256):
     return res
 
 
-def run_learned(n_meas=30, train_steps=150, learned_per_sweep=4):
-    """10x10, R=3, chi=128, 8192 walkers, BF16: effective samples/s of
-    single-flip sweeps alone vs single-flip sweeps + learned multi-spin moves
-    (network trained online on the chain, then frozen), same GPU."""
+def compare_learned(psi, ham, net, spins0, N, seed, n_meas, train_steps, learned_per_sweep, burn, lr,
+                    sigma_target):
+    """Single-flip sweeps against sweeps + learned MH moves on the same state
+    and walkers: burn-in, online training of the network on the chain's own
+    states (then frozen), and n_meas measurements of every walker's E_loc per
+    chain.  Both chains sample |psi|^2 exactly; the wall time to bring the
+    error of the mean energy to sigma_target (per site) is
+    (sigma_E / sigma_target)^2 / ESS-rate, so ESS/s orders them at equal
+    energy error."""
     import torch
 
     from paper_2604_22718_amd import rtt as R
-    from paper_2604_22718_amd import workloads as wl
-    w = wl.LARGE_10x10
-    psi = R.RTT.create(w.N, w.pi(), w.cores(), "bf16")
-    ham = R.TFIM(w.Lx, w.Ly, w.J, w.h)
-    net = R.Net(w.Lx, w.Ly, wl.net_init_params(4004))
-    out = {"workload": w.name, "walkers": w.W}
-    spins0 = R.spins_to_device(wl.pack_spins(w.spins()))
-    # burn-in and online training
-    ch = R.LearnedChain(psi, net, spins0.clone(), seed=w.chain_seed)
+    W = spins0.shape[0]
+    out = {"walkers": W, "burn_in_sweeps": burn, "measurements": n_meas}
+    ch = R.LearnedChain(psi, net, spins0.clone(), seed=seed)
     t0 = time.perf_counter()
-    ch.sweep(5)
-    for it in range(train_steps):
-        ch.learned_step()
-        ch.train(lr=2e-3)
-        if it % 10 == 9:
-            ch.sweep(1)
-    torch.cuda.synchronize()
-    out["train_s"] = time.perf_counter() - t0
-    out["train_steps"] = train_steps
-
-    def measure(learned):
-        c = R.LearnedChain(psi, net, ch.spins.clone(), seed=w.chain_seed + 17, rng_stream=1 + int(learned))
-        c.sweep(2)
-        torch.cuda.synchronize()
-        series = []
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        ev0.record()
-        for _ in range(n_meas):
-            c.sweep(1)
-            if learned:
-                for _ in range(learned_per_sweep):
-                    c.learned_step()
-            series.append(psi.local_energy(c.spins, ham).mean())
-        ev1.record()
-        torch.cuda.synchronize()
-        secs = ev0.elapsed_time(ev1) * 1e-3
-        e = torch.stack(series).cpu().numpy()
-        tau = tau_int(e)
-        res = {"seconds": secs, "tau_int_measurements": tau, "energy_per_site": float(e.mean()) / w.N,
-               "effective_samples_per_s": w.W * n_meas / tau / secs,
-               "single_flip_acceptance": c.acc_flip.sum().item() / (w.W * w.N * (n_meas + 2))}
-        if learned:
-            res["learned_acceptance"] = c.acc_learn.sum().item() / (w.W * learned_per_sweep * n_meas)
-        return res
-
-    out["single_flip"] = measure(False)
-    out["single_flip_plus_learned"] = measure(True)
-    # the network's forward pass alone over every walker (head outputs to HBM)
-    net.forward(ch.spins)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-    ev[0].record()
-    for _ in range(10):
-        net.forward(ch.spins)
-    ev[1].record()
-    torch.cuda.synchronize()
-    out["network_forward_ms"] = ev[0].elapsed_time(ev[1]) / 10
-    out["network_forward_over_sweep"] = out["network_forward_ms"] / out["single_flip"]["sweep_ms"]
-    out["learned_moves_per_sweep"] = learned_per_sweep
-    out["ess_gain"] = (out["single_flip_plus_learned"]["effective_samples_per_s"]
-                       / out["single_flip"]["effective_samples_per_s"])
-    return out
-
-
-
-def run_learned_chi2(n_meas=300, train_steps=300, learned_per_sweep=2, burn=50, W=4096, power_steps=120):
-    """The bond-2 state of the paper's pipeline (10x10 open lattice, h = 3,
-    H+V+D+D' path, replica-space power method with H-bar_HV from the
-    constant train), where single-flip sweeps decorrelate slowly: effective
-    samples/s of single-flip sweeps alone against single-flip sweeps plus
-    learned multi-spin moves (network trained online on the chain's own
-    states, then frozen), same GPU, same walkers.  Both chains sample
-    |psi|^2 exactly, so at equal per-sample spread sigma_E the one with more
-    effective samples per second reaches a given energy error sooner."""
-    import torch
-
-    from paper_2604_22718_amd import pipeline
-    from paper_2604_22718_amd import rtt as R
-    from paper_2604_22718_amd import workloads as wl
-    L, hx = 10, 3.0
-    N = L * L
-    t0 = time.perf_counter()
-    pi, phi = pipeline.power_method(L, L, "HV", hx, 0.1, power_steps, chi=2, chi_sum=8, periodic=False)
-    out = {"workload": f"tfim{L}x{L}_open_h3_path_HVDDp_chi2_HV", "walkers": W, "power_steps": power_steps,
-           "power_method_s": time.perf_counter() - t0}
-    psi = R.RTT.create(N, pi, phi, "f32")
-    ham = R.TFIM(L, L, 1.0, hx, periodic=False)
-    net = R.Net(L, L, wl.net_init_params(4006))
-    out["narrow_kernels"] = bool(psi.info.get("narrow", 0))
-    ch = R.LearnedChain(psi, net, R.spins_to_device(wl.pack_spins(wl.random_spins(W, N, 4007))), seed=4008)
     ch.sweep(burn)
-    t0 = time.perf_counter()
     for it in range(train_steps):
         ch.learned_step()
-        ch.train(lr=2e-3)
+        ch.train(lr=lr)
         if it % 4 == 3:
             ch.sweep(1)
     torch.cuda.synchronize()
-    out["train_s"] = time.perf_counter() - t0
+    out["burn_in_and_training_s"] = time.perf_counter() - t0
     out["train_steps"] = train_steps
     eloc = torch.empty(W, dtype=torch.float64, device="cuda")
 
     def measure(learned):
-        c = R.LearnedChain(psi, net, ch.spins.clone(), seed=4009, rng_stream=1 + int(learned))
+        c = R.LearnedChain(psi, net, ch.spins.clone(), seed=seed + 1, rng_stream=1 + int(learned))
         c.sweep(5)
         torch.cuda.synchronize()
-        series, means = [], []
+        series = []
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-        t_sw = t_le = 0.0
         ev[0].record()
         for t in range(n_meas):
             c.sweep(1)
@@ -292,18 +210,19 @@ def run_learned_chi2(n_meas=300, train_steps=300, learned_per_sweep=2, burn=50, 
         ev[1].record()
         torch.cuda.synchronize()
         secs = ev[0].elapsed_time(ev[1]) * 1e-3
-        # cost of one sweep and of one learned move, timed apart
         ev[2].record()
         c.sweep(1)
         ev[3].record()
         torch.cuda.synchronize()
-        sweep_ms = ev[2].elapsed_time(ev[3])
         E = torch.stack(series).cpu().numpy()
         st = energy_stats(E, N)
-        res = {"seconds": secs, "measurements": n_meas, "tau_int": st["tau_int"],
-               "E_per_site": st["E_per_site"], "sigma_of_mean_per_site": st["sigma_per_site"],
-               "sigma_E_per_sample_per_site": float(E.std()) / N,
-               "effective_samples_per_s": W * n_meas / st["tau_int"] / secs, "sweep_ms": sweep_ms,
+        ess = W * n_meas / st["tau_int"] / secs
+        sig = float(E.std()) / N
+        res = {"seconds": secs, "tau_int": st["tau_int"], "E_per_site": st["E_per_site"],
+               "sigma_of_mean_per_site": st["sigma_per_site"], "sigma_E_per_sample_per_site": sig,
+               "effective_samples_per_s": ess,
+               "seconds_to_sigma_target": (sig / sigma_target) ** 2 / ess,
+               "sweep_ms": ev[2].elapsed_time(ev[3]),
                "single_flip_acceptance": c.acc_flip.sum().item() / (W * N * (n_meas + 6))}
         if learned:
             ev[2].record()
@@ -314,6 +233,7 @@ def run_learned_chi2(n_meas=300, train_steps=300, learned_per_sweep=2, burn=50, 
             res["learned_acceptance"] = c.acc_learn.sum().item() / (W * learned_per_sweep * n_meas + W)
         return res
 
+    out["sigma_target_per_site"] = sigma_target
     out["single_flip"] = measure(False)
     out["single_flip_plus_learned"] = measure(True)
     # the network's forward pass alone over every walker (head outputs to HBM)
@@ -330,6 +250,50 @@ def run_learned_chi2(n_meas=300, train_steps=300, learned_per_sweep=2, burn=50, 
     out["ess_gain"] = (out["single_flip_plus_learned"]["effective_samples_per_s"]
                        / out["single_flip"]["effective_samples_per_s"])
     out["tau_ratio"] = out["single_flip"]["tau_int"] / out["single_flip_plus_learned"]["tau_int"]
+    return out
+
+
+def run_learned(n_meas=200, train_steps=150, learned_per_sweep=4):
+    """10x10 periodic TFIM, R = 3, chi = 128, 8192 walkers, BF16 cores (the
+    learned-proposal workload): single-flip sweeps against sweeps + learned
+    moves, network trained online on the chain and then frozen."""
+    from paper_2604_22718_amd import rtt as R
+    from paper_2604_22718_amd import workloads as wl
+    w = wl.LARGE_10x10
+    psi = R.RTT.create(w.N, w.pi(), w.cores(), "bf16")
+    ham = R.TFIM(w.Lx, w.Ly, w.J, w.h)
+    net = R.Net(w.Lx, w.Ly, wl.net_init_params(4004))
+    spins0 = R.spins_to_device(wl.pack_spins(w.spins()))
+    out = {"workload": w.name}
+    out.update(compare_learned(psi, ham, net, spins0, w.N, w.chain_seed, n_meas, train_steps,
+                               learned_per_sweep, w.burn_in, 2e-3, sigma_target=1e-4))
+    net.close()
+    psi.close()
+    ham.close()
+    return out
+
+
+def run_learned_chi2(n_meas=300, train_steps=300, learned_per_sweep=2, burn=50, W=4096, power_steps=120):
+    """The bond-2 state of the paper's pipeline (10x10 open lattice, h = 3,
+    H+V+D+D' path, replica-space power method with H-bar_HV from the
+    constant train), where single-flip sweeps decorrelate more slowly than
+    on random cores: single-flip sweeps against sweeps + learned moves."""
+    from paper_2604_22718_amd import pipeline
+    from paper_2604_22718_amd import rtt as R
+    from paper_2604_22718_amd import workloads as wl
+    L, hx = 10, 3.0
+    N = L * L
+    t0 = time.perf_counter()
+    pi, phi = pipeline.power_method(L, L, "HV", hx, 0.1, power_steps, chi=2, chi_sum=8, periodic=False)
+    out = {"workload": f"tfim{L}x{L}_open_h3_path_HVDDp_chi2_HV", "power_steps": power_steps,
+           "power_method_s": time.perf_counter() - t0}
+    psi = R.RTT.create(N, pi, phi, "f32")
+    ham = R.TFIM(L, L, 1.0, hx, periodic=False)
+    net = R.Net(L, L, wl.net_init_params(4006))
+    out["narrow_kernels"] = bool(psi.info.get("narrow", 0))
+    spins0 = R.spins_to_device(wl.pack_spins(wl.random_spins(W, N, 4007)))
+    out.update(compare_learned(psi, ham, net, spins0, N, 4008, n_meas, train_steps, learned_per_sweep, burn,
+                               2e-3, sigma_target=1e-5))
     net.close()
     psi.close()
     ham.close()
@@ -964,7 +928,8 @@ def main():
     ap.add_argument("--no-wide", action="store_true", help="skip the 10x10 chi=128 BF16 wide-bond line")
     ap.add_argument("--only-8x8", action="store_true", help="only the 8x8 lines (no headline)")
     ap.add_argument("--batched", type=int, default=3, help="time the 256-RTT batch for this many steps (0: skip)")
-    ap.add_argument("--learned", action="store_true", help="also compare learned-proposal ESS/s (10x10, chi=128)")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-proposal ESS/s comparison on the 10x10, chi=128 workload")
     ap.add_argument("--no-learned-chi2", action="store_true",
                     help="skip the learned-proposal ESS/s comparison on the bond-2 H-bar_HV state (10x10 open)")
     ap.add_argument("--dual", action="store_true", help="also the dual Monte Carlo line")
@@ -1010,8 +975,9 @@ def main():
         res["paper_pipeline"] = run_paper_pipeline(L=a.paper_side, steps=a.paper_pipeline, table=a.paper_table)
     if a.batched:
         res["batched"] = run_batched(a.batched)
-    if a.learned:
+    if not a.no_learned:
         res["learned"] = run_learned()
+        print("[bench] learned-proposal comparison (10x10, chi=128) done", file=sys.stderr, flush=True)
     if not a.no_learned_chi2:
         res["learned_chi2"] = run_learned_chi2()
         print("[bench] learned-proposal comparison done", file=sys.stderr, flush=True)
