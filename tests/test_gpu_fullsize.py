@@ -19,7 +19,8 @@ Philox words must make the oracle's decisions for every walker whose
 decision margins |u - r^2| exceed 10 times the error in r^2 measured on that
 walker's near-tie ratios.  At 8x8 the mean
 energy of the full GPU chain (50 burn-in + 200 measured sweeps) must lie
-within 3 sigma of the oracle chain's FP64 mean."""
+within 3 sigma of the oracle chain's FP64 mean.  At 16x16 one learned MH
+step of the full launch proposes the oracle's moves."""
 import math
 
 import numpy as np
@@ -142,3 +143,62 @@ def test_full_size_chain_energy_within_3_sigma_of_oracle(R, dtype):
         assert np.all(rel[:, same] <= 1e-3)
     psi.close()
     ham.close()
+
+
+def test_full_size_learned_step(R):
+    """16x16, R = 2, chi = 256, four FP8 terms, 16384 walkers, with the
+    learned proposal on (the headline launch): one learned MH step from the
+    oracle-sampled configurations placed at their walker indices.  For those
+    walkers the GPU proposes the oracle's move (c, k) — same network on the
+    device's BF16 weights, same Philox words — and makes the oracle's
+    accept decision wherever the decision is not a near-tie: the uniform is
+    further than 1e-2 from the acceptance ratio, whose GPU value carries the
+    FP8 path's amplitude errors, and no sampling uniform lies within 1e-5 of
+    a cumulative boundary.  (On these |psi|^2-typical configurations of a
+    random state the oracle's acceptance ratios are below 1e-13, so the
+    decisions compared are rejections; accepted learned moves are compared
+    with the oracle at 4x4 in test_gpu_learned.py.)"""
+    from oracle import net as onet
+    from oracle import rtt as orc
+    from helpers import device_cores
+    name = "tfim16x16_R2_chi256_W16384_T4"
+    print(f"[case] {name} learned step", flush=True)
+    w = wl.WORKLOADS[name]
+    g = sampled_refs(name, "fp8")
+    ids = g["walkers"]
+    psi = make_state(R, w, "fp8")
+    pi, bond = w.pi(), wl.open_bonds(w.L, w.chi)
+    qts = device_cores(psi, bond, n_terms=w.n_terms)
+    params = onet.init_params(31) + 0.3 * np.random.default_rng(31).standard_normal(onet.N_PARAMS)
+    net = R.Net(w.Lx, w.Ly, params)
+    p16 = net.params(1)
+    words = wl.pack_spins(w.spins())
+    words[ids] = g["sampled"]
+    spins = R.spins_to_device(words)
+    ch = R.LearnedChain(psi, net, spins, seed=41, rng_stream=5)
+    ch.learned_step()
+    torch.cuda.synchronize()
+    got_moves = ch.moves.cpu().numpy()[ids]
+    got = wl.unpack_spins(R.spins_to_host(ch.spins)[ids], w.N)
+    bits = wl.unpack_spins(g["sampled"], w.N)
+    amp = lambda S: orc.lincomb_amplitudes(qts, w.coeffs(), pi, S)
+    ref, ref_moves, a, acc, margin = onet.mh_step(p16, amp, bits, w.Lx, w.Ly, seed=41, stream=5, step=0,
+                                                  walker_ids=ids)
+    o = onet.forward(p16, bits, w.Lx, w.Ly)
+    clean = np.abs(margin) > 1e-2
+    for b, wid in enumerate(ids):
+        c, k = ref_moves[b]
+        pc = np.cumsum(np.exp(onet.log_softmax(o[b, 0], 0)))
+        pk = np.cumsum(np.exp(onet.log_softmax(o[b, 1:9, c], 0)))
+        if (np.min(np.abs(pc - onet.uniform(41, 5, wid, 0, 0))) < 1e-5
+                or np.min(np.abs(pk - onet.uniform(41, 5, wid, 0, 1))) < 1e-5):
+            clean[b] = False
+    print(f"  moves {[tuple(m) for m in ref_moves]}, acceptance {np.round(a, 4)}, margins {np.round(margin, 4)}, "
+          f"clean {clean}", flush=True)
+    assert clean.sum() >= len(ids) // 2
+    for b in np.where(clean)[0]:
+        c, k = ref_moves[b]
+        assert got_moves[b] == (c | (k << 16)), b
+    assert np.array_equal(got[clean], ref[clean])
+    net.close()
+    psi.close()
