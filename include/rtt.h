@@ -388,7 +388,9 @@ rtt_status rtt_batch_destroy(rtt_batch_t b);
  * params (host double[19113]): W1[32][1][3][3], b1[32], W2[32][32][3][3], b2,
  * W3[32][32][3][3], b3, Wh[9][32], bh[9], row-major, concatenated.  The
  * library keeps FP32 master weights and uses them rounded to BF16 (FP32
- * accumulation) in every forward pass.
+ * accumulation) in every forward pass; in the proposal and forward kernels
+ * the two 32-channel layers run on the BF16 matrix cores with each
+ * activation split into three BF16 parts, which keeps FP32 accuracy.
  * A move samples a centre c ~ softmax(o[0]) and k ~ softmax(o[1..8][c]) and
  * flips the first k sites of the spiral (dx,dy) = (0,0),(1,0),(1,1),(0,1),
  * (-1,1),(-1,0),(-1,-1),(0,-1) around c.  It is accepted iff
