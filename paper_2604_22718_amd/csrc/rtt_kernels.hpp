@@ -233,9 +233,9 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int bx, int ty) {
   // A ring of PFP fragment sets: loads run PFP - 1 items ahead of the
   // matrix ops, issued on every path (clamped to the last item) so that the
   // wait before the matrix ops never covers an item still being prefetched.
-  // FP8 sets are half the registers of BF16 ones, which pays for a third
-  // set at bond 256, where one wave per SIMD leaves the fragment
-  // latency exposed.
+  // Two sets everywhere: a third (the FP8 sets are half the registers of
+  // BF16 ones) measured slower at bond 256, and at bond 128 it costs the
+  // kernel its second wave per SIMD.
   constexpr int PFP = (kDec && CHI == 256) ? PASS_PF_FP8 : 2;
   Frags FR[PFP];
   if (n_items > 0) {
@@ -458,8 +458,9 @@ struct ChainLayout {
 // register file) with two waves per side.
 template <int CHI, class D = DBF16>
 struct ChainGeo {
-  // waves per side: FP8 fragments are half the registers, which lets the
-  // bond-256 kernel run four waves per side (two per SIMD, CHAIN_SW_FP8_256)
+  // waves per side: FP8 fragments are half the registers of BF16 ones, but
+  // four waves per side at bond 256 (two per SIMD) still spill, so
+  // CHAIN_SW_FP8_256 keeps two
   static constexpr int SW = (CHI == 256 && std::is_same<D, DFP8>::value) ? CHAIN_SW_FP8_256
                             : CHI >= 128 ? 2 : Geo<CHI>::WPW;
   static constexpr int MT = CHI / (16 * SW);                   // output tiles per wave
@@ -478,8 +479,10 @@ struct ChainGeo {
 // from the right boundary (backward layout); the two meet half way and are
 // joined by an FP64 dot product.  The number of dependent steps per
 // amplitude is halved and each SIMD runs two independent chains.  CKP
-// compiles the column checkpoints in (bonds up to 64: wider bonds leave LDS
-// for too few of them, and their register-bound kernels stay as they are).
+// compiles the column checkpoints in: kept in LDS at bonds up to 64 (wider
+// bonds leave LDS for too few of them), and with CKG in global memory for
+// the term-sequential layout of FP8 cores at bond 256 (other bond-128 and
+// bond-256 kernels are register-bound and stay without them).
 template <class D, int CHI, int CG, bool CKP = false, bool CKG = false>
 __device__ __forceinline__ void chain_body(const ChainArgs& a, int bx, uint64_t sweep0) {
   using E = typename D::elem;
