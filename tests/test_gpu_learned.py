@@ -82,11 +82,13 @@ def test_adam_step_matches_oracle(R):
     assert np.all(np.abs(got - master0) <= 1e-3 * (1 + 1e-5))
 
 
-def test_learned_step_matches_oracle(R):
+@pytest.mark.parametrize("Lx,Ly", [(4, 4), (5, 3), (10, 10)])
+def test_learned_step_matches_oracle(R, Lx, Ly):
     """Same seeds: GPU and oracle propose the same moves and make the same
-    accept decisions, except where a uniform falls within 1e-5 of a cut."""
-    Lx, Ly, Rr, chi, W = 4, 4, 2, 8, 48
-    N = 16
+    accept decisions, except where a uniform falls within 1e-5 of a cut.
+    At 10x10 the centre draw's prefix sums run across two waves."""
+    Rr, chi, W = 2, 8, 48
+    N = Lx * Ly
     pi = wl.path_site_plus_perms(N, Rr, 12)
     bond = wl.open_bonds(N * Rr, chi)
     cores = wl.gaussian_cores(bond, 13)
