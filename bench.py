@@ -606,17 +606,34 @@ def sampled_energy_error(R, psi, ham, name, dtype):
     if g is None:
         return None
     spins = R.spins_to_device(g["sampled"])
-    e = psi.local_energy(spins, ham)
+    out = psi.evaluate(spins, ham)
     torch.cuda.synchronize()
-    e = e.cpu().numpy()
+    e = out["eloc"].cpu().numpy()
     q, u = np.array(g["eloc_quantised_cores"]), np.array(g["eloc_fp64_cores"])
     rq = np.abs(e - q) / np.maximum(1.0, np.abs(q))
     ru = np.abs(e - u) / np.maximum(1.0, np.abs(u))
+    # every flip ratio of those configurations against the oracle's FP64
+    # ratios: the stated bar unscaled, and how far each ratio is inside
+    # its condition-number-scaled bound tol * max(1, kappa / 10)
+    r_ref = np.asarray(g["flip_ratios"], dtype=np.float64)
+    kap = np.asarray(g["flip_kappa"], dtype=np.float64)
+    lr = out["logratio"].cpu().numpy()
+    nz = r_ref != 0
+    dlog = np.abs(lr[nz] - np.log(np.abs(r_ref[nz])))
+    tol = 1e-5 if dtype == "f32" else 2e-2
+    allow = tol * np.maximum(1.0, kap[nz] / 10.0)
+    ratios = {"n": int(nz.sum()), "tol": tol, "frac_within_tol": float(np.mean(dlog <= tol)),
+              "p999": float(np.quantile(dlog, 0.999)), "max": float(dlog.max()),
+              "n_well_conditioned": int(np.sum(kap[nz] <= 10.0)),
+              "n_held_to_scaled_bound_only": int(np.sum(kap[nz] > 10.0)),
+              "worst_ratio_to_scaled_bound": float(np.max(dlog / allow)),
+              "sign_errors": int(np.sum(np.sign(r_ref[nz]) != out["rsign"].cpu().numpy()[nz]))}
     return {"walkers": len(e), "configurations": f"oracle Metropolis chain, {g['burn']} sweeps from the seeded walkers",
             "max_rel_vs_fp64_same_cores": float(rq.max()), "median_rel_vs_fp64_same_cores": float(np.median(rq)),
             "mean_diff_vs_fp64_same_cores": float(np.mean(e - q)),
             "max_rel_vs_fp64_unquantised_cores": float(ru.max()),
             "mean_diff_vs_fp64_unquantised_cores": float(np.mean(e - u)),
+            "flip_ratios_vs_fp64_same_cores": ratios,
             "reference": "tests/golden/sampled_refs.json"}
 
 
