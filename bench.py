@@ -894,21 +894,30 @@ def cpu_baseline(n_props=16, n_ratios=64):
     terms = [quant.quantise_cores(w.cores(t), w.dtype) for t in range(w.n_terms)]
     g = golden(w.name, w.dtype)
     s = wl.unpack_spins(g["sampled"][:1], w.N) if g is not None else w.spins(1)
-    with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
-        for j in range(n_props):
-            orc.lincomb_amplitudes(terms, c, pi, s)
-            orc.lincomb_amplitudes(terms, c, pi, orc.flip(s, j))
-        t_props = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        orc.lincomb_flip_ratios(terms, c, pi, s, which=list(range(n_ratios)))
-        t_ratios = time.perf_counter() - t0
-    step_s = t_props * w.N / n_props + t_ratios * w.N / n_ratios
+    def timed(threads, n_p, n_r):
+        with threadpool_limits(limits=threads):
+            t0 = time.perf_counter()
+            for j in range(n_p):
+                orc.lincomb_amplitudes(terms, c, pi, s)
+                orc.lincomb_amplitudes(terms, c, pi, orc.flip(s, j))
+            t_p = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            orc.lincomb_flip_ratios(terms, c, pi, s, which=list(range(n_r)))
+            t_r = time.perf_counter() - t0
+        return t_p, t_r, t_p * w.N / n_p + t_r * w.N / n_r
+
+    t_props, t_ratios, step_s = timed(1, n_props, n_ratios)
+    ncpu = len(os.sched_getaffinity(0))
+    # the same with BLAS threads on every host core, on a quarter of the sample
+    a_p, a_r, a_step = timed(ncpu, max(1, n_props // 4), max(1, n_ratios // 4))
     return {"value": 1.0 / step_s, "unit": "local-energy evals/s", "cores": 1, "kind": "oracle",
             "sample": f"1 walker of the {w.name} workload (FP8-quantised cores, FP64 numpy): {n_props} Metropolis "
                       f"proposals ({t_props:.1f} s) and {n_ratios} of the {w.N} flip ratios of a local energy "
                       f"({t_ratios:.1f} s), scaled to one sweep + local energy = {step_s:.0f} s per walker-step",
-            "host_cpus_available": len(os.sched_getaffinity(0))}
+            "host_cpus_available": ncpu,
+            "all_cores": {"value": 1.0 / a_step, "unit": "local-energy evals/s", "cores": ncpu, "kind": "oracle",
+                          "sample": f"{max(1, n_props // 4)} proposals ({a_p:.1f} s) and {max(1, n_ratios // 4)} "
+                                    f"ratios ({a_r:.1f} s) of the same walker, BLAS threads = {ncpu}"}}
 
 
 def cpu_baseline_8x8(n_walkers=64, n_steps=6):
