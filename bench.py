@@ -756,9 +756,14 @@ def headline(steps, warmup, burn, learned_per_step=2, lr=1e-3):
     roof = {"kernel": nm, "bound": "mfma", "achieved": ach / 1e12, "peak": PEAK[dtype] / 1e12,
             "unit": "TFLOP/s", "frac": ach / PEAK[dtype],
             "traffic": traffic_from_profile(nm, w.name),
+            "traffic_note": "bytes fetched past L2 (MALL hits included) and written, per launch, from the committed "
+                            "counter summary of the same kernel sources",
             "flop_count": "method minimum: L + sum_j (last_j - first_j + 1) row-steps per walker-sweep and "
                           "term, 2 chi^2 flops each (the hi+lo BF16 activation split and both core slices, "
                           "which the matrix ops also execute, are not counted)"}
+    if roof["traffic"] is not None:   # the rate those bytes imply at the measured launch time
+        t_ms = sweep_ms.mean() if nm == "chain_kernel" else eval_ms.mean()
+        roof["traffic_TB_per_s"] = roof["traffic"] / (t_ms * 1e-3) / 1e12
     ess = W * steps / st["tau_int"]
     n_fl = (ch.sweeps - sweeps0) * W * w.N
     n_le = (ch.steps - steps0) * W
