@@ -16,6 +16,12 @@ Modules
   stats   exactly rounded means, integrated autocorrelation time, V-score
   tt      TT-SVD, direct-sum trains, MPS transfer-matrix expectation values
   quant   BF16 / FP8-e4m3 core quantisation via torch CPU casts
+  net     the learned proposal: network, move sampling, exact set
+          probabilities, REINFORCE gradient, Adam, the learned MH step
+  dual    dual Monte Carlo estimators and the generalised eigenproblem
+  paths   the H+V+D+D' path, replica operators, Pauli strings as Kronecker
+          products
+  replica replica-space operators on trains, rounding, the power method
 
 Every function states the passage of the paper it follows.  None is
 "parity unpinned": each is pinned by tests under ``tests/test_oracle_*.py``.
