@@ -42,6 +42,22 @@ def test_eight_by_eight_workload_count():
     assert bench.sweep_rowsteps(pi, w.N, len(pi)) == 4288
 
 
+def test_baseline_sweep_count_closed_form():
+    """A sweep whose flipped rows run from each spin's first position to the
+    end of the train, one prefix step per proposal: with the first replica
+    in site order, first(j) = j, so sum_j (L - j) + N = N L - N(N-1)/2 + N
+    whatever the later replicas (6240, 25150 and 98688 row-steps per walker
+    and term on the 8x8, 10x10 R = 3 and 16x16 workloads)."""
+    for name, want in (("tfim8x8_R2_chi64_W4096", 6240), ("tfim10x10_R3_chi128_W8192", 25150),
+                       ("tfim16x16_R2_chi256_W16384_T4", 98688)):
+        w = wl.WORKLOADS[name]
+        pi = w.pi()
+        N, L = w.N, len(pi)
+        assert bench.baseline_sweep_rowsteps(pi, N, L) == N * L - N * (N - 1) // 2 + N == want
+    pi = np.array([2, 0, 2, 1, 0])                   # spin 3 unread: first = {2: 0, 0: 1, 1: 3}
+    assert bench.baseline_sweep_rowsteps(pi, 4, 5) == (5 - 0) + (5 - 1) + (5 - 3) + 3
+
+
 def test_bench_statistics_on_known_series():
     """tau_int of an AR(1) series of many walkers against (1 + rho)/(1 - rho),
     a constant series (tau 1, sigma 0), and the V-score / sigma formulas of
