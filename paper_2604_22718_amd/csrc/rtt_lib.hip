@@ -179,11 +179,17 @@ Sched build_sched(const std::vector<int>& pi, int N, int L, int c, int ng) {
 
 int rttk_wpw(int chi) { return chi >= 64 ? 4 : chi / 16; }
 
-size_t pass_lds_bytes(int chi, int nslot, int nw) {
+// the bond-256 FP8 pass runs the K-outer form (rows in place when so built,
+// and at most kPassWideTiles row tiles per walker)
+bool pass_wide(int dtype, int chi) { return PASS_W_ENABLE && dtype == RTT_FP8_E4M3 && chi == 256; }
+int pass_max_slots(int dtype, int chi) { return pass_wide(dtype, chi) ? 16 * rttk::kPassWideTiles : 1 << 30; }
+
+size_t pass_lds_bytes(int chi, int nslot, int nw, int dtype) {
   const int wpw = chi >= 64 ? 4 : chi / 16;
   const int wpb = 4 / wpw;
   const size_t rs = chi + 4;
-  return (size_t)wpb * (2 * nslot * rs * 4 + 2 * nslot * 4 + nw * 8);
+  const int nb = (pass_wide(dtype, chi) && rttk::kPassWideInPlace) ? 1 : 2;  // row buffers
+  return (size_t)wpb * (nb * nslot * rs * 4 + nb * nslot * 4 + nw * 8);
 }
 
 size_t chain_lds_bytes(int chi, int T, int L, int nw, int n_spins, int cg = 1) {
@@ -421,8 +427,8 @@ rtt_status finish_create(rtt_s* h) {
     if (first_ng && ng > first_ng + 3) break;
     for (int c = 0; c <= h->L; ++c) {
       Sched s = build_sched(h->pi, h->N, h->L, c, ng);
-      const size_t lds = pass_lds_bytes(h->chi, s.nslot, h->nw);
-      if (lds > kLdsLimit) continue;
+      const size_t lds = pass_lds_bytes(h->chi, s.nslot, h->nw, h->dtype);
+      if (lds > kLdsLimit || s.nslot > pass_max_slots(h->dtype, h->chi)) continue;
       if (!first_ng) first_ng = ng;
       const int occ = std::min<int>(occ_cap, (int)(kLdsLimit / lds));
       const double score = (double)s.cost / occ;
@@ -504,7 +510,7 @@ template <class D, int CHI>
 rtt_status launch_pass(const rttk::PassArgs& a, int T, hipStream_t s) {
   constexpr int WPW = rttk::Geo<CHI>::WPW;
   constexpr int WPB = 4 / WPW;
-  const size_t lds = pass_lds_bytes(CHI, a.nslot, a.nw);
+  const size_t lds = pass_lds_bytes(CHI, a.nslot, a.nw, rttk::pass_wide_form<D, CHI>() ? RTT_FP8_E4M3 : -1);
   auto kfn = rttk::pass_kernel<D, CHI>;
   HIPX(hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   dim3 grid((a.W + WPB - 1) / WPB, T);
@@ -1721,7 +1727,7 @@ static rtt_status rtt_batch_create_impl(int32_t n, const rtt_t* rtts, const rtt_
       pa.cores = h->d_bwd; pa.sched = h->d_sb; pa.gsteps = h->d_bgs;
       pa.out_vec = ws_v(i); pa.out_exp = ws_ve(i);
       c.pass.push_back(pa);
-      c.pass_lds = std::max(c.pass_lds, pass_lds_bytes(c.chi, h->sched.nslot, h->nw));
+      c.pass_lds = std::max(c.pass_lds, pass_lds_bytes(c.chi, h->sched.nslot, h->nw, h->dtype));
       // sweep cost ~ (L + sum_j (L - first_j)) row-steps per walker tile
       double sweep_rows = h->L;
       for (int j = 0; j < h->N; ++j) if (h->first[j] >= 0) sweep_rows += h->L - h->first[j];

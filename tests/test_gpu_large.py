@@ -42,6 +42,31 @@ def test_row_groups_match_oracle(R):
     assert np.all(out["sign"] == sg) and np.max(np.abs(out["logabs"] - la)) < 2e-2
 
 
+@pytest.mark.parametrize("N,W,seed", [(16, 8, 70), (100, 4, 60), (160, 1, 64)])
+def test_fp8_bond256_row_tiles_match_oracle(R, N, W, seed):
+    """FP8 at bond 256 (the K-outer pass with rows updated in place): a
+    second row tile that first appears on the last two steps (N = 16), row
+    groups (N = 100), and six row tiles per group, more rows than two
+    buffers would hold (N = 160)."""
+    print(f"[case] fp8 bond 256 N={N} W={W}", flush=True)
+    pi, bond, cores = case(N, 2, 256, "perm", seed=seed)
+    psi = R.RTT.create(N, pi, cores, "fp8")
+    qc = device_cores(psi, bond)
+    bits = wl.random_spins(W, N, seed + 1)
+    out = psi.evaluate(R.spins_to_device(wl.pack_spins(bits)))
+    torch.cuda.synchronize()
+    out = {k: v.cpu().numpy() for k, v in out.items()}
+    r_ref = orc.flip_ratios(qc, pi, bits)
+    kap = orc.flip_condition_numbers(qc, pi, bits)
+    st = check_ratios(out["logratio"], out["rsign"], r_ref, kap, HILO_TOL, min_well=0)
+    print(psi.info, st)
+    if N == 160:
+        assert psi.info["nslot"] > 64
+    assert st["n_bad"] == 0 and st["n_sign_bad"] == 0
+    la, sg = orc.log_sign(orc.amplitudes(qc, pi, bits))
+    assert np.all(out["sign"] == sg) and np.max(np.abs(out["logabs"] - la)) < 1e-3
+
+
 def test_row_groups_fp32_many_spins(R):
     """FP32, chi = 128, N = 144: groups also in the FP32 path."""
     N, Rr, chi, W = 144, 2, 128, 2
