@@ -76,14 +76,25 @@ struct PassArgs {
 // With PASS_W_INPL rows are updated in place: the step's outputs wait in
 // registers until every wave has read its inputs, so a walker's rows take
 // half the LDS and twice as many fit (fewer row groups, fewer core reads).
-#ifndef PASS_W_NTM
-#define PASS_W_NTM 6
+// Tuning on the 16x16 four-term workload (local energies, 16384 walkers):
+// the double-buffered item form 2.75 s; K outermost, two buffers 2.59 s; in
+// place with 6 row tiles 2.22 s; with 9 (two row groups instead of three)
+// and the two-slot ring below 2.06 s; with the chunk's activations read
+// ahead 2.05 s.  Nine tiles with a four-slot ring spill.
+#ifndef PASS_W_NTM  // row tiles a group may hold
+#define PASS_W_NTM 9
 #endif
 #ifndef PASS_W_INPL
 #define PASS_W_INPL 1
 #endif
 #ifndef PASS_W_ENABLE  // 0: the bond-256 FP8 pass runs pass_body's item form
 #define PASS_W_ENABLE 1
+#endif
+#ifndef PASS_W_BPRE  // 2: read every tile's chunk first (inactive tiles re-read the last active one)
+#define PASS_W_BPRE 2
+#endif
+#ifndef PASS_W_RING  // fragment ring slots: 4 = one step ahead, 2 = half a step
+#define PASS_W_RING 2
 #endif
 constexpr int kPassWideTiles = PASS_W_NTM;        // row tiles a step may hold
 constexpr bool kPassWideInPlace = PASS_W_INPL != 0;
@@ -121,23 +132,28 @@ __device__ __forceinline__ void pass_body_wide(const PassArgs& a, int bx, int ty
   const int4* sched = a.sched + gs.x;
   const int n = gs.y;
 
-  // Ring of fragment codes: slot j holds the 16-byte chunk j (codes 16j ..
+  // Ring of fragment codes: a slot holds one 16-byte chunk j (codes 16j ..
   // 16j + 15 of each lane) of this wave's four tiles, of the walker's slice
-  // (Rm) and, on steps with an odd row, of the other slice (Ro).  A slot is
-  // refilled with the next step's chunk as soon as both of its K chunks are
-  // decoded, so every load has about one step to arrive.
-  uint4 Rm[4][MT], Ro[4][MT];
+  // (Rm) and, on steps with an odd row, of the other slice (Ro).  A step
+  // streams its chunks 0..3 through the RING slots; a slot is refilled with
+  // the chunk RING places further on (in this step or the next) as soon as
+  // both of its K chunks are decoded, so every load has RING / 4 of a step
+  // to arrive.
+  constexpr int RING = PASS_W_RING;
+  uint4 Rm[RING][MT], Ro[RING][MT];
   constexpr int TILE16 = 64 * KPL / 16;  // 16-byte words per fragment tile
+  // load chunk j of a step's fragments into ring slot j % RING
   auto issue = [&](int j, const int4& st, int bit) {
+    const int sl = j % RING;
     const uint4* bm = reinterpret_cast<const uint4*>(cores + ((size_t)st.x * 2 + bit) * (CHI * CHI)) +
                       (size_t)wv * MT * TILE16;
 #pragma unroll
-    for (int q = 0; q < MT; ++q) Rm[j][q] = bm[q * TILE16 + 64 * j + lane];
+    for (int q = 0; q < MT; ++q) Rm[sl][q] = bm[q * TILE16 + 64 * j + lane];
     if (st.w >= 0) {
       const uint4* bo = reinterpret_cast<const uint4*>(cores + ((size_t)st.x * 2 + (bit ^ 1)) * (CHI * CHI)) +
                         (size_t)wv * MT * TILE16;
 #pragma unroll
-      for (int q = 0; q < MT; ++q) Ro[j][q] = bo[q * TILE16 + 64 * j + lane];
+      for (int q = 0; q < MT; ++q) Ro[sl][q] = bo[q * TILE16 + 64 * j + lane];
     }
   };
   // codes 8c .. 8c + 7 of a lane (half h = c & 1 of its chunk) as BF16 values
@@ -154,7 +170,7 @@ __device__ __forceinline__ void pass_body_wide(const PassArgs& a, int bx, int ty
     const int4 st0 = sched[0];
     const int bit0 = spin_bit(spw, st0.y);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) issue(j, st0, bit0);
+    for (int j = 0; j < RING; ++j) issue(j, st0, bit0);
   }
   for (int s = 0; s < n; ++s) {
     const int4 st = sched[s];
@@ -165,7 +181,7 @@ __device__ __forceinline__ void pass_body_wide(const PassArgs& a, int bx, int ty
     // renormalise every kRenormEvery steps (a row grows by at most chi per step)
     const bool rn = (s % kRenormEvery) == 0;
     const int4 stn = sched[min(s + 1, n - 1)];
-    const int bitn = spin_bit(spw, stn.y);
+    const int bitc = spin_bit(spw, st.y), bitn = spin_bit(spw, stn.y);
     f4 acc[NTM][MT], oacc[MT];
 #pragma unroll
     for (int r = 0; r < NTM; ++r) {
@@ -176,21 +192,50 @@ __device__ __forceinline__ void pass_body_wide(const PassArgs& a, int bx, int ty
     for (int q = 0; q < MT; ++q) oacc[q] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int c = 0; c < KPL / 8; ++c) {
-      const int j = c >> 1, h = c & 1;
+      const int j = c >> 1, h = c & 1, sl = j % RING;
       bf16x8 Am[MT], Ao[MT];
 #pragma unroll
-      for (int q = 0; q < MT; ++q) Am[q] = dec(Rm[j][q], h);
+      for (int q = 0; q < MT; ++q) Am[q] = dec(Rm[sl][q], h);
       if (ot >= 0) {
 #pragma unroll
-        for (int q = 0; q < MT; ++q) Ao[q] = dec(Ro[j][q], h);
+        for (int q = 0; q < MT; ++q) Ao[q] = dec(Ro[sl][q], h);
       }
-      if (h == 1) issue(j, stn, bitn);
+      // the slot is free: refill it with the chunk RING places further on
+      if (h == 1) {
+        if (j + RING < 4) issue(j + RING, st, bitc);
+        else issue(j + RING - 4, stn, bitn);
+      }
+#if PASS_W_BPRE
+      // this chunk's activations of every row tile, read before its matrix
+      // ops so that the LDS latency of one tile hides behind another (with
+      // PASS_W_BPRE 2 unconditionally: tiles past the active ones re-read the
+      // last active tile, which keeps the reads out of branches)
+      bf16x8 BH[NTM], BL[NTM];
+#pragma unroll
+      for (int r = 0; r < NTM; ++r) {
+#if PASS_W_BPRE == 2
+        const int rr = min(r, ntile - 1);
+#else
+        const int rr = r;
+        if (r < ntile)
+#endif
+        {
+          const uint16_t* hp = A::hi(cur + (16 * rr + m) * RS) + g * KPL + 8 * c;
+          BH[r] = *reinterpret_cast<const bf16x8*>(hp);
+          BL[r] = *reinterpret_cast<const bf16x8*>(hp + CHI);
+        }
+      }
+#endif
 #pragma unroll
       for (int r = 0; r < NTM; ++r) {
         if (r < ntile) {
+#if PASS_W_BPRE
+          const bf16x8 bh = BH[r], bl = BL[r];
+#else
           const uint16_t* hp = A::hi(cur + (16 * r + m) * RS) + g * KPL + 8 * c;
           const bf16x8 bh = *reinterpret_cast<const bf16x8*>(hp);
           const bf16x8 bl = *reinterpret_cast<const bf16x8*>(hp + CHI);
+#endif
 #pragma unroll
           for (int q = 0; q < MT; ++q) {
             acc[r][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Am[q], bh, acc[r][q], 0, 0, 0);
@@ -240,8 +285,10 @@ __device__ __forceinline__ void pass_body_wide(const PassArgs& a, int bx, int ty
 #pragma unroll
         for (int q = 0; q < MT; ++q) {
           f4 v = acc[r][q];
+          if (rn) {  // the scale is 1 on other steps
 #pragma unroll
-          for (int i = 0; i < 4; ++i) v[i] *= sc;
+            for (int i = 0; i < 4; ++i) v[i] *= sc;
+          }
           A::store4(nxt + (16 * r + m) * RS, 16 * (wv * MT + q) + 4 * g, v);
         }
         if (wv == 0 && g == 0) exn[16 * r + m] = eold[r] + e[r] + cexp;
