@@ -79,8 +79,8 @@ struct PassArgs {
 // Tuning on the 16x16 four-term workload (local energies, 16384 walkers):
 // the double-buffered item form 2.75 s; K outermost, two buffers 2.59 s; in
 // place with 6 row tiles 2.22 s; with 9 (two row groups instead of three)
-// and the two-slot ring below 2.06 s; with the chunk's activations read
-// ahead 2.05 s.  Nine tiles with a four-slot ring spill.
+// and the two-slot ring below 2.06 s; with each step compiled for its exact
+// row-tile count (no per-tile branches) 1.61 s.  A four-slot ring spills.
 #ifndef PASS_W_NTM  // row tiles a group may hold
 #define PASS_W_NTM 9
 #endif
@@ -89,9 +89,6 @@ struct PassArgs {
 #endif
 #ifndef PASS_W_ENABLE  // 0: the bond-256 FP8 pass runs pass_body's item form
 #define PASS_W_ENABLE 1
-#endif
-#ifndef PASS_W_BPRE  // 2: read every tile's chunk first (inactive tiles re-read the last active one)
-#define PASS_W_BPRE 2
 #endif
 #ifndef PASS_W_RING  // fragment ring slots: 4 = one step ahead, 2 = half a step
 #define PASS_W_RING 2
@@ -104,6 +101,7 @@ constexpr bool pass_wide_form() { return PASS_W_ENABLE && std::is_same<D, DFP8>:
 
 __device__ __forceinline__ void pass_body_wide(const PassArgs& a, int bx, int ty) {
   constexpr int CHI = 256, KPL = 64, MT = 4, RS = CHI + 4, NTM = kPassWideTiles;
+  static_assert(NTM >= 1 && NTM <= 9, "the step dispatch covers 1 to 9 row tiles");
   constexpr bool INPL = kPassWideInPlace;
   constexpr int NB = INPL ? 1 : 2;  // row buffers
   using A = Act<DFP8, CHI>;
@@ -182,105 +180,92 @@ __device__ __forceinline__ void pass_body_wide(const PassArgs& a, int bx, int ty
     const bool rn = (s % kRenormEvery) == 0;
     const int4 stn = sched[min(s + 1, n - 1)];
     const int bitc = spin_bit(spw, st.y), bitn = spin_bit(spw, stn.y);
-    f4 acc[NTM][MT], oacc[MT];
+    const int cexp = cexp_p ? cexp_p[k] : 0;
+    const float* orow = cur + (16 * (ot < 0 ? 0 : ot) + m) * RS;  // the odd row's input tile
+    // One step over exactly NT row tiles (dispatched below on the step's
+    // tile count): no branch per tile, so the compiler is free to issue a
+    // chunk's reads ahead of the matrix ops, and no accumulator of an idle
+    // tile is carried through the K loop.
+    auto step = [&](auto ntc) {
+      constexpr int NT = decltype(ntc)::value;
+      f4 acc[NT][MT], oacc[MT];
 #pragma unroll
-    for (int r = 0; r < NTM; ++r) {
+      for (int r = 0; r < NT; ++r) {
 #pragma unroll
-      for (int q = 0; q < MT; ++q) acc[r][q] = f4{0.f, 0.f, 0.f, 0.f};
-    }
-#pragma unroll
-    for (int q = 0; q < MT; ++q) oacc[q] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int c = 0; c < KPL / 8; ++c) {
-      const int j = c >> 1, h = c & 1, sl = j % RING;
-      bf16x8 Am[MT], Ao[MT];
-#pragma unroll
-      for (int q = 0; q < MT; ++q) Am[q] = dec(Rm[sl][q], h);
-      if (ot >= 0) {
-#pragma unroll
-        for (int q = 0; q < MT; ++q) Ao[q] = dec(Ro[sl][q], h);
+        for (int q = 0; q < MT; ++q) acc[r][q] = f4{0.f, 0.f, 0.f, 0.f};
       }
-      // the slot is free: refill it with the chunk RING places further on
-      if (h == 1) {
-        if (j + RING < 4) issue(j + RING, st, bitc);
-        else issue(j + RING - 4, stn, bitn);
-      }
-#if PASS_W_BPRE
-      // this chunk's activations of every row tile, read before its matrix
-      // ops so that the LDS latency of one tile hides behind another (with
-      // PASS_W_BPRE 2 unconditionally: tiles past the active ones re-read the
-      // last active tile, which keeps the reads out of branches)
-      bf16x8 BH[NTM], BL[NTM];
 #pragma unroll
-      for (int r = 0; r < NTM; ++r) {
-#if PASS_W_BPRE == 2
-        const int rr = min(r, ntile - 1);
-#else
-        const int rr = r;
-        if (r < ntile)
-#endif
-        {
-          const uint16_t* hp = A::hi(cur + (16 * rr + m) * RS) + g * KPL + 8 * c;
-          BH[r] = *reinterpret_cast<const bf16x8*>(hp);
-          BL[r] = *reinterpret_cast<const bf16x8*>(hp + CHI);
+      for (int q = 0; q < MT; ++q) oacc[q] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int c = 0; c < KPL / 8; ++c) {
+        const int j = c >> 1, h = c & 1, sl = j % RING;
+        bf16x8 Am[MT];
+#pragma unroll
+        for (int q = 0; q < MT; ++q) Am[q] = dec(Rm[sl][q], h);
+        // the odd row: the other slice applied to its input row (the same
+        // LDS values its tile reads above)
+        if (ot >= 0) {
+          bf16x8 Ao[MT];
+#pragma unroll
+          for (int q = 0; q < MT; ++q) Ao[q] = dec(Ro[sl][q], h);
+          const uint16_t* hp = A::hi(orow) + g * KPL + 8 * c;
+          const bf16x8 bh = *reinterpret_cast<const bf16x8*>(hp);
+          const bf16x8 bl = *reinterpret_cast<const bf16x8*>(hp + CHI);
+#pragma unroll
+          for (int q = 0; q < MT; ++q) {
+            oacc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ao[q], bh, oacc[q], 0, 0, 0);
+            oacc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ao[q], bl, oacc[q], 0, 0, 0);
+          }
         }
-      }
-#endif
+        // the slot is free: refill it with the chunk RING places further on
+        if (h == 1) {
+          if (j + RING < 4) issue(j + RING, st, bitc);
+          else issue(j + RING - 4, stn, bitn);
+        }
 #pragma unroll
-      for (int r = 0; r < NTM; ++r) {
-        if (r < ntile) {
-#if PASS_W_BPRE
-          const bf16x8 bh = BH[r], bl = BL[r];
-#else
+        for (int r = 0; r < NT; ++r) {
           const uint16_t* hp = A::hi(cur + (16 * r + m) * RS) + g * KPL + 8 * c;
           const bf16x8 bh = *reinterpret_cast<const bf16x8*>(hp);
           const bf16x8 bl = *reinterpret_cast<const bf16x8*>(hp + CHI);
-#endif
 #pragma unroll
           for (int q = 0; q < MT; ++q) {
             acc[r][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Am[q], bh, acc[r][q], 0, 0, 0);
             acc[r][q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Am[q], bl, acc[r][q], 0, 0, 0);
           }
-          if (r == ot) {
-#pragma unroll
-            for (int q = 0; q < MT; ++q) {
-              oacc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ao[q], bh, oacc[q], 0, 0, 0);
-              oacc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ao[q], bl, oacc[q], 0, 0, 0);
-            }
-          }
         }
       }
-    }
-    // per-row exponents on renormalisation steps, from a second read of the
-    // rows' hi parts exactly as in pass_body (a running maximum carried over
-    // the K chunks instead gave wrong values in row tiles after the first;
-    // its cause was not identified, so that form is not used)
-    int e[NTM];
-    int oe = 0;
+      // per-row exponents on renormalisation steps, from a second read of
+      // the rows' hi parts exactly as in pass_body (a running maximum carried
+      // over the K chunks instead gave wrong values in row tiles after the
+      // first; its cause was not identified, so that form is not used)
+      int e[NT];
+      int oe = 0;
 #pragma unroll
-    for (int r = 0; r < NTM; ++r) {
-      e[r] = 0;
-      if (rn && r < ntile) {
-        DBF16::BOp<KPL> bo;
-        A::template load_b<KPL>(cur + (16 * r + m) * RS, g, bo);
-        e[r] = A::template row_exp<KPL>(bo);
+      for (int r = 0; r < NT; ++r) {
+        e[r] = 0;
+        if (rn) {
+          DBF16::BOp<KPL> bo;
+          A::template load_b<KPL>(cur + (16 * r + m) * RS, g, bo);
+          e[r] = A::template row_exp<KPL>(bo);
+        }
       }
-      if (r == ot) oe = e[r];
-    }
-    const int cexp = cexp_p ? cexp_p[k] : 0;
-    // exponents are read and written by wave 0 alone (program order); rows
-    // are read by every wave, so in place they wait for the barrier
-    int eold[NTM];
-    int eoin = 0;
-    if (wv == 0) {
+      if (rn && ot >= 0) {  // the exponent of the odd row's input row
+        DBF16::BOp<KPL> bo;
+        A::template load_b<KPL>(orow, g, bo);
+        oe = A::template row_exp<KPL>(bo);
+      }
+      // exponents are read and written by wave 0 alone (program order); rows
+      // are read by every wave, so in place they wait for the barrier
+      int eold[NT];
+      int eoin = 0;
+      if (wv == 0) {
 #pragma unroll
-      for (int r = 0; r < NTM; ++r) eold[r] = r < ntile ? exc[16 * r + m] : 0;
-      if (oin >= 0) eoin = exc[oin];
-    }
-    if (INPL) lds_barrier();
+        for (int r = 0; r < NT; ++r) eold[r] = exc[16 * r + m];
+        if (oin >= 0) eoin = exc[oin];
+      }
+      if (INPL) lds_barrier();
 #pragma unroll
-    for (int r = 0; r < NTM; ++r) {
-      if (r < ntile) {
+      for (int r = 0; r < NT; ++r) {
         const float sc = __builtin_amdgcn_ldexpf(1.f, -e[r]);  // exact power of two
 #pragma unroll
         for (int q = 0; q < MT; ++q) {
@@ -293,19 +278,31 @@ __device__ __forceinline__ void pass_body_wide(const PassArgs& a, int bx, int ty
         }
         if (wv == 0 && g == 0) exn[16 * r + m] = eold[r] + e[r] + cexp;
       }
-    }
-    if (oin >= 0) {  // lanes of column oin % 16 hold the odd row's outputs
-      if (m == (oin & 15)) {
-        const float sc = __builtin_amdgcn_ldexpf(1.f, -oe);
+      if (oin >= 0) {  // lanes of column oin % 16 hold the odd row's outputs
+        if (m == (oin & 15)) {
+          const float sc = __builtin_amdgcn_ldexpf(1.f, -oe);
 #pragma unroll
-        for (int q = 0; q < MT; ++q) {
-          f4 v = oacc[q];
+          for (int q = 0; q < MT; ++q) {
+            f4 v = oacc[q];
+            if (rn) {
 #pragma unroll
-          for (int i = 0; i < 4; ++i) v[i] *= sc;
-          A::store4(nxt + oout * RS, 16 * (wv * MT + q) + 4 * g, v);
+              for (int i = 0; i < 4; ++i) v[i] *= sc;
+            }
+            A::store4(nxt + oout * RS, 16 * (wv * MT + q) + 4 * g, v);
+          }
         }
+        if (wv == 0 && lane == (oin & 15)) exn[oout] = eoin + oe + cexp;
       }
-      if (wv == 0 && lane == (oin & 15)) exn[oout] = eoin + oe + cexp;
+    };
+    switch (ntile) {
+#define PASS_W_CASE(x)                                                  \
+  case x:                                                              \
+    if constexpr (x <= NTM) step(std::integral_constant<int, x>{});     \
+    break;
+      PASS_W_CASE(1) PASS_W_CASE(2) PASS_W_CASE(3) PASS_W_CASE(4) PASS_W_CASE(5)
+      PASS_W_CASE(6) PASS_W_CASE(7) PASS_W_CASE(8) PASS_W_CASE(9)
+#undef PASS_W_CASE
+      default: break;  // the host keeps every group within NTM tiles
     }
     lds_barrier();
     if (!INPL) {
