@@ -67,8 +67,9 @@ struct PassArgs {
 
 // ----------------------------------------------------------------------------
 // Bond-256 FP8 pass with the K loop outermost.  One walker per block; wave
-// wv owns output features [64 wv, 64 wv + 64), four 16-feature tiles.  For
-// each 32-wide K chunk a lane's 8 codes of every tile are decoded once, and
+// wv owns output features [64 wv, 64 wv + 64), four 16-feature tiles (MT =
+// chi / 64 in general).  For each 32-wide K chunk a lane's 8 codes of every
+// tile are decoded once, and
 // each active row tile's activations for that chunk are read from LDS once
 // and multiplied into the four tiles' accumulators, which stay live for the
 // whole step.  Every accumulator sees the matrix-op sequence of pass_body
@@ -96,15 +97,31 @@ struct PassArgs {
 constexpr int kPassWideTiles = PASS_W_NTM;        // row tiles a step may hold
 constexpr bool kPassWideInPlace = PASS_W_INPL != 0;
 
+// PASS_W_128 1 also runs FP8 and BF16 at bond 128 in this form: bit-identical
+// there, but it needs one wave per SIMD where pass_body fits two, and the
+// 10x10 bond-128 BF16 local energies went from 18.3 to 30.2 ms.  BF16 at
+// bond 256 spills in this form.
+#ifndef PASS_W_128
+#define PASS_W_128 0
+#endif
 template <class D, int CHI>
-constexpr bool pass_wide_form() { return PASS_W_ENABLE && std::is_same<D, DFP8>::value && CHI == 256; }
+constexpr bool pass_wide_form() {
+  return PASS_W_ENABLE && ((std::is_same<D, DFP8>::value && (CHI == 256 || (PASS_W_128 && CHI == 128))) ||
+                           (std::is_same<D, DBF16>::value && PASS_W_128 && CHI == 128));
+}
 
+template <class D, int CHI>
 __device__ __forceinline__ void pass_body_wide(const PassArgs& a, int bx, int ty) {
-  constexpr int CHI = 256, KPL = 64, MT = 4, RS = CHI + 4, NTM = kPassWideTiles;
+  constexpr bool F8 = std::is_same<D, DFP8>::value;
+  constexpr int KPL = CHI / 4, MT = CHI / 64, RS = CHI + 4, NTM = kPassWideTiles;
+  constexpr int NCH = KPL / 8;     // 32-wide K chunks per step
+  constexpr int CPW = F8 ? 2 : 1;  // K chunks per 16-byte fragment word (FP8: 16 codes)
+  constexpr int NWD = NCH / CPW;   // fragment words per lane and tile
   static_assert(NTM >= 1 && NTM <= 9, "the step dispatch covers 1 to 9 row tiles");
   constexpr bool INPL = kPassWideInPlace;
   constexpr int NB = INPL ? 1 : 2;  // row buffers
-  using A = Act<DFP8, CHI>;
+  using A = Act<D, CHI>;
+  using E = typename D::elem;
   extern __shared__ __align__(16) float lds[];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int g = lane >> 4, m = lane & 15;
@@ -124,23 +141,23 @@ __device__ __forceinline__ void pass_body_wide(const PassArgs& a, int bx, int ty
   __syncthreads();
 
   const int term = ty / a.ng, grp = ty % a.ng;
-  const uint8_t* cores = static_cast<const uint8_t*>(a.cores) + (size_t)term * a.L * 2 * CHI * CHI;
+  const E* cores = static_cast<const E*>(a.cores) + (size_t)term * a.L * 2 * CHI * CHI;
   const int* cexp_p = a.core_exp ? a.core_exp + (size_t)term * a.L : nullptr;
   const int2 gs = a.gsteps[grp];
   const int4* sched = a.sched + gs.x;
   const int n = gs.y;
 
-  // Ring of fragment codes: a slot holds one 16-byte chunk j (codes 16j ..
-  // 16j + 15 of each lane) of this wave's four tiles, of the walker's slice
-  // (Rm) and, on steps with an odd row, of the other slice (Ro).  A step
-  // streams its chunks 0..3 through the RING slots; a slot is refilled with
-  // the chunk RING places further on (in this step or the next) as soon as
-  // both of its K chunks are decoded, so every load has RING / 4 of a step
-  // to arrive.
-  constexpr int RING = PASS_W_RING;
+  // Ring of fragment words: a slot holds one 16-byte word j of each lane's
+  // fragment (elements 16j .. 16j + 15 for FP8 codes, 8j .. 8j + 7 for BF16)
+  // of this wave's MT tiles, of the walker's slice (Rm) and, on steps with an
+  // odd row, of the other slice (Ro).  A step streams its NWD words through
+  // the RING slots; a slot is refilled with the word RING places further on
+  // (in this step or the next) as soon as its K chunks are decoded, so every
+  // load has RING / NWD of a step to arrive.
+  constexpr int RING = PASS_W_RING < NWD ? PASS_W_RING : NWD;
   uint4 Rm[RING][MT], Ro[RING][MT];
-  constexpr int TILE16 = 64 * KPL / 16;  // 16-byte words per fragment tile
-  // load chunk j of a step's fragments into ring slot j % RING
+  constexpr int TILE16 = 64 * KPL * (int)sizeof(E) / 16;  // 16-byte words per fragment tile
+  // load word j of a step's fragments into ring slot j % RING
   auto issue = [&](int j, const int4& st, int bit) {
     const int sl = j % RING;
     const uint4* bm = reinterpret_cast<const uint4*>(cores + ((size_t)st.x * 2 + bit) * (CHI * CHI)) +
@@ -154,14 +171,19 @@ __device__ __forceinline__ void pass_body_wide(const PassArgs& a, int bx, int ty
       for (int q = 0; q < MT; ++q) Ro[sl][q] = bo[q * TILE16 + 64 * j + lane];
     }
   };
-  // codes 8c .. 8c + 7 of a lane (half h = c & 1 of its chunk) as BF16 values
+  // the A operand of K chunk c from its fragment word: FP8 codes 8c .. 8c + 7
+  // (half h = c % 2 of the word) decoded to BF16, or the word's 8 BF16 values
   auto dec = [](const uint4& v, int h) -> bf16x8 {
-    const uint32_t w0 = h ? v.z : v.x, w1 = h ? v.w : v.y;
-    const auto p0 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(w0, kFp8Scale, false);
-    const auto p1 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(w0, kFp8Scale, true);
-    const auto p2 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(w1, kFp8Scale, false);
-    const auto p3 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(w1, kFp8Scale, true);
-    return bf16x8{p0[0], p0[1], p1[0], p1[1], p2[0], p2[1], p3[0], p3[1]};
+    if constexpr (F8) {
+      const uint32_t w0 = h ? v.z : v.x, w1 = h ? v.w : v.y;
+      const auto p0 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(w0, kFp8Scale, false);
+      const auto p1 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(w0, kFp8Scale, true);
+      const auto p2 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(w1, kFp8Scale, false);
+      const auto p3 = __builtin_amdgcn_cvt_scalef32_pk_bf16_fp8(w1, kFp8Scale, true);
+      return bf16x8{p0[0], p0[1], p1[0], p1[1], p2[0], p2[1], p3[0], p3[1]};
+    } else {
+      return __builtin_bit_cast(bf16x8, v);
+    }
   };
 
   if (n > 0) {
@@ -197,8 +219,8 @@ __device__ __forceinline__ void pass_body_wide(const PassArgs& a, int bx, int ty
 #pragma unroll
       for (int q = 0; q < MT; ++q) oacc[q] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int c = 0; c < KPL / 8; ++c) {
-        const int j = c >> 1, h = c & 1, sl = j % RING;
+      for (int c = 0; c < NCH; ++c) {
+        const int j = c / CPW, h = c % CPW, sl = j % RING;
         bf16x8 Am[MT];
 #pragma unroll
         for (int q = 0; q < MT; ++q) Am[q] = dec(Rm[sl][q], h);
@@ -217,10 +239,10 @@ __device__ __forceinline__ void pass_body_wide(const PassArgs& a, int bx, int ty
             oacc[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ao[q], bl, oacc[q], 0, 0, 0);
           }
         }
-        // the slot is free: refill it with the chunk RING places further on
-        if (h == 1) {
-          if (j + RING < 4) issue(j + RING, st, bitc);
-          else issue(j + RING - 4, stn, bitn);
+        // the slot is free: refill it with the word RING places further on
+        if (h == CPW - 1) {
+          if (j + RING < NWD) issue(j + RING, st, bitc);
+          else issue(j + RING - NWD, stn, bitn);
         }
 #pragma unroll
         for (int r = 0; r < NT; ++r) {
@@ -323,7 +345,7 @@ __device__ __forceinline__ void pass_body_wide(const PassArgs& a, int bx, int ty
 template <class D, int CHI>
 __device__ __forceinline__ void pass_body(const PassArgs& a, int bx, int ty) {
   if constexpr (pass_wide_form<D, CHI>()) {
-    pass_body_wide(a, bx, ty);
+    pass_body_wide<D, CHI>(a, bx, ty);
     return;
   }
   using E = typename D::elem;

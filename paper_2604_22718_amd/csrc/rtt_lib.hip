@@ -179,9 +179,12 @@ Sched build_sched(const std::vector<int>& pi, int N, int L, int c, int ng) {
 
 int rttk_wpw(int chi) { return chi >= 64 ? 4 : chi / 16; }
 
-// the bond-256 FP8 pass runs the K-outer form (rows in place when so built,
-// and at most kPassWideTiles row tiles per walker)
-bool pass_wide(int dtype, int chi) { return PASS_W_ENABLE && dtype == RTT_FP8_E4M3 && chi == 256; }
+// the passes of rttk::pass_wide_form run the K-outer form (rows in place
+// when so built, and at most kPassWideTiles row tiles per walker)
+bool pass_wide(int dtype, int chi) {
+  return PASS_W_ENABLE && ((dtype == RTT_FP8_E4M3 && (chi == 256 || (PASS_W_128 && chi == 128))) ||
+                           (dtype == RTT_BF16 && PASS_W_128 && chi == 128));
+}
 int pass_max_slots(int dtype, int chi) { return pass_wide(dtype, chi) ? 16 * rttk::kPassWideTiles : 1 << 30; }
 
 size_t pass_lds_bytes(int chi, int nslot, int nw, int dtype) {
@@ -510,7 +513,10 @@ template <class D, int CHI>
 rtt_status launch_pass(const rttk::PassArgs& a, int T, hipStream_t s) {
   constexpr int WPW = rttk::Geo<CHI>::WPW;
   constexpr int WPB = 4 / WPW;
-  const size_t lds = pass_lds_bytes(CHI, a.nslot, a.nw, rttk::pass_wide_form<D, CHI>() ? RTT_FP8_E4M3 : -1);
+  const size_t lds = pass_lds_bytes(CHI, a.nslot, a.nw,
+                                    std::is_same<D, rttk::DFP8>::value    ? RTT_FP8_E4M3
+                                    : std::is_same<D, rttk::DBF16>::value ? RTT_BF16
+                                                                          : RTT_F32);
   auto kfn = rttk::pass_kernel<D, CHI>;
   HIPX(hipFuncSetAttribute((const void*)kfn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   dim3 grid((a.W + WPB - 1) / WPB, T);
