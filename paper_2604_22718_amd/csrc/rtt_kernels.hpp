@@ -81,7 +81,9 @@ struct PassArgs {
 // the double-buffered item form 2.75 s; K outermost, two buffers 2.59 s; in
 // place with 6 row tiles 2.22 s; with 9 (two row groups instead of three)
 // and the two-slot ring below 2.06 s; with each step compiled for its exact
-// row-tile count (no per-tile branches) 1.61 s.  A four-slot ring spills.
+// row-tile count (no per-tile branches) 1.61 s, and for whether it
+// renormalises (no scaling on the other steps) 1.55 s.  A four-slot ring
+// spills.
 #ifndef PASS_W_NTM  // row tiles a group may hold
 #define PASS_W_NTM 9
 #endif
@@ -208,8 +210,9 @@ __device__ __forceinline__ void pass_body_wide(const PassArgs& a, int bx, int ty
     // tile count): no branch per tile, so the compiler is free to issue a
     // chunk's reads ahead of the matrix ops, and no accumulator of an idle
     // tile is carried through the K loop.
-    auto step = [&](auto ntc) {
+    auto step = [&](auto ntc, auto rnc) {
       constexpr int NT = decltype(ntc)::value;
+      constexpr bool RN = decltype(rnc)::value;  // a renormalisation step
       f4 acc[NT][MT], oacc[MT];
 #pragma unroll
       for (int r = 0; r < NT; ++r) {
@@ -265,13 +268,13 @@ __device__ __forceinline__ void pass_body_wide(const PassArgs& a, int bx, int ty
 #pragma unroll
       for (int r = 0; r < NT; ++r) {
         e[r] = 0;
-        if (rn) {
+        if constexpr (RN) {
           DBF16::BOp<KPL> bo;
           A::template load_b<KPL>(cur + (16 * r + m) * RS, g, bo);
           e[r] = A::template row_exp<KPL>(bo);
         }
       }
-      if (rn && ot >= 0) {  // the exponent of the odd row's input row
+      if (RN && ot >= 0) {  // the exponent of the odd row's input row
         DBF16::BOp<KPL> bo;
         A::template load_b<KPL>(orow, g, bo);
         oe = A::template row_exp<KPL>(bo);
@@ -292,7 +295,7 @@ __device__ __forceinline__ void pass_body_wide(const PassArgs& a, int bx, int ty
 #pragma unroll
         for (int q = 0; q < MT; ++q) {
           f4 v = acc[r][q];
-          if (rn) {  // the scale is 1 on other steps
+          if constexpr (RN) {  // the scale is 1 on other steps
 #pragma unroll
             for (int i = 0; i < 4; ++i) v[i] *= sc;
           }
@@ -306,7 +309,7 @@ __device__ __forceinline__ void pass_body_wide(const PassArgs& a, int bx, int ty
 #pragma unroll
           for (int q = 0; q < MT; ++q) {
             f4 v = oacc[q];
-            if (rn) {
+            if constexpr (RN) {
 #pragma unroll
               for (int i = 0; i < 4; ++i) v[i] *= sc;
             }
@@ -316,16 +319,22 @@ __device__ __forceinline__ void pass_body_wide(const PassArgs& a, int bx, int ty
         if (wv == 0 && lane == (oin & 15)) exn[oout] = eoin + oe + cexp;
       }
     };
-    switch (ntile) {
-#define PASS_W_CASE(x)                                                  \
-  case x:                                                              \
-    if constexpr (x <= NTM) step(std::integral_constant<int, x>{});     \
+    // dispatched on the tile count and, as a second template parameter, on
+    // whether the step renormalises (the other steps then carry no scaling)
+    auto dispatch = [&](auto rnc) {
+      switch (ntile) {
+#define PASS_W_CASE(x)                                                     \
+  case x:                                                                 \
+    if constexpr (x <= NTM) step(std::integral_constant<int, x>{}, rnc);   \
     break;
-      PASS_W_CASE(1) PASS_W_CASE(2) PASS_W_CASE(3) PASS_W_CASE(4) PASS_W_CASE(5)
-      PASS_W_CASE(6) PASS_W_CASE(7) PASS_W_CASE(8) PASS_W_CASE(9)
+        PASS_W_CASE(1) PASS_W_CASE(2) PASS_W_CASE(3) PASS_W_CASE(4) PASS_W_CASE(5)
+        PASS_W_CASE(6) PASS_W_CASE(7) PASS_W_CASE(8) PASS_W_CASE(9)
 #undef PASS_W_CASE
-      default: break;  // the host keeps every group within NTM tiles
-    }
+        default: break;  // the host keeps every group within NTM tiles
+      }
+    };
+    if (rn) dispatch(std::true_type{});
+    else dispatch(std::false_type{});
     lds_barrier();
     if (!INPL) {
       float* tp = cur; cur = nxt; nxt = tp;
