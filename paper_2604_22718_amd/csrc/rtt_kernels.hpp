@@ -99,18 +99,25 @@ struct PassArgs {
 constexpr int kPassWideTiles = PASS_W_NTM;        // row tiles a step may hold
 constexpr bool kPassWideInPlace = PASS_W_INPL != 0;
 
-// PASS_W_128 1 also runs FP8 and BF16 at bond 128 in this form: bit-identical
-// there, but it needs one wave per SIMD where pass_body fits two, and the
-// 10x10 bond-128 BF16 local energies went from 18.3 to 30.2 ms.  BF16 at
-// bond 256 spills in this form.
+// PASS_W_128 also runs FP8 and BF16 at bond 128 in this form (bit-identical
+// there), compiled for two waves per SIMD (pass_min_blocks): 10x10 bond-128
+// BF16 local energies 18.7 -> 16.7 ms against the item form; left free to
+// use one wave per SIMD it was slower (30.2 ms).  BF16 at bond 256 spills
+// in this form.
 #ifndef PASS_W_128
-#define PASS_W_128 0
+#define PASS_W_128 1
 #endif
 template <class D, int CHI>
 constexpr bool pass_wide_form() {
   return PASS_W_ENABLE && ((std::is_same<D, DFP8>::value && (CHI == 256 || (PASS_W_128 && CHI == 128))) ||
                            (std::is_same<D, DBF16>::value && PASS_W_128 && CHI == 128));
 }
+
+// blocks per CU the pass kernels are compiled for (a register budget): two
+// for the bond-128 K-outer form, whose registers would otherwise grow past
+// what two waves per SIMD allow
+template <class D, int CHI>
+constexpr int pass_min_blocks() { return (pass_wide_form<D, CHI>() && CHI == 128) ? 2 : 1; }
 
 template <class D, int CHI>
 __device__ __forceinline__ void pass_body_wide(const PassArgs& a, int bx, int ty) {
@@ -560,7 +567,7 @@ __device__ __forceinline__ void pass_body(const PassArgs& a, int bx, int ty) {
 }
 
 template <class D, int CHI>
-__global__ void __launch_bounds__(256) pass_kernel(PassArgs a) {
+__global__ void __launch_bounds__(256, (pass_min_blocks<D, CHI>())) pass_kernel(PassArgs a) {
   pass_body<D, CHI>(a, blockIdx.x, blockIdx.y);  // y = term * ng + group
 }
 
@@ -1454,7 +1461,7 @@ __device__ __forceinline__ int next_item(int* counter, int* s_item) {
 }
 
 template <class D, int CHI>
-__global__ void __launch_bounds__(256) pass_persistent(const PassArgs* descs, const int4* items,
+__global__ void __launch_bounds__(256, (pass_min_blocks<D, CHI>())) pass_persistent(const PassArgs* descs, const int4* items,
                                                        int n_items, int* counter) {
   __shared__ int s_item;
   for (;;) {
