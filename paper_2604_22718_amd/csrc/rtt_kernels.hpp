@@ -66,14 +66,15 @@ struct PassArgs {
 };
 
 // ----------------------------------------------------------------------------
-// Bond-256 FP8 pass with the K loop outermost.  One walker per block; wave
-// wv owns output features [64 wv, 64 wv + 64), four 16-feature tiles (MT =
-// chi / 64 in general).  For each 32-wide K chunk a lane's 8 codes of every
-// tile are decoded once, and
-// each active row tile's activations for that chunk are read from LDS once
-// and multiplied into the four tiles' accumulators, which stay live for the
-// whole step.  Every accumulator sees the matrix-op sequence of pass_body
-// (chunk by chunk, hi part then lo part), so the results are the same bits.
+// Flip-ratio pass with the K loop outermost (FP8 cores at bond 256, BF16 and
+// FP8 cores at bond 128).  One walker per block; wave wv owns output
+// features [wv chi / 4, (wv + 1) chi / 4), MT = chi / 64 tiles of 16.  For
+// each 32-wide K chunk a lane's 8 core values of every tile are taken from
+// its fragment word once (FP8 codes decoded to BF16), each active row tile's
+// activations for that chunk are read from LDS once and multiplied into the
+// MT tiles' accumulators, which stay live for the whole step.  Every
+// accumulator sees the matrix-op sequence of pass_body (chunk by chunk, hi
+// part then lo part), so the results are the same bits.
 // With PASS_W_INPL rows are updated in place: the step's outputs wait in
 // registers until every wave has read its inputs, so a walker's rows take
 // half the LDS and twice as many fit (fewer row groups, fewer core reads).
@@ -90,7 +91,7 @@ struct PassArgs {
 #ifndef PASS_W_INPL
 #define PASS_W_INPL 1
 #endif
-#ifndef PASS_W_ENABLE  // 0: the bond-256 FP8 pass runs pass_body's item form
+#ifndef PASS_W_ENABLE  // 0: every pass runs pass_body's item form
 #define PASS_W_ENABLE 1
 #endif
 #ifndef PASS_W_RING  // fragment ring slots: 4 = one step ahead, 2 = half a step
