@@ -42,15 +42,18 @@ def test_row_groups_match_oracle(R):
     assert np.all(out["sign"] == sg) and np.max(np.abs(out["logabs"] - la)) < 2e-2
 
 
-@pytest.mark.parametrize("N,W,seed", [(16, 8, 70), (100, 4, 60), (160, 1, 64)])
-def test_fp8_bond256_row_tiles_match_oracle(R, N, W, seed):
-    """FP8 at bond 256 (the K-outer pass with rows updated in place): a
-    second row tile that first appears on the last two steps (N = 16), row
-    groups (N = 100), and six row tiles per group, more rows than two
-    buffers would hold (N = 160)."""
-    print(f"[case] fp8 bond 256 N={N} W={W}", flush=True)
-    pi, bond, cores = case(N, 2, 256, "perm", seed=seed)
-    psi = R.RTT.create(N, pi, cores, "fp8")
+@pytest.mark.parametrize("N,W,seed,chi,dtype", [(16, 8, 70, 256, "fp8"), (100, 4, 60, 256, "fp8"),
+                                                (160, 1, 64, 256, "fp8"), (101, 4, 61, 128, "bf16"),
+                                                (102, 4, 62, 128, "fp8")])
+def test_k_outer_pass_row_tiles_match_oracle(R, N, W, seed, chi, dtype):
+    """The K-outer flip-ratio pass with rows updated in place (FP8 at bond
+    256, BF16 and FP8 at bond 128): a second row tile that first appears on
+    the last two steps (N = 16), row groups (N = 100), six row tiles per
+    group, more rows than two buffers would hold (N = 160), and bond 128
+    with up to seven row tiles in one group."""
+    print(f"[case] {dtype} bond {chi} N={N} W={W}", flush=True)
+    pi, bond, cores = case(N, 2, chi, "perm", seed=seed)
+    psi = R.RTT.create(N, pi, cores, dtype)
     qc = device_cores(psi, bond)
     bits = wl.random_spins(W, N, seed + 1)
     out = psi.evaluate(R.spins_to_device(wl.pack_spins(bits)))
